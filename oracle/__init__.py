@@ -1,0 +1,127 @@
+"""ORACLE -- test infrastructure only.
+
+Only the tests, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  It is a plain CPU definition of the evolving-graph
+query (per-snapshot Dijkstra / BFS on each materialised snapshot, Section 2 and
+Section 3 Step 1 of the paper) and shares no code with the HIP library.
+
+Functions:
+  replay(inst)        distinct triples + per-snapshot presence bits
+  solve(V, edges, a, s)          values on one explicit edge list
+  query(V, trip, bits, a, s, snaps)   values[v, j] for snapshot snaps[j]
+  bounds(V, trip, bits, a, s, b, L)   (R_cap, R_cup) of the window [b, b+L)
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+SSSP, BFS, SSWP, SSNP = 0, 1, 2, 3
+ALGOS = {"sssp": SSSP, "bfs": BFS, "sswp": SSWP, "ssnp": SSNP}
+INF = 0xFFFFFFFF
+SAT = 0xFFFFFFFE
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_replay.restype = ctypes.c_int64
+        lib.oracle_replay.argtypes = [ctypes.c_uint32, P, ctypes.c_uint64, P, P, P, P, P, P, ctypes.c_uint64]
+        lib.oracle_solve.restype = ctypes.c_int
+        lib.oracle_solve.argtypes = [ctypes.c_uint32, ctypes.c_uint64, P, ctypes.c_int, ctypes.c_uint32, P]
+        lib.oracle_query.restype = ctypes.c_int
+        lib.oracle_query.argtypes = [ctypes.c_uint32, ctypes.c_uint64, P, P, ctypes.c_int, ctypes.c_uint32,
+                                     P, ctypes.c_uint32, P, ctypes.c_int]
+        lib.oracle_bounds.restype = ctypes.c_int
+        lib.oracle_bounds.argtypes = [ctypes.c_uint32, ctypes.c_uint64, P, P, ctypes.c_int, ctypes.c_uint32,
+                                      ctypes.c_uint32, ctypes.c_uint32, P, P]
+        _lib = lib
+    return _lib
+
+
+def _tri(a) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32).reshape(-1, 3))
+    return a
+
+
+def replay(inst):
+    """(trip (n,3) uint32, bits (n,2) uint64): every distinct triple ever present;
+    bit t of the 128-bit mask (word t // 64) set iff the triple is in snapshot t."""
+    lib = _load()
+    K = len(inst.dels)
+    base = _tri(inst.base)
+    dels = _tri(np.concatenate([_tri(d) for d in inst.dels]) if K else np.zeros((0, 3)))
+    adds = _tri(np.concatenate([_tri(a) for a in inst.adds]) if K else np.zeros((0, 3)))
+    doff = np.zeros(K + 1, dtype=np.uint64)
+    aoff = np.zeros(K + 1, dtype=np.uint64)
+    doff[1:] = np.cumsum([len(d) for d in inst.dels]) if K else []
+    aoff[1:] = np.cumsum([len(a) for a in inst.adds]) if K else []
+    cap = len(base) + len(adds) + 1
+    trip = np.empty((cap, 3), dtype=np.uint32)
+    bits = np.empty((cap, 2), dtype=np.uint64)
+    n = lib.oracle_replay(K, base.ctypes.data, len(base), dels.ctypes.data, doff.ctypes.data,
+                          adds.ctypes.data, aoff.ctypes.data, trip.ctypes.data, bits.ctypes.data, cap)
+    if n < 0:
+        raise ValueError("oracle_replay failed")
+    return trip[:n].copy(), bits[:n].copy()
+
+
+def solve(V: int, edges, algo: int, source: int) -> np.ndarray:
+    lib = _load()
+    e = _tri(edges)
+    out = np.empty(max(V, 1), dtype=np.uint32)
+    rc = lib.oracle_solve(V, len(e), e.ctypes.data, algo, source, out.ctypes.data)
+    if rc:
+        raise ValueError("oracle_solve failed")
+    return out[:V]
+
+
+def query(V: int, trip, bits, algo: int, source: int, snaps, nthreads: int = 0) -> np.ndarray:
+    lib = _load()
+    t = _tri(trip)
+    b = np.ascontiguousarray(bits, dtype=np.uint64)
+    s = np.ascontiguousarray(snaps, dtype=np.uint32)
+    out = np.empty((V, len(s)), dtype=np.uint32)
+    rc = lib.oracle_query(V, len(t), t.ctypes.data, b.ctypes.data, algo, source, s.ctypes.data, len(s),
+                          out.ctypes.data, nthreads)
+    if rc:
+        raise ValueError("oracle_query failed")
+    return out
+
+
+def bounds(V: int, trip, bits, algo: int, source: int, b: int, L: int):
+    lib = _load()
+    t = _tri(trip)
+    bb = np.ascontiguousarray(bits, dtype=np.uint64)
+    rcap = np.empty(V, dtype=np.uint32)
+    rcup = np.empty(V, dtype=np.uint32)
+    rc = lib.oracle_bounds(V, len(t), t.ctypes.data, bb.ctypes.data, algo, source, b, L,
+                           rcap.ctypes.data, rcup.ctypes.data)
+    if rc:
+        raise ValueError("oracle_bounds failed")
+    return rcap, rcup
+
+
+def window_values(inst, algo: int, source: int, b: int, L: int, snaps=None, replayed=None, nthreads: int = 0):
+    """values[v, i] for snapshot b + i of the window (or for the listed snapshots)."""
+    trip, bits = replayed if replayed is not None else replay(inst)
+    s = list(range(b, b + L)) if snaps is None else list(snaps)
+    return query(inst.num_vertices, trip, bits, algo, source, s, nthreads)
