@@ -1,0 +1,199 @@
+/*
+ * evq -- evolving-graph snapshot queries by intersection-union analysis on
+ * MI355X (gfx950).
+ *
+ * A window of graph snapshots is answered in four steps (paper Section 3,
+ * Algorithm 1, and Section 4, Algorithm 2):
+ *   1. solve the query on the window's intersection graph and union graph
+ *      (Step 1, Theorem 1; the union solve starts from the intersection
+ *      result and adds the missing edges, Section 6.2);
+ *   2. vertices whose two bounds agree keep that value in every snapshot
+ *      (Step 2, Theorem 2);
+ *   3. the remaining vertices and the edges that can still change them form
+ *      the reduced subgraph (Step 3; built "in reverse" from the mismatching
+ *      vertices, Section 6.2);
+ *   4. every snapshot of the window is relaxed concurrently over that
+ *      subgraph, with a per-edge snapshot mask and one snapshot-oblivious
+ *      frontier (Section 4.1, 4.2, Algorithm 2).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an evq_status; nothing throws or aborts across the
+ *     ABI.  On failure evq_last_error() describes the cause.
+ *   - Arguments are validated before any device work.  A failing call leaves
+ *     no partial object behind.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is ordered on that stream.
+ *   - Host pointers are read during the call only; the caller keeps
+ *     ownership.  Device pointers belong to the caller unless stated.
+ *   - Edge weights are uint32 >= 1; vertex ids are uint32 < num_vertices.
+ *
+ * Query values (Table 2 edge functions; sentinels are this library's reading
+ * where the paper is silent):
+ *   SSSP  min over paths of the weight sum, saturating at 0xFFFFFFFE;
+ *         source 0; unreachable 0xFFFFFFFF
+ *   BFS   min over paths of the edge count; source 0; unreachable 0xFFFFFFFF
+ *   SSWP  max over paths of the minimum weight; source 0xFFFFFFFF;
+ *         unreachable 0
+ *   SSNP  min over paths of the maximum weight; source 0; unreachable
+ *         0xFFFFFFFF
+ */
+#ifndef EVQ_H
+#define EVQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t evq_status;
+#define EVQ_OK 0
+#define EVQ_EINVAL (-1)    /* malformed argument: NULL pointer, id >= V, w == 0, K out of range */
+#define EVQ_ERANGE (-2)    /* window / source / size out of the supported range */
+#define EVQ_ENOMEM (-3)    /* device or host allocation failed */
+#define EVQ_EDEVICE (-4)   /* a HIP runtime call failed */
+#define EVQ_ENOCONV (-5)   /* a frontier loop exceeded its iteration cap */
+
+#define EVQ_SSSP 0
+#define EVQ_BFS 1
+#define EVQ_SSWP 2
+#define EVQ_SSNP 3
+
+#define EVQ_MAX_SNAPSHOTS 128
+
+/* One directed weighted edge, 12 bytes, host memory. */
+typedef struct {
+    uint32_t src, dst, w;
+} evq_edge;
+
+/* One update batch (Section 2.1): its deletions are applied before its additions. */
+typedef struct {
+    const evq_edge* del;
+    uint64_t n_del;
+    const evq_edge* add;
+    uint64_t n_add;
+} evq_batch;
+
+/* Opaque handle; owns the device copy of the versioned graph. */
+typedef struct evq_graph evq_graph;
+
+typedef struct {
+    uint32_t num_vertices;
+    uint32_t num_snapshots;  /* K */
+    uint32_t mask_words;     /* 64-bit words per edge presence mask: 1 (K <= 64) or 2 */
+    uint32_t reserved;
+    uint64_t num_edges;      /* distinct (src, dst, w) triples present in >= 1 snapshot */
+    uint64_t num_partial;    /* of those, triples absent from >= 1 snapshot */
+    uint64_t device_bytes;   /* device memory held by the handle */
+    double build_ms;         /* wall time of evq_build, host validation included */
+} evq_graph_info;
+
+/* Filled by evq_query when a non-NULL pointer is passed (the call then synchronises). */
+typedef struct {
+    double ms_total, ms_cap, ms_cup, ms_compact, ms_relax, ms_writeback;
+    uint64_t n_unstable;        /* vertices whose intersection and union bounds differ */
+    uint64_t n_seed_edges;      /* window-partial edges into unstable vertices (the reduced batches) */
+    uint64_t n_relax_edges;     /* reduced-subgraph edges between unstable vertices */
+    uint64_t iters_cap, iters_cup, iters_relax;
+    uint64_t edges_cap, edges_cup;        /* edge visits of the two bound solves */
+    uint64_t edge_visits_relax;           /* edge visits of the multi-snapshot relaxation */
+    uint64_t lane_relaxations;            /* (edge visit, snapshot) pairs evaluated there */
+} evq_query_stats;
+
+/*
+ * Build the versioned graph (Section 4.1) of K snapshots.
+ * Snapshot -1 is the set of distinct triples in `base`; snapshot i
+ * (0 <= i < K) is snapshot i-1 with batches[i].del removed and then
+ * batches[i].add inserted.  A snapshot is a set of (src, dst, w) triples:
+ * exact duplicates collapse, parallel edges with different weights stay.
+ * The result is one CSR over every triple present in at least one snapshot,
+ * each edge carrying a K-bit mask, bit i = present in snapshot i; per row
+ * the edges present in all K snapshots come first.
+ *   num_vertices >= 1; 1 <= K <= 128; base may be NULL when n_base == 0,
+ *   likewise del/add when their counts are 0.
+ * Errors: EVQ_EINVAL (NULL out/batches, id >= num_vertices, w == 0, K out of
+ * range), EVQ_ERANGE (more than 2^32 - 2 events or union edges),
+ * EVQ_ENOMEM, EVQ_EDEVICE.  On success *out owns its device memory until
+ * evq_free.  The call synchronises `stream`.
+ */
+evq_status evq_build(uint32_t num_vertices, const evq_edge* base, uint64_t n_base,
+                     const evq_batch* batches, uint32_t K, void* stream, evq_graph** out);
+
+/* Sizes of a built graph.  EVQ_EINVAL on NULL arguments. */
+evq_status evq_graph_info_get(const evq_graph* g, evq_graph_info* info);
+
+/*
+ * Copy the versioned graph to host buffers (inspection and tests).
+ *   row_ptr: V + 1 entries; row_split: V entries (end of the all-present
+ *   prefix of each row); col, w: num_edges entries; mask: num_edges *
+ *   mask_words 64-bit words, word j of edge e at mask[e * mask_words + j].
+ * Any pointer may be NULL to skip that array.  Synchronises `stream`.
+ */
+evq_status evq_graph_export(const evq_graph* g, uint32_t* row_ptr, uint32_t* row_split, uint32_t* col,
+                            uint32_t* w, uint64_t* mask, void* stream);
+
+/*
+ * Answer a query over the window [win_begin, win_begin + win_len) of
+ * snapshots (Algorithm 1 followed by Algorithm 2).
+ *   algo: EVQ_SSSP / EVQ_BFS / EVQ_SSWP / EVQ_SSNP; source < V.
+ *   1 <= win_len and win_begin + win_len <= K.
+ *   d_values: caller-owned DEVICE buffer of V * win_len uint32,
+ *             d_values[v * win_len + i] = value of v in snapshot win_begin + i.
+ *   stats: NULL, or a host struct filled after the call synchronises.
+ * Errors: EVQ_EINVAL (NULL g/d_values, bad algo), EVQ_ERANGE (source or
+ * window out of range), EVQ_ENOMEM, EVQ_EDEVICE, EVQ_ENOCONV.
+ * The graph is only read, so queries may run concurrently on several streams.
+ * The call returns once the last frontier loop has drained (it reads frontier
+ * sizes back); the values are complete when `stream` reaches that point.
+ */
+evq_status evq_query(const evq_graph* g, uint32_t algo, uint32_t source, uint32_t win_begin,
+                     uint32_t win_len, uint32_t* d_values, evq_query_stats* stats, void* stream);
+
+/*
+ * Only the bounds of Step 1: d_rcap[v] = value on the window's intersection
+ * graph, d_rcup[v] = value on its union graph (device buffers of V uint32,
+ * either may be NULL).  Same arguments and errors as evq_query.
+ */
+evq_status evq_query_bounds(const evq_graph* g, uint32_t algo, uint32_t source, uint32_t win_begin,
+                            uint32_t win_len, uint32_t* d_rcap, uint32_t* d_rcup, void* stream);
+
+/*
+ * Plain concurrent evaluation without the intersection-union analysis: every
+ * snapshot of the window is solved from scratch over the whole versioned
+ * graph with one snapshot-oblivious frontier (the naive full evaluation of
+ * Section 2, run concurrently as in Algorithm 2).  Same arguments, output
+ * layout and errors as evq_query.
+ */
+evq_status evq_query_plain(const evq_graph* g, uint32_t algo, uint32_t source, uint32_t win_begin,
+                           uint32_t win_len, uint32_t* d_values, evq_query_stats* stats, void* stream);
+
+/* Release the handle and its device memory.  NULL is allowed. */
+void evq_free(evq_graph* g);
+
+/* Message of the last failing call on this thread ("" if none); valid until the next call. */
+const char* evq_last_error(void);
+
+/*
+ * Per-kernel timing (measurement only).  While enabled, every kernel the
+ * library launches is bracketed by HIP events on the stream it runs on.
+ * evq_timing_report writes up to `cap` entries: name (NUL-terminated, at most
+ * 47 chars), launch count and total milliseconds; it synchronises the
+ * recorded events and returns the number of distinct kernels (may exceed
+ * cap).  evq_timing_reset discards what was recorded.
+ */
+typedef struct {
+    char name[48];
+    uint64_t launches;
+    double total_ms;
+} evq_kernel_time;
+
+void evq_timing_enable(int on);
+void evq_timing_reset(void);
+int evq_timing_report(evq_kernel_time* out, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EVQ_H */

@@ -1,0 +1,242 @@
+"""Python binding of the evq C ABI (include/evq.h): argument marshalling only.
+
+Every step of a query runs in the HIP library (libevq.so, gfx950).  Device
+buffers are torch tensors (uint32 values held in int32 tensors) and the
+stream is torch's current stream.  Importing this package fails loudly when
+the library has not been built: there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libevq.so")
+
+SSSP, BFS, SSWP, SSNP = 0, 1, 2, 3
+ALGOS = {"sssp": SSSP, "bfs": BFS, "sswp": SSWP, "ssnp": SSNP}
+INF = 0xFFFFFFFF
+
+EVQ_OK, EVQ_EINVAL, EVQ_ERANGE, EVQ_ENOMEM, EVQ_EDEVICE, EVQ_ENOCONV = 0, -1, -2, -3, -4, -5
+_STATUS = {EVQ_EINVAL: "EINVAL", EVQ_ERANGE: "ERANGE", EVQ_ENOMEM: "ENOMEM", EVQ_EDEVICE: "EDEVICE",
+           EVQ_ENOCONV: "ENOCONV"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it first (python paper_2502_10579_amd/_build.py)")
+
+
+class Edge(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_uint32), ("dst", ctypes.c_uint32), ("w", ctypes.c_uint32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("dels", ctypes.POINTER(Edge)), ("n_del", ctypes.c_uint64),
+                ("adds", ctypes.POINTER(Edge)), ("n_add", ctypes.c_uint64)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("num_vertices", ctypes.c_uint32), ("num_snapshots", ctypes.c_uint32),
+                ("mask_words", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("num_edges", ctypes.c_uint64), ("num_partial", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64), ("build_ms", ctypes.c_double)]
+
+
+class QueryStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("ms_total", "ms_cap", "ms_cup", "ms_compact", "ms_relax",
+                                               "ms_writeback")] + \
+               [(n, ctypes.c_uint64) for n in ("n_unstable", "n_seed_edges", "n_relax_edges", "iters_cap",
+                                               "iters_cup", "iters_relax", "edges_cap", "edges_cup",
+                                               "edge_visits_relax", "lane_relaxations")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_lib.evq_build.restype = ctypes.c_int32
+_lib.evq_build.argtypes = [ctypes.c_uint32, ctypes.POINTER(Edge), ctypes.c_uint64, ctypes.POINTER(Batch),
+                           ctypes.c_uint32, _P, ctypes.POINTER(_P)]
+_lib.evq_graph_info_get.restype = ctypes.c_int32
+_lib.evq_graph_info_get.argtypes = [_P, ctypes.POINTER(GraphInfo)]
+_lib.evq_graph_export.restype = ctypes.c_int32
+_lib.evq_graph_export.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+for _name in ("evq_query", "evq_query_plain"):
+    getattr(_lib, _name).restype = ctypes.c_int32
+    getattr(_lib, _name).argtypes = [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _P,
+                                     ctypes.POINTER(QueryStats), _P]
+_lib.evq_query_bounds.restype = ctypes.c_int32
+_lib.evq_query_bounds.argtypes = [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _P, _P,
+                                  _P]
+_lib.evq_free.restype = None
+_lib.evq_free.argtypes = [_P]
+_lib.evq_last_error.restype = ctypes.c_char_p
+_lib.evq_last_error.argtypes = []
+_lib.evq_timing_enable.restype = None
+_lib.evq_timing_enable.argtypes = [ctypes.c_int]
+_lib.evq_timing_reset.restype = None
+_lib.evq_timing_reset.argtypes = []
+_lib.evq_timing_report.restype = ctypes.c_int
+_lib.evq_timing_report.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int]
+
+EXPORTED = ["evq_build", "evq_graph_info_get", "evq_graph_export", "evq_query", "evq_query_bounds",
+            "evq_query_plain", "evq_free", "evq_last_error", "evq_timing_enable", "evq_timing_reset",
+            "evq_timing_report"]
+
+
+class EvqError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(rc):
+    if rc != EVQ_OK:
+        raise EvqError(rc, _lib.evq_last_error().decode(errors="replace"))
+
+
+def last_error() -> str:
+    return _lib.evq_last_error().decode(errors="replace")
+
+
+def _edges(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32).reshape(-1, 3))
+    return a, (a.ctypes.data_as(ctypes.POINTER(Edge)) if len(a) else None)
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    if torch.cuda.is_available():
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(0)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Graph:
+    """Versioned graph of K snapshots resident on the current device (evq_build)."""
+
+    def __init__(self, num_vertices, base, dels, adds, stream=None):
+        if len(dels) != len(adds):
+            raise ValueError("dels and adds must have one entry per batch")
+        keep = []
+        b, bp = _edges(base)
+        keep.append(b)
+        batches = (Batch * max(len(dels), 1))()
+        for i, (d, a) in enumerate(zip(dels, adds)):
+            d, dp = _edges(d)
+            a, ap = _edges(a)
+            keep += [d, a]
+            batches[i] = Batch(dp, len(d), ap, len(a))
+        h = ctypes.c_void_p()
+        _check(_lib.evq_build(num_vertices, bp, len(b), batches, len(dels), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.num_vertices = num_vertices
+        self.K = len(dels)
+
+    @classmethod
+    def from_instance(cls, inst, stream=None):
+        return cls(inst.num_vertices, inst.base, inst.dels, inst.adds, stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.evq_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def info(self) -> dict:
+        gi = GraphInfo()
+        _check(_lib.evq_graph_info_get(self._h, ctypes.byref(gi)))
+        return {k: getattr(gi, k) for k, _ in GraphInfo._fields_ if k != "reserved"}
+
+    def export(self, stream=None) -> dict:
+        """Host copy of the versioned graph: row_ptr, row_split, col, w, mask (E, mask_words)."""
+        inf = self.info
+        V, E, MW = inf["num_vertices"], inf["num_edges"], inf["mask_words"]
+        out = dict(row_ptr=np.empty(V + 1, np.uint32), row_split=np.empty(V, np.uint32),
+                   col=np.empty(max(E, 1), np.uint32), w=np.empty(max(E, 1), np.uint32),
+                   mask=np.empty((max(E, 1), MW), np.uint64))
+        _check(_lib.evq_graph_export(self._h, *(ctypes.c_void_p(out[k].ctypes.data)
+                                               for k in ("row_ptr", "row_split", "col", "w", "mask")),
+                                     _stream(stream)))
+        for k in ("col", "w", "mask"):
+            out[k] = out[k][:E]
+        return out
+
+    def _alloc(self, L, out):
+        import torch
+        if out is None:
+            out = torch.empty((self.num_vertices, L), dtype=torch.int32, device="cuda")
+        if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous() or \
+                out.numel() != self.num_vertices * L:
+            raise ValueError("out must be a contiguous int32 CUDA tensor of V * L elements")
+        return out
+
+    def query(self, algo, source, win_begin=0, win_len=None, out=None, stats=False, stream=None):
+        """values (V, L) int32 tensor holding uint32 values (evq_query)."""
+        algo = ALGOS.get(algo, algo)
+        L = self.K - win_begin if win_len is None else win_len
+        out = self._alloc(L, out)
+        st = QueryStats() if stats else None
+        _check(_lib.evq_query(self._h, algo, source, win_begin, L, _ptr(out),
+                              ctypes.byref(st) if st is not None else None, _stream(stream)))
+        return (out, st.as_dict()) if stats else out
+
+    def query_plain(self, algo, source, win_begin=0, win_len=None, out=None, stats=False, stream=None):
+        """Same output as query(), without the intersection-union analysis (evq_query_plain)."""
+        algo = ALGOS.get(algo, algo)
+        L = self.K - win_begin if win_len is None else win_len
+        out = self._alloc(L, out)
+        st = QueryStats() if stats else None
+        _check(_lib.evq_query_plain(self._h, algo, source, win_begin, L, _ptr(out),
+                                    ctypes.byref(st) if st is not None else None, _stream(stream)))
+        return (out, st.as_dict()) if stats else out
+
+    def query_bounds(self, algo, source, win_begin=0, win_len=None, stream=None):
+        """(R_cap, R_cup) int32 tensors of V values (evq_query_bounds)."""
+        import torch
+        algo = ALGOS.get(algo, algo)
+        L = self.K - win_begin if win_len is None else win_len
+        rcap = torch.empty(self.num_vertices, dtype=torch.int32, device="cuda")
+        rcup = torch.empty(self.num_vertices, dtype=torch.int32, device="cuda")
+        _check(_lib.evq_query_bounds(self._h, algo, source, win_begin, L, _ptr(rcap), _ptr(rcup), _stream(stream)))
+        return rcap, rcup
+
+
+def to_u32(t) -> np.ndarray:
+    """Host uint32 view of an int32 device tensor."""
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def timing_enable(on=True):
+    _lib.evq_timing_enable(1 if on else 0)
+
+
+def timing_reset():
+    _lib.evq_timing_reset()
+
+
+def timing_report() -> dict:
+    n = _lib.evq_timing_report(None, 0)
+    arr = (KernelTime * max(n, 1))()
+    n = _lib.evq_timing_report(arr, n)
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n)}
+
+
+lib = _lib

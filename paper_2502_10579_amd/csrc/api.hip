@@ -1,0 +1,170 @@
+// C ABI of the library: argument validation, error capture and dispatch.
+// Nothing throws across this boundary; every failure becomes an evq_status
+// with a thread-local message.
+#include "evq_internal.h"
+
+struct evq_graph {
+    evq::Graph* g;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+evq_status guard_exc() {
+    try {
+        throw;
+    } catch (const evq::Error& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return EVQ_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return EVQ_EDEVICE;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return EVQ_EDEVICE;
+    }
+}
+
+evq_status bad(evq_status c, const char* msg) {
+    g_last_error = msg;
+    return c;
+}
+
+// Validates a query and forms the window mask [b, b + L).
+evq_status make_window(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t b, uint32_t L, evq::Window& W) {
+    if (!h || !h->g) return bad(EVQ_EINVAL, "graph handle is NULL");
+    if (algo > EVQ_SSNP) return bad(EVQ_EINVAL, "unknown algorithm");
+    const evq::Graph& g = *h->g;
+    if (source >= g.V) return bad(EVQ_ERANGE, "source vertex out of range");
+    if (L == 0 || b >= g.K || L > g.K - b) return bad(EVQ_ERANGE, "window out of range");
+    W.b = b;
+    W.L = L;
+    W.w[0] = W.w[1] = 0;
+    for (uint32_t t = b; t < b + L; ++t) W.w[t >> 6] |= 1ull << (t & 63);
+    W.full = (b == 0 && L == g.K);
+    return EVQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+evq_status evq_build(uint32_t num_vertices, const evq_edge* base, uint64_t n_base, const evq_batch* batches,
+                     uint32_t K, void* stream, evq_graph** out) {
+    g_last_error.clear();
+    if (!out) return bad(EVQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (num_vertices == 0) return bad(EVQ_EINVAL, "num_vertices must be >= 1");
+    if (K == 0 || K > EVQ_MAX_SNAPSHOTS) return bad(EVQ_EINVAL, "K must be in [1, 128]");
+    if (!batches) return bad(EVQ_EINVAL, "batches is NULL");
+    if (n_base && !base) return bad(EVQ_EINVAL, "base is NULL with n_base > 0");
+    try {
+        evq::Graph* g = evq::build_graph(num_vertices, base, n_base, batches, K, (hipStream_t)stream);
+        evq_graph* h = new evq_graph{g};
+        *out = h;
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+evq_status evq_graph_info_get(const evq_graph* h, evq_graph_info* info) {
+    g_last_error.clear();
+    if (!h || !h->g || !info) return bad(EVQ_EINVAL, "NULL argument");
+    const evq::Graph& g = *h->g;
+    std::memset(info, 0, sizeof(*info));
+    info->num_vertices = g.V;
+    info->num_snapshots = g.K;
+    info->mask_words = g.MW;
+    info->num_edges = g.E;
+    info->num_partial = g.n_partial;
+    info->device_bytes = g.bytes;
+    info->build_ms = g.build_ms;
+    return EVQ_OK;
+}
+
+evq_status evq_graph_export(const evq_graph* h, uint32_t* row_ptr, uint32_t* row_split, uint32_t* col, uint32_t* w,
+                            uint64_t* mask, void* stream) {
+    g_last_error.clear();
+    if (!h || !h->g) return bad(EVQ_EINVAL, "graph handle is NULL");
+    try {
+        const evq::Graph& g = *h->g;
+        hipStream_t s = (hipStream_t)stream;
+        if (row_ptr) EVQ_HIP(hipMemcpyAsync(row_ptr, g.row_ptr, ((uint64_t)g.V + 1) * 4, hipMemcpyDeviceToHost, s));
+        if (row_split) EVQ_HIP(hipMemcpyAsync(row_split, g.row_split, (uint64_t)g.V * 4, hipMemcpyDeviceToHost, s));
+        if (g.E) {
+            if (col) EVQ_HIP(hipMemcpyAsync(col, g.col, g.E * 4, hipMemcpyDeviceToHost, s));
+            if (w) EVQ_HIP(hipMemcpyAsync(w, g.wgt, g.E * 4, hipMemcpyDeviceToHost, s));
+            if (mask) EVQ_HIP(hipMemcpyAsync(mask, g.mask, g.E * 8 * g.MW, hipMemcpyDeviceToHost, s));
+        }
+        EVQ_HIP(hipStreamSynchronize(s));
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+evq_status evq_query(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t win_begin, uint32_t win_len,
+                     uint32_t* d_values, evq_query_stats* stats, void* stream) {
+    g_last_error.clear();
+    evq::Window W;
+    evq_status rc = make_window(h, algo, source, win_begin, win_len, W);
+    if (rc != EVQ_OK) return rc;
+    if (!d_values) return bad(EVQ_EINVAL, "d_values is NULL");
+    try {
+        evq::QueryOut qo;
+        qo.want_stats = stats != nullptr;
+        evq::run_query(*h->g, algo, source, W, d_values, nullptr, nullptr, false, qo, (hipStream_t)stream);
+        if (stats) *stats = qo.st;
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+evq_status evq_query_bounds(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t win_begin, uint32_t win_len,
+                            uint32_t* d_rcap, uint32_t* d_rcup, void* stream) {
+    g_last_error.clear();
+    evq::Window W;
+    evq_status rc = make_window(h, algo, source, win_begin, win_len, W);
+    if (rc != EVQ_OK) return rc;
+    try {
+        evq::QueryOut qo;
+        evq::run_query(*h->g, algo, source, W, nullptr, d_rcap, d_rcup, true, qo, (hipStream_t)stream);
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+evq_status evq_query_plain(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t win_begin, uint32_t win_len,
+                           uint32_t* d_values, evq_query_stats* stats, void* stream) {
+    g_last_error.clear();
+    evq::Window W;
+    evq_status rc = make_window(h, algo, source, win_begin, win_len, W);
+    if (rc != EVQ_OK) return rc;
+    if (!d_values) return bad(EVQ_EINVAL, "d_values is NULL");
+    try {
+        evq::QueryOut qo;
+        qo.want_stats = stats != nullptr;
+        evq::run_plain(*h->g, algo, source, W, d_values, qo, (hipStream_t)stream);
+        if (stats) *stats = qo.st;
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+void evq_free(evq_graph* h) {
+    if (!h) return;
+    evq::free_graph(h->g);
+    delete h;
+}
+
+const char* evq_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

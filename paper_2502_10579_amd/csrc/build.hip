@@ -1,0 +1,465 @@
+// Versioned-graph builder (Section 4.1): base edge set + K update batches ->
+// one CSR over every (src, dst, w) triple present in some snapshot, each edge
+// carrying a K-bit presence mask (bit i = snapshot i), the edges present in
+// all K snapshots first in each row.
+//
+// Pipeline (all on the device after one host->device copy of the events):
+//   1. encode each event as one sortable key  src | dst | w | t  where
+//      t = 0 for the base, 2i+1 for a deletion of batch i, 2i+2 for an
+//      addition of batch i (deletions of a batch act before its additions);
+//   2. LSD radix sort of the keys, 8-bit digits over the used bits only;
+//   3. per run of equal triples, replay its events in t order into the mask
+//      (an addition at snapshot s makes the triple present from s until the
+//      next event of that triple);
+//   4. prefix-sum compaction of the triples whose mask is non-zero;
+//   5. row offsets from the sorted sources, then a stable per-row partition
+//      (all-present edges first) and the list of partial edges.
+#include <chrono>
+
+#include "evq_internal.h"
+
+namespace evq {
+namespace {
+
+typedef unsigned __int128 u128;
+
+struct KeyLayout {
+    int vb, wb, tb;  // bits of a vertex id, a weight, an event time
+    int total() const { return 2 * vb + wb + tb; }
+};
+
+__host__ __device__ inline int bits_for(uint64_t maxval) {
+    int b = 0;
+    while (b < 64 && (maxval >> b) != 0) ++b;
+    return b < 1 ? 1 : b;
+}
+
+template <typename KT>
+__device__ __forceinline__ KT make_key(uint32_t s, uint32_t d, uint32_t w, uint32_t t, KeyLayout L) {
+    KT k = (KT)s;
+    k = (k << L.vb) | (KT)d;
+    k = (k << L.wb) | (KT)w;
+    k = (k << L.tb) | (KT)t;
+    return k;
+}
+
+// Event segments: seg_start[j] = first event index of segment j, j = 0 .. 2K+1
+// (segment 0 = base, 2i+1 = deletions of batch i, 2i+2 = additions of batch i);
+// seg_start[2K+1] = total.  The segment index is the event time t.
+template <typename KT>
+__global__ void k_encode(const uint32_t* __restrict__ ev, uint64_t n, const uint64_t* __restrict__ seg_start,
+                         int nseg, KeyLayout L, KT* __restrict__ keys) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = nseg - 1;  // largest j with seg_start[j] <= i
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (seg_start[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        keys[i] = make_key<KT>(ev[3 * i], ev[3 * i + 1], ev[3 * i + 2], (uint32_t)lo, L);
+    }
+}
+
+// ------------------------------------------------------------------ radix sort
+
+constexpr int kRsBlock = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsBlock * kRsItems;
+
+template <typename KT>
+__device__ __forceinline__ uint32_t digit_of(KT k, int shift) {
+    return (uint32_t)(k >> shift) & 0xFFu;
+}
+
+// Lanes of this wave holding the same 8-bit digit (restricted to `valid` lanes).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        bool bit = (d >> b) & 1u;
+        uint64_t bb = __ballot(bit);
+        peers &= bit ? bb : ~bb;
+    }
+    return peers;
+}
+
+template <typename KT>
+__global__ void __launch_bounds__(kRsBlock) k_rs_hist(const KT* __restrict__ keys, uint64_t n, int shift,
+                                                      uint32_t* __restrict__ hist, uint32_t nb) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsItems; ++r) {
+        uint64_t i = base + (uint64_t)r * kRsBlock + threadIdx.x;
+        bool valid = i < n;
+        uint32_t d = valid ? digit_of(keys[i], shift) : 0u;
+        uint64_t peers = match_digit(d, valid);
+        if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: keys of a tile keep their order within each digit.
+template <typename KT>
+__global__ void __launch_bounds__(kRsBlock) k_rs_scatter(const KT* __restrict__ in, KT* __restrict__ out, uint64_t n,
+                                                         int shift, const uint32_t* __restrict__ offs, uint32_t nb) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[kRsBlock / 64][256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    run[tid] = offs[(uint64_t)tid * nb + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kRsBlock / 64; ++w) wc[w][tid] = 0;
+    __syncthreads();
+    uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsItems; ++r) {
+        uint64_t i = base + (uint64_t)r * kRsBlock + tid;
+        bool valid = i < n;
+        KT k = valid ? in[i] : (KT)0;
+        uint32_t d = valid ? digit_of(k, shift) : 0u;
+        uint64_t peers = match_digit(d, valid);
+        uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+        if (valid && rank == 0) wc[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = run[d];
+            for (int w = 0; w < wave; ++w) off += wc[w][d];
+            out[off + rank] = k;
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < kRsBlock / 64; ++w) {
+            tot += wc[w][tid];
+            wc[w][tid] = 0;
+        }
+        run[tid] += tot;
+        __syncthreads();
+    }
+}
+
+// Sorts keys[0..n) on their low `bits` bits; returns the buffer holding the result.
+template <typename KT>
+KT* radix_sort(KT* keys, KT* tmp, uint64_t n, int bits, hipStream_t s, Arena& ar) {
+    uint64_t nb64 = (n + kRsTile - 1) / kRsTile;
+    uint32_t nb = (uint32_t)nb64;
+    uint32_t* hist = ar.alloc<uint32_t>(256ull * nb);
+    for (int shift = 0; shift < bits; shift += 8) {
+        EVQ_LAUNCH("build_rs_hist", k_rs_hist<KT>, nb, kRsBlock, s, keys, n, shift, hist, nb);
+        scan_exclusive(hist, hist, 256ull * nb, nullptr, s, ar);
+        EVQ_LAUNCH("build_rs_scatter", k_rs_scatter<KT>, nb, kRsBlock, s, keys, tmp, n, shift, hist, nb);
+        KT* t = keys;
+        keys = tmp;
+        tmp = t;
+    }
+    ar.release(hist);
+    return keys;
+}
+
+// ------------------------------------------------------------------ masks
+
+__device__ __forceinline__ int snap_of(uint32_t t) { return t == 0 ? -1 : (int)((t - 1) >> 1); }
+
+template <int MW>
+__device__ __forceinline__ void set_range(uint64_t (&m)[MW], int a, int b) {
+#pragma unroll
+    for (int j = 0; j < MW; ++j) {
+        int lo = a - 64 * j, hi = b - 64 * j;
+        if (lo < 0) lo = 0;
+        if (hi > 64) hi = 64;
+        if (hi <= lo) continue;
+        uint64_t upto = hi == 64 ? ~0ull : ((1ull << hi) - 1ull);
+        uint64_t from = (1ull << lo) - 1ull;
+        m[j] |= upto & ~from;
+    }
+}
+
+template <typename KT, int MW>
+__global__ void k_seg_masks(const KT* __restrict__ keys, uint64_t n, KeyLayout L, int K, uint64_t* __restrict__ mtmp,
+                            uint32_t* __restrict__ flag) {
+    const KT tmask = ((KT)1 << L.tb) - 1;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        KT k = keys[i];
+        KT trip = k >> L.tb;
+        bool head = (i == 0) || ((keys[i - 1] >> L.tb) != trip);
+        uint32_t f = 0;
+        if (head) {
+            uint64_t m[MW];
+#pragma unroll
+            for (int j = 0; j < MW; ++j) m[j] = 0;
+            uint64_t j = i;
+            uint32_t t = (uint32_t)(k & tmask);
+            while (true) {
+                bool has_next = false;
+                uint32_t tn = 0;
+                if (j + 1 < n) {
+                    KT kn = keys[j + 1];
+                    if ((kn >> L.tb) == trip) {
+                        has_next = true;
+                        tn = (uint32_t)(kn & tmask);
+                    }
+                }
+                bool is_add = (t & 1u) == 0;  // base (0) and additions (even)
+                if (is_add) {
+                    int a = snap_of(t);
+                    if (a < 0) a = 0;
+                    set_range<MW>(m, a, has_next ? snap_of(tn) : K);
+                }
+                if (!has_next) break;
+                ++j;
+                t = tn;
+            }
+#pragma unroll
+            for (int q = 0; q < MW; ++q) {
+                mtmp[i * MW + q] = m[q];
+                f |= m[q] != 0;
+            }
+        }
+        flag[i] = f;
+    }
+}
+
+template <typename KT, int MW>
+__global__ void k_compact(const KT* __restrict__ keys, uint64_t n, KeyLayout L, const uint32_t* __restrict__ flag,
+                          const uint32_t* __restrict__ pos, const uint64_t* __restrict__ mtmp, Mask<MW> all,
+                          uint32_t* __restrict__ c_src, uint32_t* __restrict__ c_dst, uint32_t* __restrict__ c_w,
+                          uint64_t* __restrict__ c_mask, uint32_t* __restrict__ c_full) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (!flag[i]) continue;
+        uint32_t p = pos[i];
+        KT k = keys[i] >> L.tb;
+        uint32_t w = (uint32_t)(k & (((KT)1 << L.wb) - 1));
+        k >>= L.wb;
+        uint32_t d = (uint32_t)(k & (((KT)1 << L.vb) - 1));
+        k >>= L.vb;
+        c_src[p] = (uint32_t)k;
+        c_dst[p] = d;
+        c_w[p] = w;
+        bool full = true;
+#pragma unroll
+        for (int q = 0; q < MW; ++q) {
+            uint64_t m = mtmp[i * MW + q];
+            c_mask[(uint64_t)p * MW + q] = m;
+            full &= m == all.w[q];
+        }
+        c_full[p] = full ? 1u : 0u;
+    }
+}
+
+// row_ptr[v] = first compacted edge with src >= v (sources are sorted).
+__global__ void k_row_ptr(const uint32_t* __restrict__ c_src, uint64_t E, uint32_t V, uint32_t* __restrict__ row_ptr) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= E; i += (uint64_t)gridDim.x * blockDim.x) {
+        int64_t prev = i == 0 ? -1 : (int64_t)c_src[i - 1];
+        int64_t cur = i == E ? (int64_t)V : (int64_t)c_src[i];
+        for (int64_t v = prev + 1; v <= cur; ++v) row_ptr[v] = (uint32_t)i;
+    }
+}
+
+template <int MW>
+__global__ void k_partition(const uint32_t* __restrict__ c_src, const uint32_t* __restrict__ c_dst,
+                            const uint32_t* __restrict__ c_w, const uint64_t* __restrict__ c_mask,
+                            const uint32_t* __restrict__ c_full, const uint32_t* __restrict__ fb, uint64_t E,
+                            const uint32_t* __restrict__ row_ptr, uint32_t* __restrict__ col,
+                            uint32_t* __restrict__ wgt, uint64_t* __restrict__ mask, uint32_t* __restrict__ p_src,
+                            uint32_t* __restrict__ p_eid) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < E; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t u = c_src[i];
+        uint32_t c0 = row_ptr[u], c1 = row_ptr[u + 1];
+        uint32_t fr = fb[i] - fb[c0];
+        uint32_t nf = fb[c1] - fb[c0];
+        uint32_t pos;
+        if (c_full[i]) {
+            pos = c0 + fr;
+        } else {
+            pos = c0 + nf + ((uint32_t)i - c0 - fr);
+            uint32_t p = (uint32_t)i - fb[i];
+            p_src[p] = u;
+            p_eid[p] = pos;
+        }
+        col[pos] = c_dst[i];
+        wgt[pos] = c_w[i];
+#pragma unroll
+        for (int q = 0; q < MW; ++q) mask[(uint64_t)pos * MW + q] = c_mask[i * MW + q];
+    }
+}
+
+__global__ void k_row_split(const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ fb, uint32_t V,
+                            uint32_t* __restrict__ row_split) {
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < V; u += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t c0 = row_ptr[u], c1 = row_ptr[u + 1];
+        row_split[u] = c0 + (fb[c1] - fb[c0]);
+    }
+}
+
+template <typename KT, int MW>
+void build_impl(Graph* g, const uint32_t* d_ev, uint64_t N, const uint64_t* d_seg, int nseg, KeyLayout L,
+                hipStream_t s, Arena& ar) {
+    const uint32_t K = g->K;
+    KT* keys = ar.alloc<KT>(N);
+    KT* tmp = ar.alloc<KT>(N);
+    EVQ_LAUNCH("build_encode", k_encode<KT>, grid_for(N, 256), 256, s, d_ev, N, d_seg, nseg, L, keys);
+    KT* sorted = radix_sort<KT>(keys, tmp, N, L.total(), s, ar);
+    KT* other = sorted == keys ? tmp : keys;
+    ar.release(other);
+
+    uint64_t* mtmp = ar.alloc<uint64_t>(N * MW);
+    uint32_t* flag = ar.alloc<uint32_t>(N + 1);
+    uint32_t* pos = ar.alloc<uint32_t>(N + 1);
+    EVQ_LAUNCH("build_seg_masks", (k_seg_masks<KT, MW>), grid_for(N, 256), 256, s, sorted, N, L, (int)K, mtmp, flag);
+    scan_exclusive(flag, pos, N, pos + N, s, ar);
+    Mailbox mb(1);
+    EVQ_HIP(hipMemcpyAsync(mb.h, pos + N, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipStreamSynchronize(s));
+    const uint64_t E = mb.h[0];
+    g->E = E;
+
+    Mask<MW> all;
+#pragma unroll
+    for (int q = 0; q < MW; ++q) {
+        int lo = 64 * q, hi = (int)K - 64 * q;
+        all.w[q] = hi >= 64 ? ~0ull : (hi <= 0 ? 0ull : ((1ull << hi) - 1ull));
+        (void)lo;
+    }
+
+    uint32_t* c_src = ar.alloc<uint32_t>(E + 1);
+    uint32_t* c_dst = ar.alloc<uint32_t>(E + 1);
+    uint32_t* c_w = ar.alloc<uint32_t>(E + 1);
+    uint64_t* c_mask = ar.alloc<uint64_t>((E + 1) * MW);
+    uint32_t* c_full = ar.alloc<uint32_t>(E + 1);
+    uint32_t* fb = ar.alloc<uint32_t>(E + 1);
+    EVQ_LAUNCH("build_compact", (k_compact<KT, MW>), grid_for(N, 256), 256, s, sorted, N, L, flag, pos, mtmp, all,
+               c_src, c_dst, c_w, c_mask, c_full);
+    ar.release(mtmp);
+    ar.release(flag);
+    ar.release(pos);
+    ar.release(sorted);
+
+    g->row_ptr = (uint32_t*)dev_alloc(((uint64_t)g->V + 1) * 4);
+    g->row_split = (uint32_t*)dev_alloc((uint64_t)g->V * 4);
+    g->col = (uint32_t*)dev_alloc(E * 4);
+    g->wgt = (uint32_t*)dev_alloc(E * 4);
+    g->mask = (uint64_t*)dev_alloc(E * 8 * MW);
+    g->bytes = ((uint64_t)g->V + 1) * 4 + (uint64_t)g->V * 4 + E * (8 + 8 * MW);
+
+    EVQ_LAUNCH("build_row_ptr", k_row_ptr, grid_for(E + 1, 256), 256, s, c_src, E, g->V, g->row_ptr);
+    scan_exclusive(c_full, fb, E, fb + E, s, ar);
+    EVQ_HIP(hipMemcpyAsync(mb.h, fb + E, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipStreamSynchronize(s));
+    const uint64_t n_full = mb.h[0];
+    g->n_partial = E - n_full;
+    g->p_src = (uint32_t*)dev_alloc(g->n_partial * 4);
+    g->p_eid = (uint32_t*)dev_alloc(g->n_partial * 4);
+    g->bytes += g->n_partial * 8;
+    if (E > 0)
+        EVQ_LAUNCH("build_partition", k_partition<MW>, grid_for(E, 256), 256, s, c_src, c_dst, c_w, c_mask, c_full, fb,
+                   E, g->row_ptr, g->col, g->wgt, g->mask, g->p_src, g->p_eid);
+    EVQ_LAUNCH("build_row_split", k_row_split, grid_for(g->V, 256), 256, s, g->row_ptr, fb, g->V, g->row_split);
+    EVQ_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void free_graph(Graph* g) {
+    if (!g) return;
+    dev_free(g->row_ptr);
+    dev_free(g->row_split);
+    dev_free(g->col);
+    dev_free(g->wgt);
+    dev_free(g->mask);
+    dev_free(g->p_src);
+    dev_free(g->p_eid);
+    delete g;
+}
+
+Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_batch* batches, uint32_t K,
+                   hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    // ---- validation (host, before any device work)
+    uint64_t maxw = 1;
+    uint64_t N = n_base;
+    auto check = [&](const evq_edge* e, uint64_t n, const char* what) {
+        if (n && !e) fail(EVQ_EINVAL, std::string(what) + " is NULL with a non-zero count");
+        for (uint64_t i = 0; i < n; ++i) {
+            if (e[i].src >= V || e[i].dst >= V)
+                fail(EVQ_EINVAL, std::string(what) + ": vertex id out of range at index " + std::to_string(i));
+            if (e[i].w == 0) fail(EVQ_EINVAL, std::string(what) + ": zero weight at index " + std::to_string(i));
+            if (e[i].w > maxw) maxw = e[i].w;
+        }
+    };
+    check(base, n_base, "base");
+    for (uint32_t i = 0; i < K; ++i) {
+        check(batches[i].del, batches[i].n_del, "batch deletions");
+        check(batches[i].add, batches[i].n_add, "batch additions");
+        N += batches[i].n_del + batches[i].n_add;
+    }
+    if (N >= 0xFFFFFFFEull) fail(EVQ_ERANGE, "more than 2^32 - 2 edge events");
+
+    int dev = 0;
+    EVQ_HIP(hipGetDevice(&dev));
+    init_mempool(dev);
+    Graph* g = new Graph();
+    g->V = V;
+    g->K = K;
+    g->MW = K > 64 ? 2 : 1;
+    g->device = dev;
+    try {
+        Arena ar(s);
+        // ---- events to the device: [base | del_0 | add_0 | del_1 | add_1 | ...]
+        const int nseg = 2 * (int)K + 2;
+        std::vector<uint64_t> seg(nseg);
+        uint32_t* d_ev = ar.alloc<uint32_t>(3 * (N + 1));
+        uint64_t at = 0;
+        auto put = [&](const evq_edge* e, uint64_t n) {
+            if (n) EVQ_HIP(hipMemcpyAsync(d_ev + 3 * at, e, n * sizeof(evq_edge), hipMemcpyHostToDevice, s));
+            at += n;
+        };
+        seg[0] = 0;
+        put(base, n_base);
+        for (uint32_t i = 0; i < K; ++i) {
+            seg[2 * i + 1] = at;
+            put(batches[i].del, batches[i].n_del);
+            seg[2 * i + 2] = at;
+            put(batches[i].add, batches[i].n_add);
+        }
+        seg[nseg - 1] = at;  // sentinel: never matched for i < N (segments are [seg[j], seg[j+1]))
+        uint64_t* d_seg = ar.alloc<uint64_t>(nseg);
+        EVQ_HIP(hipMemcpyAsync(d_seg, seg.data(), nseg * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+
+        KeyLayout L;
+        L.vb = bits_for(V - 1);
+        L.wb = bits_for(maxw);
+        L.tb = bits_for(2ull * K);
+        if (N == 0) {
+            g->E = 0;
+            g->n_partial = 0;
+            g->row_ptr = (uint32_t*)dev_alloc(((uint64_t)V + 1) * 4);
+            g->row_split = (uint32_t*)dev_alloc((uint64_t)V * 4);
+            fill_u32(g->row_ptr, (uint64_t)V + 1, 0u, s);
+            fill_u32(g->row_split, V, 0u, s);
+            g->col = (uint32_t*)dev_alloc(4);
+            g->wgt = (uint32_t*)dev_alloc(4);
+            g->mask = (uint64_t*)dev_alloc(16);
+            g->p_src = (uint32_t*)dev_alloc(4);
+            g->p_eid = (uint32_t*)dev_alloc(4);
+            g->bytes = ((uint64_t)V + 1) * 8;
+            EVQ_HIP(hipStreamSynchronize(s));
+        } else if (L.total() <= 64) {
+            if (g->MW == 1) build_impl<uint64_t, 1>(g, d_ev, N, d_seg, nseg - 1, L, s, ar);
+            else build_impl<uint64_t, 2>(g, d_ev, N, d_seg, nseg - 1, L, s, ar);
+        } else {
+            if (g->MW == 1) build_impl<u128, 1>(g, d_ev, N, d_seg, nseg - 1, L, s, ar);
+            else build_impl<u128, 2>(g, d_ev, N, d_seg, nseg - 1, L, s, ar);
+        }
+        if (g->E >= 0xFFFFFFFEull) fail(EVQ_ERANGE, "more than 2^32 - 2 union edges");
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        free_graph(g);
+        throw;
+    }
+    EVQ_HIP(hipStreamSynchronize(s));
+    g->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return g;
+}
+
+}  // namespace evq

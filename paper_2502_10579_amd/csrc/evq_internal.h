@@ -1,0 +1,249 @@
+// Internal declarations shared by the library's HIP sources (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "evq.h"
+
+namespace evq {
+
+// ------------------------------------------------------------------ errors
+
+struct Error {
+    evq_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(evq_status code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+
+#define EVQ_HIP(expr) ::evq::hip_check((expr), #expr)
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+constexpr uint32_t kSat = 0xFFFFFFFEu;
+
+// ------------------------------------------------------------------ graph
+
+struct Graph {
+    uint32_t V = 0, K = 0, MW = 1;
+    uint64_t E = 0, n_partial = 0;
+    uint32_t* row_ptr = nullptr;    // V + 1
+    uint32_t* row_split = nullptr;  // V: end of the edges present in all K snapshots
+    uint32_t* col = nullptr;        // E
+    uint32_t* wgt = nullptr;        // E
+    uint64_t* mask = nullptr;       // E * MW, bit i of the 128/64-bit word group = snapshot i
+    uint32_t* p_src = nullptr;      // n_partial: source of each partial edge (ascending edge id)
+    uint32_t* p_eid = nullptr;      // n_partial: edge id of each partial edge
+    int device = 0;
+    uint64_t bytes = 0;
+    double build_ms = 0.0;
+};
+
+// ------------------------------------------------------------------ memory
+
+// Per-call device temporaries, stream-ordered (hipMallocAsync / hipFreeAsync).
+class Arena {
+  public:
+    explicit Arena(hipStream_t s) : s_(s) {}
+    ~Arena();
+    Arena(const Arena&) = delete;
+    Arena& operator=(const Arena&) = delete;
+    template <typename T>
+    T* alloc(uint64_t n) {
+        return static_cast<T*>(raw(n * sizeof(T)));
+    }
+    void* raw(uint64_t bytes);
+    void release(void* p);
+    uint64_t bytes() const { return bytes_; }
+
+  private:
+    hipStream_t s_;
+    std::vector<void*> ptrs_;
+    uint64_t bytes_ = 0;
+};
+
+void* dev_alloc(uint64_t bytes);  // hipMalloc; throws EVQ_ENOMEM
+void dev_free(void* p);
+void init_mempool(int device);
+
+// Small pinned host mailbox used to read counters back.
+struct Mailbox {
+    uint32_t* h = nullptr;
+    explicit Mailbox(size_t n);
+    ~Mailbox();
+};
+
+// ------------------------------------------------------------------ launches
+
+bool timing_on();
+struct TimingScope {
+    TimingScope(const char* name, hipStream_t s);
+    ~TimingScope();
+    const char* name;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+};
+void post_launch(const char* name);
+
+#define EVQ_LAUNCH(NAME, KERNEL, GRID, BLOCK, STREAM, ...)          \
+    do {                                                            \
+        ::evq::TimingScope _evq_ts((NAME), (STREAM));               \
+        KERNEL<<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);      \
+        ::evq::post_launch(NAME);                                   \
+    } while (0)
+
+inline uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap = 65536u) {
+    uint64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+// ------------------------------------------------------------------ host entry points of each part
+
+// Device-wide exclusive scan of n uint32 (in may equal out).  If d_total is
+// non-null it receives the sum.  n < 2^32.
+void scan_exclusive(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* d_total, hipStream_t s, Arena& ar);
+
+void fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+
+Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_batch* batches, uint32_t K,
+                   hipStream_t s);
+void free_graph(Graph* g);
+
+struct Window {
+    uint32_t b = 0, L = 0;
+    uint64_t w[2] = {0, 0};  // bits [b, b+L)
+    bool full = false;       // the window is all K snapshots
+};
+
+struct QueryOut {
+    evq_query_stats st{};
+    bool want_stats = false;
+};
+
+void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values,
+               uint32_t* d_rcap_out, uint32_t* d_rcup_out, bool bounds_only, QueryOut& qo, hipStream_t s);
+void run_plain(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values, QueryOut& qo,
+               hipStream_t s);
+
+}  // namespace evq
+
+// ------------------------------------------------------------------ device helpers
+
+namespace evq {
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+template <typename T>
+__device__ __forceinline__ T uniform(T x) {
+    return (T)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+// Wave-wide inclusive prefix sum (64 lanes).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Query value algebra (Table 2).  `better(a, b)`: a strictly improves on b.
+template <int A>
+struct Alg;
+
+template <>
+struct Alg<EVQ_SSSP> {
+    static constexpr uint32_t unreached = kInf, at_source = 0u;
+    __device__ static __forceinline__ uint32_t extend(uint32_t x, uint32_t w) {
+        if (x == kInf) return kInf;
+        uint64_t s = (uint64_t)x + w;
+        return s > kSat ? kSat : (uint32_t)s;
+    }
+    __device__ static __forceinline__ bool better(uint32_t a, uint32_t b) { return a < b; }
+    __device__ static __forceinline__ uint32_t improve(uint32_t* p, uint32_t v) { return atomicMin(p, v); }
+    __device__ static __forceinline__ void improve_nr(uint32_t* p, uint32_t v) {
+        __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+template <>
+struct Alg<EVQ_BFS> {
+    static constexpr uint32_t unreached = kInf, at_source = 0u;
+    __device__ static __forceinline__ uint32_t extend(uint32_t x, uint32_t) {
+        return x == kInf ? kInf : (x >= kSat ? kSat : x + 1u);
+    }
+    __device__ static __forceinline__ bool better(uint32_t a, uint32_t b) { return a < b; }
+    __device__ static __forceinline__ uint32_t improve(uint32_t* p, uint32_t v) { return atomicMin(p, v); }
+    __device__ static __forceinline__ void improve_nr(uint32_t* p, uint32_t v) {
+        __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+template <>
+struct Alg<EVQ_SSWP> {
+    static constexpr uint32_t unreached = 0u, at_source = kInf;
+    __device__ static __forceinline__ uint32_t extend(uint32_t x, uint32_t w) { return x < w ? x : w; }
+    __device__ static __forceinline__ bool better(uint32_t a, uint32_t b) { return a > b; }
+    __device__ static __forceinline__ uint32_t improve(uint32_t* p, uint32_t v) { return atomicMax(p, v); }
+    __device__ static __forceinline__ void improve_nr(uint32_t* p, uint32_t v) {
+        __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+template <>
+struct Alg<EVQ_SSNP> {
+    static constexpr uint32_t unreached = kInf, at_source = 0u;
+    __device__ static __forceinline__ uint32_t extend(uint32_t x, uint32_t w) {
+        return x == kInf ? kInf : (x > w ? x : w);
+    }
+    __device__ static __forceinline__ bool better(uint32_t a, uint32_t b) { return a < b; }
+    __device__ static __forceinline__ uint32_t improve(uint32_t* p, uint32_t v) { return atomicMin(p, v); }
+    __device__ static __forceinline__ void improve_nr(uint32_t* p, uint32_t v) {
+        __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+inline uint32_t host_unreached(uint32_t algo) { return algo == EVQ_SSWP ? 0u : kInf; }
+inline uint32_t host_at_source(uint32_t algo) { return algo == EVQ_SSWP ? kInf : 0u; }
+
+// Snapshot-mask helpers: MW 64-bit words per edge.
+template <int MW>
+struct Mask {
+    uint64_t w[MW];
+};
+
+template <int MW>
+__device__ __forceinline__ Mask<MW> load_mask(const uint64_t* m, uint64_t e) {
+    Mask<MW> r;
+#pragma unroll
+    for (int j = 0; j < MW; ++j) r.w[j] = m[e * MW + j];
+    return r;
+}
+
+// Bits [b, b+L) of a mask, moved down to bit 0 (L <= 64 -> one word, else two).
+__device__ __forceinline__ uint64_t window_bits64(const uint64_t* w, int MW, uint32_t b) {
+    // MW == 1: b < 64
+    if (MW == 1) return w[0] >> b;
+    if (b == 0) return w[0];
+    if (b < 64) return (w[0] >> b) | (w[1] << (64 - b));
+    return w[1] >> (b - 64);
+}
+
+}  // namespace evq

@@ -1,0 +1,720 @@
+// One query over a window of snapshots (Algorithm 1 then Algorithm 2):
+//   bounds  -> intersection and union solves (solve.hip)
+//   K3      -> U = {v : R_cap[v] != R_cup[v]} with compact ids (Step 2,
+//              Theorem 2), then the reduced subgraph built from U's rows
+//              ("in reverse", Section 6.2): every window edge u -> v with both
+//              ends in U, stored as (dst id, w, window lane bits)
+//   K4      -> per-snapshot values X[|U|][S] start at R_cap (Step 3); the
+//              window-partial edges into U (the reduced addition batches of
+//              Step 4) seed them, then one snapshot-oblivious frontier is
+//              relaxed until empty, lane i of an edge group testing bit i of
+//              the edge's window mask (Section 4.2)
+//   K5      -> values[v][i] = R_cap[v] for v outside U, X row of v otherwise
+//
+// Lane layout: L snapshots of a window map to LG = 8/16/32/64/128 lanes
+// (LG >= L, a power of two); a wave holds 64/LG edge groups (one for
+// LG >= 64; with LG = 128 each lane serves snapshots i and i + 64).  Rows of
+// X are LG uint32 wide, so a group's reads and atomics on one destination row
+// are one contiguous, coalesced span.
+#include <chrono>
+
+#include "bounds.h"
+
+namespace evq {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr uint32_t kRowChunk = 1024;   // union-row edges per compaction task
+constexpr uint32_t kRelaxChunk = 64;   // reduced-subgraph edges per relaxation task
+
+__global__ void k_reset_pair(FrontierCounters* c, int p) {
+    if (threadIdx.x == 0) {
+        c->small[p] = 0;
+        c->big[p] = 0;
+    }
+}
+
+template <int NLW>
+struct Rec {
+    uint32_t dst;
+    uint32_t w;
+    uint64_t lanes[NLW];
+};
+
+template <int LG>
+struct Lanes {
+    static constexpr int G = LG >= 64 ? 1 : 64 / LG;  // edge groups per wave
+    static constexpr int SPL = LG > 64 ? 2 : 1;       // snapshots per lane
+    static constexpr int NLW = LG > 64 ? 2 : 1;       // 64-bit lane words per record
+    static constexpr uint32_t S = LG;                 // X row stride (uint32)
+};
+
+__device__ __forceinline__ uint64_t low_mask(uint32_t n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+
+// Window lane bits of edge e (bit i = present in snapshot b + i).
+template <int MW, int NLW>
+__device__ __forceinline__ void edge_lanes(const uint64_t* __restrict__ mask, uint32_t e, bool full_edge, uint32_t b,
+                                           uint32_t L, uint64_t (&out)[NLW]) {
+    if (full_edge) {
+        out[0] = low_mask(L);
+        if (NLW == 2) out[NLW - 1] = L > 64 ? low_mask(L - 64) : 0ull;
+        return;
+    }
+    if (MW == 1) {
+        out[0] = (mask[e] >> b) & low_mask(L);
+        if (NLW == 2) out[NLW - 1] = 0ull;
+        return;
+    }
+    unsigned __int128 m = ((unsigned __int128)mask[2ull * e + 1] << 64) | mask[2ull * e];
+    m >>= b;
+    out[0] = (uint64_t)m & low_mask(L);
+    if (NLW == 2) out[NLW - 1] = L > 64 ? ((uint64_t)(m >> 64) & low_mask(L - 64)) : 0ull;
+}
+
+template <int NLW>
+__device__ __forceinline__ bool lanes_partial(const uint64_t (&x)[NLW], uint32_t L) {
+    bool any = false, all = true;
+#pragma unroll
+    for (int j = 0; j < NLW; ++j) {
+        any |= x[j] != 0;
+        uint32_t n = L > 64u * j ? L - 64u * j : 0u;
+        all &= x[j] == low_mask(n > 64 ? 64 : n);
+    }
+    return any && !all;
+}
+
+// ------------------------------------------------------------------ K3: unstable set
+
+__global__ void k_flag_unstable(const uint32_t* __restrict__ rcap, const uint32_t* __restrict__ rcup, uint32_t V,
+                                uint32_t* __restrict__ flag) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x)
+        flag[v] = rcap[v] != rcup[v] ? 1u : 0u;
+}
+
+__global__ void k_flag_all(uint32_t V, uint32_t* __restrict__ flag) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x)
+        flag[v] = 1u;
+}
+
+__global__ void k_assign(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ cidx, uint32_t V,
+                         uint32_t* __restrict__ cid_of, uint32_t* __restrict__ ulist) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x) {
+        if (flag[v]) {
+            cid_of[v] = cidx[v];
+            ulist[cidx[v]] = (uint32_t)v;
+        } else {
+            cid_of[v] = kNone;
+        }
+    }
+}
+
+// Compaction tasks: ceil(deg / kRowChunk) (at least one) per vertex of U.
+__global__ void k_task_count(const uint32_t* __restrict__ ulist, uint32_t nU, const uint32_t* __restrict__ row_ptr,
+                             uint32_t* __restrict__ tcnt) {
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nU; c += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t u = ulist[c];
+        uint32_t deg = row_ptr[u + 1] - row_ptr[u];
+        uint32_t n = (deg + kRowChunk - 1) / kRowChunk;
+        tcnt[c] = n ? n : 1u;
+    }
+}
+
+__global__ void k_task_fill(const uint32_t* __restrict__ tcnt, const uint32_t* __restrict__ toff, uint32_t nU,
+                            uint64_t* __restrict__ tasks) {
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nU; c += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t o = toff[c];
+        for (uint32_t k = 0; k < tcnt[c]; ++k) tasks[o + k] = ((uint64_t)k << 32) | (uint32_t)c;
+    }
+}
+
+struct CompactArgs {
+    const uint32_t* row_ptr;
+    const uint32_t* row_split;
+    const uint32_t* col;
+    const uint32_t* wgt;
+    const uint64_t* mask;
+    const uint32_t* ulist;
+    const uint32_t* cid_of;
+    const uint64_t* tasks;
+    uint32_t n_tasks;
+    uint32_t b, L;
+};
+
+// Pass 1 (count) and pass 2 (fill) over the union rows of U: keep the edges
+// present in some snapshot of the window whose destination is in U.
+template <int MW, int NLW, bool FILL>
+__global__ void __launch_bounds__(kBlock) k_reduce_rows(CompactArgs a, uint32_t* __restrict__ ecnt,
+                                                        const uint32_t* __restrict__ eoff, Rec<NLW>* __restrict__ out) {
+    const int lane = lane_id();
+    const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t nw = gridDim.x * (kBlock / 64);
+    for (uint32_t t = gw; t < a.n_tasks; t += nw) {
+        uint64_t tk = a.tasks[t];
+        uint32_t c = (uint32_t)tk, ch = (uint32_t)(tk >> 32);
+        uint32_t u = a.ulist[c];
+        uint32_t beg = a.row_ptr[u], end = a.row_ptr[u + 1], split = a.row_split[u];
+        uint32_t e0 = beg + ch * kRowChunk;
+        uint32_t e1 = e0 + kRowChunk < end ? e0 + kRowChunk : end;
+        uint32_t at = FILL ? eoff[t] : 0u;
+        for (uint32_t e = e0; e < e1; e += 64) {
+            uint32_t ee = e + lane;
+            bool keep = false;
+            uint64_t lanes[NLW];
+            uint32_t cd = 0;
+            if (ee < e1) {
+                cd = a.cid_of[a.col[ee]];
+                if (cd != kNone) {
+                    edge_lanes<MW, NLW>(a.mask, ee, ee < split, a.b, a.L, lanes);
+                    bool any = false;
+#pragma unroll
+                    for (int j = 0; j < NLW; ++j) any |= lanes[j] != 0;
+                    keep = any;
+                }
+            }
+            uint64_t bal = __ballot(keep);
+            if (FILL && keep) {
+                Rec<NLW> r;
+                r.dst = cd;
+                r.w = a.wgt[ee];
+#pragma unroll
+                for (int j = 0; j < NLW; ++j) r.lanes[j] = lanes[j];
+                out[at + (uint32_t)__popcll(bal & lanemask_lt())] = r;
+            }
+            at += (uint32_t)__popcll(bal);
+        }
+        if (!FILL && lane == 0) ecnt[t] = at;
+    }
+}
+
+__global__ void k_rptr(const uint32_t* __restrict__ toff, const uint32_t* __restrict__ eoff, uint32_t nU,
+                       uint32_t* __restrict__ rptr) {
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c <= nU; c += (uint64_t)gridDim.x * blockDim.x)
+        rptr[c] = eoff[toff[c]];
+}
+
+// ------------------------------------------------------------------ K4: multi-snapshot relaxation
+
+struct RelaxArgs {
+    const uint32_t* rptr;
+    const void* recs;
+    uint32_t* X;
+    uint32_t* stamps;
+    uint64_t* tasks[2];
+    FrontierCounters* cnt;
+    unsigned long long* stats;  // [1] edge visits, [2] lane relaxations, [3] seed edges
+};
+
+// Push the group leaders' vertices (compact ids) as relaxation tasks.
+__device__ __forceinline__ void push_task(const RelaxArgs& r, uint32_t c, bool want, uint32_t stamp, int np) {
+    bool fresh = claim(r.stamps, c, want, stamp);
+    uint32_t nch = 0;
+    if (fresh) {
+        uint32_t deg = r.rptr[c + 1] - r.rptr[c];
+        nch = (deg + kRelaxChunk - 1) / kRelaxChunk;
+    }
+    wave_append_tasks(nch, c, r.tasks[np], &r.cnt->small[np]);
+}
+
+template <int LG>
+__device__ __forceinline__ bool group_any(bool x) {
+    uint64_t bal = __ballot(x);
+    if (LG >= 64) return bal != 0;
+    const int g = lane_id() / LG;
+    return ((bal >> (g * LG)) & low_mask(LG)) != 0;
+}
+
+template <int LG>
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint32_t o = __shfl_xor(v, d, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+template <bool ST>
+__device__ __forceinline__ void add_stat(unsigned long long* p, uint32_t v) {
+    if (!ST) return;
+    uint32_t s = wave_sum(v);
+    if (lane_id() == 0 && s) atomicAdd(p, (unsigned long long)s);
+}
+
+// Seeding pass (the parfor over the reduced addition batches in Algorithm 2):
+// each window-partial edge u -> v with v in U improves v's lanes from R_cap[u].
+template <int A, int MW, int LG, bool ST>
+__global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32_t* __restrict__ p_src,
+                                                       const uint32_t* __restrict__ p_eid, uint32_t n_partial,
+                                                       const uint32_t* __restrict__ col,
+                                                       const uint32_t* __restrict__ wgt,
+                                                       const uint64_t* __restrict__ mask,
+                                                       const uint32_t* __restrict__ cid_of,
+                                                       const uint32_t* __restrict__ rcap, uint32_t b, uint32_t L,
+                                                       uint32_t stamp) {
+    using T = Lanes<LG>;
+    const int lane = lane_id();
+    const int g = LG >= 64 ? 0 : lane / LG;
+    const int i0 = LG >= 64 ? lane : lane % LG;
+    const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t nw = gridDim.x * (kBlock / 64);
+    for (uint32_t qb = gw * T::G; qb < n_partial; qb += nw * T::G) {
+        uint32_t q = qb + g;
+        bool act = q < n_partial;
+        uint32_t cv = 0, cand = 0;
+        uint64_t lanes[T::NLW];
+        if (act) {
+            uint32_t e = p_eid[q];
+            cv = cid_of[col[e]];
+            act = cv != kNone;
+            if (act) {
+                edge_lanes<MW, T::NLW>(mask, e, false, b, L, lanes);
+                act = lanes_partial<T::NLW>(lanes, L);
+                cand = Alg<A>::extend(rcap[p_src[q]], wgt[e]);
+            }
+        }
+        add_stat<ST>(&r.stats[3], (act && i0 == 0) ? 1u : 0u);
+        bool imp = false;
+#pragma unroll
+        for (int s = 0; s < T::SPL; ++s) {
+            const int i = i0 + 64 * s;
+            bool bit = act && ((lanes[s] >> (i & 63)) & 1ull);
+            if (bit) {
+                uint32_t* p = &r.X[(uint64_t)cv * T::S + i];
+                if (Alg<A>::better(cand, *p)) {
+                    Alg<A>::improve_nr(p, cand);
+                    imp = true;
+                }
+            }
+        }
+        bool gi = group_any<LG>(imp);
+        push_task(r, cv, gi && i0 == 0, stamp, 0);
+    }
+}
+
+template <int A, int LG, bool ST>
+__global__ void __launch_bounds__(kBlock) k_relax(RelaxArgs r, int p, uint32_t stamp) {
+    using T = Lanes<LG>;
+    const uint32_t n = r.cnt->small[p];
+    const uint64_t* __restrict__ tasks = r.tasks[p];
+    const Rec<T::NLW>* __restrict__ recs = static_cast<const Rec<T::NLW>*>(r.recs);
+    const int lane = lane_id();
+    const int g = LG >= 64 ? 0 : lane / LG;
+    const int i0 = LG >= 64 ? lane : lane % LG;
+    const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t nw = gridDim.x * (kBlock / 64);
+    for (uint32_t tb = gw * T::G; tb < n; tb += nw * T::G) {
+        uint32_t ti = tb + g;
+        bool tact = ti < n;
+        uint32_t c = 0, e0 = 0, e1 = 0;
+        if (tact) {
+            uint64_t tk = tasks[ti];
+            if (T::G == 1) tk = ((uint64_t)uniform((uint32_t)(tk >> 32)) << 32) | uniform((uint32_t)tk);
+            c = (uint32_t)tk;
+            uint32_t ch = (uint32_t)(tk >> 32);
+            uint32_t rb = r.rptr[c], re = r.rptr[c + 1];
+            e0 = rb + ch * kRelaxChunk;
+            e1 = e0 + kRelaxChunk < re ? e0 + kRelaxChunk : re;
+        }
+        uint32_t xu[T::SPL];
+#pragma unroll
+        for (int s = 0; s < T::SPL; ++s) xu[s] = tact ? r.X[(uint64_t)c * T::S + i0 + 64 * s] : Alg<A>::unreached;
+        const uint32_t ne = e1 - e0;
+        const uint32_t maxne = T::G == 1 ? ne : wave_max<LG>(ne);
+        uint32_t lanes_done = 0;
+        for (uint32_t k = 0; k < maxne; ++k) {
+            bool ea = k < ne;
+            Rec<T::NLW> rec;
+            if (ea) rec = recs[e0 + k];
+            else {
+                rec.dst = 0;
+                rec.w = 0;
+#pragma unroll
+                for (int j = 0; j < T::NLW; ++j) rec.lanes[j] = 0;
+            }
+            bool imp = false;
+#pragma unroll
+            for (int s = 0; s < T::SPL; ++s) {
+                const int i = i0 + 64 * s;
+                bool bit = ea && ((rec.lanes[s] >> (i & 63)) & 1ull);
+                if (bit) {
+                    ++lanes_done;
+                    uint32_t cand = Alg<A>::extend(xu[s], rec.w);
+                    uint32_t* p = &r.X[(uint64_t)rec.dst * T::S + i];
+                    if (Alg<A>::better(cand, *p)) {
+                        Alg<A>::improve_nr(p, cand);
+                        imp = true;
+                    }
+                }
+            }
+            bool gi = group_any<LG>(imp);
+            push_task(r, rec.dst, gi && i0 == 0, stamp, p ^ 1);
+        }
+        if (ST) {
+            add_stat<true>(&r.stats[1], i0 == 0 ? ne : 0u);
+            add_stat<true>(&r.stats[2], lanes_done);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ init / K5
+
+template <int LG>
+__global__ void k_xinit(const uint32_t* __restrict__ ulist, uint32_t nU, const uint32_t* __restrict__ rcap,
+                        uint32_t* __restrict__ X) {
+    const uint64_t n = (uint64_t)nU * LG;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
+        X[k] = rcap[ulist[k / LG]];
+}
+
+template <int LG>
+__global__ void k_xinit_plain(uint32_t V, uint32_t source, uint32_t unreached, uint32_t at_source,
+                              uint32_t* __restrict__ X) {
+    const uint64_t n = (uint64_t)V * LG;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
+        X[k] = (k / LG) == source ? at_source : unreached;
+}
+
+__global__ void k_push_one(RelaxArgs r, uint32_t c, uint32_t stamp) {
+    if (threadIdx.x >= 64) return;
+    push_task(r, c, lane_id() == 0, stamp, 0);
+}
+
+// values[v * L + i]: one LG-lane group per vertex.
+template <int LG>
+__global__ void __launch_bounds__(kBlock) k_writeback(uint32_t V, uint32_t L, const uint32_t* __restrict__ cid_of,
+                                                      const uint32_t* __restrict__ rcap,
+                                                      const uint32_t* __restrict__ X, uint32_t* __restrict__ out) {
+    using T = Lanes<LG>;
+    const int lane = lane_id();
+    const int g = LG >= 64 ? 0 : lane / LG;
+    const int i0 = LG >= 64 ? lane : lane % LG;
+    const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
+    const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t vb = gw * T::G; vb < V; vb += nw * T::G) {
+        uint64_t v = vb + g;
+        if (v >= V) continue;
+        uint32_t c = cid_of ? cid_of[v] : kNone;
+        uint32_t base = rcap ? rcap[v] : 0u;
+#pragma unroll
+        for (int s = 0; s < T::SPL; ++s) {
+            uint32_t i = i0 + 64 * s;
+            if (i < L) out[v * L + i] = c == kNone ? base : X[(uint64_t)c * T::S + i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+uint32_t pick_lg(uint32_t L) {
+    if (L <= 8) return 8;
+    if (L <= 16) return 16;
+    if (L <= 32) return 32;
+    if (L <= 64) return 64;
+    return 128;
+}
+
+struct Timer {
+    bool on;
+    hipStream_t s;
+    std::vector<hipEvent_t> ev;
+    Timer(bool o, hipStream_t st) : on(o), s(st) {}
+    void mark() {
+        if (!on) return;
+        hipEvent_t e;
+        EVQ_HIP(hipEventCreate(&e));
+        EVQ_HIP(hipEventRecord(e, s));
+        ev.push_back(e);
+    }
+    double ms(size_t a, size_t b) {
+        if (!on || b >= ev.size()) return 0.0;
+        float m = 0.f;
+        EVQ_HIP(hipEventSynchronize(ev[b]));
+        EVQ_HIP(hipEventElapsedTime(&m, ev[a], ev[b]));
+        return m;
+    }
+    ~Timer() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+uint32_t read_u32(const uint32_t* d, Mailbox& mb, hipStream_t s) {
+    EVQ_HIP(hipMemcpyAsync(mb.h + 3, d, 4, hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipStreamSynchronize(s));
+    return mb.h[3];
+}
+
+struct Reduced {
+    uint32_t nU = 0;
+    uint64_t nRE = 0;
+    uint32_t* cid_of = nullptr;
+    uint32_t* ulist = nullptr;
+    uint32_t* rptr = nullptr;
+    void* recs = nullptr;
+};
+
+// Builds U's compact ids and the reduced relaxation CSR.  all_vertices: U = V.
+Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup, bool all_vertices, const Window& W,
+                     uint32_t NLW, Arena& ar, Mailbox& mb, hipStream_t s) {
+    Reduced r;
+    const uint32_t V = g.V;
+    uint32_t* flag = ar.alloc<uint32_t>((uint64_t)V + 1);
+    uint32_t* cidx = ar.alloc<uint32_t>((uint64_t)V + 1);
+    if (all_vertices) EVQ_LAUNCH("compact_flag", k_flag_all, grid_for(V, 256), 256, s, V, flag);
+    else EVQ_LAUNCH("compact_flag", k_flag_unstable, grid_for(V, 256), 256, s, rcap, rcup, V, flag);
+    scan_exclusive(flag, cidx, V, cidx + V, s, ar);
+    r.nU = read_u32(cidx + V, mb, s);
+    r.cid_of = ar.alloc<uint32_t>(V);
+    if (r.nU == 0) {
+        fill_u32(r.cid_of, V, kNone, s);
+        return r;
+    }
+    r.ulist = ar.alloc<uint32_t>(r.nU);
+    EVQ_LAUNCH("compact_assign", k_assign, grid_for(V, 256), 256, s, flag, cidx, V, r.cid_of, r.ulist);
+    ar.release(flag);
+    ar.release(cidx);
+
+    uint32_t* tcnt = ar.alloc<uint32_t>((uint64_t)r.nU + 1);
+    uint32_t* toff = ar.alloc<uint32_t>((uint64_t)r.nU + 1);
+    EVQ_LAUNCH("compact_task_count", k_task_count, grid_for(r.nU, 256), 256, s, r.ulist, r.nU, g.row_ptr, tcnt);
+    scan_exclusive(tcnt, toff, r.nU, toff + r.nU, s, ar);
+    const uint32_t T = read_u32(toff + r.nU, mb, s);
+    uint64_t* tasks = ar.alloc<uint64_t>(T);
+    EVQ_LAUNCH("compact_task_fill", k_task_fill, grid_for(r.nU, 256), 256, s, tcnt, toff, r.nU, tasks);
+
+    CompactArgs a;
+    a.row_ptr = g.row_ptr;
+    a.row_split = g.row_split;
+    a.col = g.col;
+    a.wgt = g.wgt;
+    a.mask = g.mask;
+    a.ulist = r.ulist;
+    a.cid_of = r.cid_of;
+    a.tasks = tasks;
+    a.n_tasks = T;
+    a.b = W.b;
+    a.L = W.L;
+    uint32_t* ecnt = ar.alloc<uint32_t>((uint64_t)T + 1);
+    uint32_t* eoff = ar.alloc<uint32_t>((uint64_t)T + 1);
+    const uint32_t blocks = grid_for(T, kBlock / 64, 32768);
+#define EVQ_REDUCE(MW_, NLW_)                                                                                      \
+    do {                                                                                                           \
+        EVQ_LAUNCH("compact_count", (k_reduce_rows<MW_, NLW_, false>), blocks, kBlock, s, a, ecnt,                \
+                   (const uint32_t*)nullptr, (Rec<NLW_>*)nullptr);                                                 \
+        scan_exclusive(ecnt, eoff, T, eoff + T, s, ar);                                                            \
+        r.nRE = read_u32(eoff + T, mb, s);                                                                         \
+        r.recs = ar.raw((r.nRE + 1) * sizeof(Rec<NLW_>));                                                          \
+        EVQ_LAUNCH("compact_fill", (k_reduce_rows<MW_, NLW_, true>), blocks, kBlock, s, a, ecnt,                  \
+                   (const uint32_t*)eoff, (Rec<NLW_>*)r.recs);                                                     \
+    } while (0)
+    if (g.MW == 1) EVQ_REDUCE(1, 1);
+    else if (NLW == 1) EVQ_REDUCE(2, 1);
+    else EVQ_REDUCE(2, 2);
+#undef EVQ_REDUCE
+    r.rptr = ar.alloc<uint32_t>((uint64_t)r.nU + 1);
+    EVQ_LAUNCH("compact_rptr", k_rptr, grid_for((uint64_t)r.nU + 1, 256), 256, s, toff, eoff, r.nU, r.rptr);
+    ar.release(tcnt);
+    ar.release(tasks);
+    ar.release(ecnt);
+    ar.release(eoff);
+    ar.release(toff);
+    return r;
+}
+
+template <int A, int LG, bool ST>
+uint64_t relax_loop(RelaxArgs ra, uint32_t& stamp, Mailbox& mb, hipStream_t s, uint64_t max_iters) {
+    int p = 0;
+    uint64_t iters = 0;
+    for (;;) {
+        EVQ_HIP(hipMemcpyAsync(mb.h, dev_small_cnt(ra.cnt, p), 4, hipMemcpyDeviceToHost, s));
+        EVQ_HIP(hipStreamSynchronize(s));
+        const uint32_t n = mb.h[0];
+        if (n == 0) break;
+        if (++iters > max_iters) fail(EVQ_ENOCONV, "snapshot relaxation exceeded its iteration cap");
+        ++stamp;
+        const uint32_t waves = (n + Lanes<LG>::G - 1) / Lanes<LG>::G;
+        EVQ_LAUNCH("relax", (k_relax<A, LG, ST>), grid_for(waves, kBlock / 64, 32768), kBlock, s, ra, p, stamp);
+        EVQ_LAUNCH("relax_reset", k_reset_pair, 1, 64, s, ra.cnt, p);
+        p ^= 1;
+    }
+    if (p != 0) EVQ_LAUNCH("relax_reset", k_reset_pair, 1, 64, s, ra.cnt, p);
+    return iters;
+}
+
+template <int A, int LG, bool ST>
+void relax_phase(const Graph& g, const Window& W, const uint32_t* rcap, const Reduced& red, uint32_t* X, bool plain,
+                 uint32_t source, const SolveWorkspace& ws, Arena& ar, uint32_t& stamp, Mailbox& mb, hipStream_t s,
+                 QueryOut& qo) {
+    using T = Lanes<LG>;
+    const uint64_t cap = (uint64_t)red.nU + red.nRE / kRelaxChunk + 64;
+    RelaxArgs ra;
+    ra.rptr = red.rptr;
+    ra.recs = red.recs;
+    ra.X = X;
+    ra.stamps = ws.stamps;
+    ra.tasks[0] = ar.alloc<uint64_t>(cap);
+    ra.tasks[1] = ar.alloc<uint64_t>(cap);
+    ra.cnt = ws.cnt;
+    ra.stats = ws.stats;
+    ++stamp;
+    if (plain) {
+        EVQ_LAUNCH("relax_xinit", k_xinit_plain<LG>, grid_for((uint64_t)red.nU * LG, 256 * 4), 256, s, g.V, source,
+                   Alg<A>::unreached, Alg<A>::at_source, X);
+        EVQ_LAUNCH("relax_seed", k_push_one, 1, 64, s, ra, source, stamp);
+    } else {
+        EVQ_LAUNCH("relax_xinit", k_xinit<LG>, grid_for((uint64_t)red.nU * LG, 256 * 4), 256, s, red.ulist, red.nU,
+                   rcap, X);
+        if (g.n_partial) {
+            const uint32_t waves = (uint32_t)((g.n_partial + T::G - 1) / T::G);
+#define EVQ_SEED(MW_)                                                                                             \
+    EVQ_LAUNCH("relax_seed", (k_relax_seed<A, MW_, LG, ST>), grid_for(waves, kBlock / 64, 32768), kBlock, s, ra,  \
+               g.p_src, g.p_eid, (uint32_t)g.n_partial, g.col, g.wgt, g.mask, red.cid_of, rcap, W.b, W.L, stamp)
+            if (g.MW == 1) EVQ_SEED(1);
+            else EVQ_SEED(2);
+#undef EVQ_SEED
+        }
+    }
+    qo.st.iters_relax = relax_loop<A, LG, ST>(ra, stamp, mb, s, (uint64_t)g.V + 2);
+}
+
+template <int A>
+void relax_dispatch(uint32_t LG, bool st, const Graph& g, const Window& W, const uint32_t* rcap, const Reduced& red,
+                    uint32_t* X, bool plain, uint32_t source, const SolveWorkspace& ws, Arena& ar, uint32_t& stamp,
+                    Mailbox& mb, hipStream_t s, QueryOut& qo) {
+#define EVQ_RX(LG_)                                                                                  \
+    case LG_:                                                                                        \
+        if (st) relax_phase<A, LG_, true>(g, W, rcap, red, X, plain, source, ws, ar, stamp, mb, s, qo); \
+        else relax_phase<A, LG_, false>(g, W, rcap, red, X, plain, source, ws, ar, stamp, mb, s, qo);   \
+        break;
+    switch (LG) {
+        EVQ_RX(8)
+        EVQ_RX(16)
+        EVQ_RX(32)
+        EVQ_RX(64)
+        EVQ_RX(128)
+    }
+#undef EVQ_RX
+}
+
+void writeback(uint32_t LG, uint32_t V, uint32_t L, const uint32_t* cid_of, const uint32_t* rcap, const uint32_t* X,
+               uint32_t* out, hipStream_t s) {
+    const uint32_t G = LG >= 64 ? 1 : 64 / LG;
+    const uint64_t waves = ((uint64_t)V + G - 1) / G;
+    const uint32_t blocks = grid_for(waves, kBlock / 64, 65535);
+#define EVQ_WB(LG_) \
+    case LG_: EVQ_LAUNCH("writeback", k_writeback<LG_>, blocks, kBlock, s, V, L, cid_of, rcap, X, out); break;
+    switch (LG) {
+        EVQ_WB(8)
+        EVQ_WB(16)
+        EVQ_WB(32)
+        EVQ_WB(64)
+        EVQ_WB(128)
+    }
+#undef EVQ_WB
+}
+
+uint64_t read_stat(const unsigned long long* d, int i, hipStream_t s) {
+    unsigned long long h = 0;
+    EVQ_HIP(hipMemcpyAsync(&h, d + i, sizeof(h), hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+}  // namespace
+
+void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values,
+               uint32_t* d_rcap_out, uint32_t* d_rcup_out, bool bounds_only, QueryOut& qo, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    init_mempool(g.device);
+    Arena ar(s);
+    Mailbox mb(8);
+    const bool st = qo.want_stats;
+    Timer tm(st, s);
+    tm.mark();
+    SolveWorkspace ws = make_solve_workspace(g, ar, s);
+    uint32_t* rcap = d_rcap_out ? d_rcap_out : ar.alloc<uint32_t>(g.V);
+    uint32_t* rcup = d_rcup_out ? d_rcup_out : ar.alloc<uint32_t>(g.V);
+    uint32_t stamp = 0;
+    qo.st.iters_cap = solve_cap(g, algo, W, source, rcap, ws, stamp, mb, s, st);
+    tm.mark();
+    EVQ_HIP(hipMemcpyAsync(rcup, rcap, (uint64_t)g.V * 4, hipMemcpyDeviceToDevice, s));
+    if (st) qo.st.edges_cap = read_stat(ws.stats, 0, s);
+    qo.st.iters_cup = solve_cup(g, algo, W, rcup, ws, stamp, mb, s, st);
+    tm.mark();
+    if (st) qo.st.edges_cup = read_stat(ws.stats, 0, s) - qo.st.edges_cap;
+    if (bounds_only) {
+        EVQ_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    const uint32_t LG = pick_lg(W.L);
+    const uint32_t NLW = LG > 64 ? 2 : 1;
+    Reduced red = reduce_graph(g, rcap, rcup, false, W, NLW, ar, mb, s);
+    tm.mark();
+    uint32_t* X = nullptr;
+    if (red.nU) {
+        X = ar.alloc<uint32_t>((uint64_t)red.nU * LG);
+        switch (algo) {
+        case EVQ_SSSP: relax_dispatch<EVQ_SSSP>(LG, st, g, W, rcap, red, X, false, source, ws, ar, stamp, mb, s, qo); break;
+        case EVQ_BFS: relax_dispatch<EVQ_BFS>(LG, st, g, W, rcap, red, X, false, source, ws, ar, stamp, mb, s, qo); break;
+        case EVQ_SSWP: relax_dispatch<EVQ_SSWP>(LG, st, g, W, rcap, red, X, false, source, ws, ar, stamp, mb, s, qo); break;
+        default: relax_dispatch<EVQ_SSNP>(LG, st, g, W, rcap, red, X, false, source, ws, ar, stamp, mb, s, qo); break;
+        }
+    }
+    tm.mark();
+    writeback(LG, g.V, W.L, red.cid_of, rcap, X, d_values, s);
+    tm.mark();
+    if (st) {
+        qo.st.ms_cap = tm.ms(0, 1);
+        qo.st.ms_cup = tm.ms(1, 2);
+        qo.st.ms_compact = tm.ms(2, 3);
+        qo.st.ms_relax = tm.ms(3, 4);
+        qo.st.ms_writeback = tm.ms(4, 5);
+        qo.st.n_unstable = red.nU;
+        qo.st.n_relax_edges = red.nRE;
+        qo.st.edge_visits_relax = read_stat(ws.stats, 1, s);
+        qo.st.lane_relaxations = read_stat(ws.stats, 2, s);
+        qo.st.n_seed_edges = read_stat(ws.stats, 3, s);
+        EVQ_HIP(hipStreamSynchronize(s));
+        qo.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+}
+
+void run_plain(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values, QueryOut& qo,
+               hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    init_mempool(g.device);
+    Arena ar(s);
+    Mailbox mb(8);
+    const bool st = qo.want_stats;
+    Timer tm(st, s);
+    tm.mark();
+    SolveWorkspace ws = make_solve_workspace(g, ar, s);
+    uint32_t stamp = 0;
+    const uint32_t LG = pick_lg(W.L);
+    const uint32_t NLW = LG > 64 ? 2 : 1;
+    Reduced red = reduce_graph(g, nullptr, nullptr, true, W, NLW, ar, mb, s);
+    tm.mark();
+    uint32_t* X = ar.alloc<uint32_t>((uint64_t)g.V * LG);
+    switch (algo) {
+    case EVQ_SSSP: relax_dispatch<EVQ_SSSP>(LG, st, g, W, nullptr, red, X, true, source, ws, ar, stamp, mb, s, qo); break;
+    case EVQ_BFS: relax_dispatch<EVQ_BFS>(LG, st, g, W, nullptr, red, X, true, source, ws, ar, stamp, mb, s, qo); break;
+    case EVQ_SSWP: relax_dispatch<EVQ_SSWP>(LG, st, g, W, nullptr, red, X, true, source, ws, ar, stamp, mb, s, qo); break;
+    default: relax_dispatch<EVQ_SSNP>(LG, st, g, W, nullptr, red, X, true, source, ws, ar, stamp, mb, s, qo); break;
+    }
+    tm.mark();
+    writeback(LG, g.V, W.L, red.cid_of, nullptr, X, d_values, s);
+    tm.mark();
+    if (st) {
+        qo.st.ms_compact = tm.ms(0, 1);
+        qo.st.ms_relax = tm.ms(1, 2);
+        qo.st.ms_writeback = tm.ms(2, 3);
+        qo.st.n_unstable = red.nU;
+        qo.st.n_relax_edges = red.nRE;
+        qo.st.edge_visits_relax = read_stat(ws.stats, 1, s);
+        qo.st.lane_relaxations = read_stat(ws.stats, 2, s);
+        EVQ_HIP(hipStreamSynchronize(s));
+        qo.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+}
+
+}  // namespace evq

@@ -1,0 +1,277 @@
+// Host runtime pieces shared by every entry point: errors, device memory,
+// pinned mailboxes, optional per-kernel timing, a fill kernel and a
+// device-wide exclusive scan.
+#include <algorithm>
+#include <map>
+#include <mutex>
+
+#include "evq_internal.h"
+
+namespace evq {
+
+// ------------------------------------------------------------------ errors
+
+[[noreturn]] void fail(evq_status code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    evq_status c = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? EVQ_ENOMEM : EVQ_EDEVICE;
+    fail(c, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ memory
+
+void* dev_alloc(uint64_t bytes) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(EVQ_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+
+void dev_free(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+void init_mempool(int device) {
+    static std::mutex mu;
+    static std::vector<int> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (std::find(done.begin(), done.end(), device) != done.end()) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    (void)hipGetLastError();
+    done.push_back(device);
+}
+
+void* Arena::raw(uint64_t bytes) {
+    void* p = nullptr;
+    uint64_t n = (bytes + 255) & ~uint64_t(255);
+    if (n == 0) n = 256;
+    hipError_t e = hipMallocAsync(&p, n, s_);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(EVQ_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    ptrs_.push_back(p);
+    bytes_ += n;
+    return p;
+}
+
+void Arena::release(void* p) {
+    auto it = std::find(ptrs_.begin(), ptrs_.end(), p);
+    if (it == ptrs_.end()) return;
+    (void)hipFreeAsync(p, s_);
+    ptrs_.erase(it);
+}
+
+Arena::~Arena() {
+    for (void* p : ptrs_) (void)hipFreeAsync(p, s_);
+}
+
+Mailbox::Mailbox(size_t n) {
+    void* p = nullptr;
+    EVQ_HIP(hipHostMalloc(&p, n * sizeof(uint32_t), hipHostMallocDefault));
+    h = static_cast<uint32_t*>(p);
+    std::memset(h, 0, n * sizeof(uint32_t));
+}
+
+Mailbox::~Mailbox() {
+    if (h) (void)hipHostFree(h);
+}
+
+// ------------------------------------------------------------------ timing
+
+namespace {
+struct TimingState {
+    std::mutex mu;
+    bool on = false;
+    struct Rec {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::map<std::string, std::pair<uint64_t, double>> acc;
+};
+TimingState& ts() {
+    static TimingState t;
+    return t;
+}
+void drain_locked(TimingState& t) {
+    for (auto& r : t.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto& x = t.acc[r.name];
+            x.first += 1;
+            x.second += ms;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    t.pending.clear();
+    (void)hipGetLastError();
+}
+}  // namespace
+
+bool timing_on() { return ts().on; }
+
+TimingScope::TimingScope(const char* n, hipStream_t st) : name(n), s(st) {
+    if (!ts().on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        a = b = nullptr;
+        return;
+    }
+    (void)hipEventRecord(a, s);
+}
+
+TimingScope::~TimingScope() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    TimingState& t = ts();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.pending.push_back({name, a, b});
+    if (t.pending.size() > 4096) drain_locked(t);
+}
+
+void post_launch(const char* name) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(EVQ_EDEVICE, std::string("launch of ") + name + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ fill
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+    if (n == 0) return;
+    EVQ_LAUNCH("fill_u32", k_fill_u32, grid_for(n, 256 * 8, 8192), 256, s, p, n, v);
+}
+
+// ------------------------------------------------------------------ scan
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+// Block-wide exclusive scan of one value per thread; returns the block total in *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t wsum[kScanBlock / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kScanBlock / 64; ++w) {
+        uint32_t x = wsum[w];
+        if (w < wave) before += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - v;
+}
+
+__global__ void k_scan_reduce(const uint32_t* __restrict__ in, uint64_t n, uint32_t* __restrict__ sums) {
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        uint64_t i = base + (uint64_t)r * kScanBlock + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    uint32_t tot;
+    (void)block_excl_scan(acc, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_apply(const uint32_t* in, uint32_t* out, uint64_t n, const uint32_t* __restrict__ offs,
+                             uint32_t* total) {
+    __shared__ uint32_t tile[kScanTile];
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        uint64_t i = base + (uint64_t)r * kScanBlock + threadIdx.x;
+        tile[r * kScanBlock + threadIdx.x] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kScanItems];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = acc;
+        acc += tile[threadIdx.x * kScanItems + k];
+    }
+    uint32_t tot;
+    uint32_t pre = block_excl_scan(acc, &tot);
+    uint32_t off = offs ? offs[blockIdx.x] : 0u;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = v[k] + pre + off;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        uint64_t i = base + (uint64_t)r * kScanBlock + threadIdx.x;
+        if (i < n) out[i] = tile[r * kScanBlock + threadIdx.x];
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
+}
+
+void scan_exclusive(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* d_total, hipStream_t s, Arena& ar) {
+    if (n == 0) {
+        if (d_total) fill_u32(d_total, 1, 0u, s);
+        return;
+    }
+    uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb > 0x7FFFFFFFull) fail(EVQ_ERANGE, "scan too large");
+    if (nb == 1) {
+        EVQ_LAUNCH("scan_apply", k_scan_apply, 1, kScanBlock, s, in, out, n, (const uint32_t*)nullptr, d_total);
+        return;
+    }
+    uint32_t* sums = ar.alloc<uint32_t>(nb);
+    EVQ_LAUNCH("scan_reduce", k_scan_reduce, (uint32_t)nb, kScanBlock, s, in, n, sums);
+    scan_exclusive(sums, sums, nb, nullptr, s, ar);
+    EVQ_LAUNCH("scan_apply", k_scan_apply, (uint32_t)nb, kScanBlock, s, in, out, n, (const uint32_t*)sums, d_total);
+    ar.release(sums);
+}
+
+}  // namespace evq
+
+// ------------------------------------------------------------------ timing ABI
+
+extern "C" void evq_timing_enable(int on) {
+    auto& t = evq::ts();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.on = on != 0;
+}
+
+extern "C" void evq_timing_reset(void) {
+    auto& t = evq::ts();
+    std::lock_guard<std::mutex> lk(t.mu);
+    evq::drain_locked(t);
+    t.acc.clear();
+}
+
+extern "C" int evq_timing_report(evq_kernel_time* out, int cap) {
+    auto& t = evq::ts();
+    std::lock_guard<std::mutex> lk(t.mu);
+    evq::drain_locked(t);
+    int i = 0;
+    for (auto& kv : t.acc) {
+        if (out && i < cap) {
+            std::memset(out[i].name, 0, sizeof(out[i].name));
+            std::strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+            out[i].launches = kv.second.first;
+            out[i].total_ms = kv.second.second;
+        }
+        ++i;
+    }
+    return i;
+}

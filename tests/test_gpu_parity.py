@@ -1,0 +1,233 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+Sizes span several tiles of every kernel and leave ragged tails; edge cases
+cover empty and degenerate inputs.  All values are uint32 and exact, so the
+tolerance is zero.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from fixtures import empty_batches_instance, instance_from, load_golden
+from gpu_util import assert_equal_values, gpu_bounds, gpu_values, oracle_triples, union_triples_from_export
+
+pytestmark = pytest.mark.gpu
+
+ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP]
+
+
+@pytest.fixture(scope="module")
+def evq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2502_10579_amd as m
+    return m
+
+
+def _graph(evq, inst):
+    return evq.Graph.from_instance(inst)
+
+
+# ------------------------------------------------------------------ K1: versioned graph
+
+
+def _check_export(g, inst):
+    ex = g.export()
+    K = inst.K
+    V = inst.num_vertices
+    rp = ex["row_ptr"].astype(np.int64)
+    assert rp[0] == 0 and rp[-1] == len(ex["col"]) and (np.diff(rp) >= 0).all()
+    assert ((ex["row_split"] >= rp[:-1]) & (ex["row_split"] <= rp[1:])).all()
+    full = (1 << K) - 1
+    # all-present edges first within each row, then the partial ones
+    for u in range(V):
+        for j in range(rp[u], rp[u + 1]):
+            m = int(ex["mask"][j, 0]) | ((int(ex["mask"][j, 1]) << 64) if ex["mask"].shape[1] == 2 else 0)
+            assert (m == full) == (j < ex["row_split"][u]), (u, j)
+    got = union_triples_from_export(ex, K)
+    want = oracle_triples(inst)
+    assert got == want
+    info = g.info
+    assert info["num_edges"] == len(want)
+    assert info["num_partial"] == sum(1 for m in want.values() if m != full)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_versioned_graph_small_config(evq, seed):
+    inst = synth.config_instance("small", seed=seed)
+    with _graph(evq, inst) as g:
+        _check_export(g, inst)
+
+
+@pytest.mark.parametrize("K", [1, 3, 63, 64, 65, 100, 128])
+def test_versioned_graph_mask_widths(evq, K):
+    inst = synth.random_instance(40, 300, K, 4, 4, 7, 100 + K)
+    with _graph(evq, inst) as g:
+        _check_export(g, inst)
+
+
+def test_versioned_graph_labels_fig7_fig8(evq):
+    for case in load_golden("p7_version_labels.json")["cases"]:
+        inst = instance_from(case)
+        with _graph(evq, inst) as g:
+            got = union_triples_from_export(g.export(), inst.K)
+        for k, lab in case["labels"].items():
+            t = tuple(int(x) for x in k.split(","))
+            assert got[t] == int(lab, 2), (case["name"], k)
+
+
+def test_versioned_graph_wide_ids_and_weights(evq):
+    # keys wider than 64 bits (32-bit weights) take the two-word sort path
+    rng = np.random.default_rng(5)
+    V = 70000
+    base = np.stack([rng.integers(0, V, 3000), rng.integers(0, V, 3000),
+                     rng.integers(1, 2**32 - 1, 3000, dtype=np.uint64)], 1).astype(np.uint32)
+    dels = [base[rng.choice(3000, 50, replace=False)] for _ in range(3)]
+    adds = [np.stack([rng.integers(0, V, 60), rng.integers(0, V, 60),
+                      rng.integers(1, 2**32 - 1, 60, dtype=np.uint64)], 1).astype(np.uint32) for _ in range(3)]
+    inst = synth.Instance(V, base, dels, adds)
+    with _graph(evq, inst) as g:
+        got = union_triples_from_export(g.export(), 3)
+    assert got == oracle_triples(inst)
+
+
+# ------------------------------------------------------------------ K2: bounds
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("win", [(0, 8), (2, 3), (5, 1)])
+def test_bounds_small_config(evq, algo, win):
+    inst = synth.config_instance("small", seed=3)
+    trip, bits = oracle.replay(inst)
+    b, L = win
+    rc_o, ru_o = oracle.bounds(inst.num_vertices, trip, bits, algo, 0, b, L)
+    with _graph(evq, inst) as g:
+        rc, ru = gpu_bounds(g, algo, 0, b, L)
+    assert np.array_equal(rc, rc_o)
+    assert np.array_equal(ru, ru_o)
+
+
+# ------------------------------------------------------------------ full method
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_query_small_config(evq, algo, seed):
+    inst = synth.config_instance("small", seed=seed)
+    trip, bits = oracle.replay(inst)
+    want = oracle.window_values(inst, algo, 0, 0, inst.K, replayed=(trip, bits))
+    with _graph(evq, inst) as g:
+        got = gpu_values(g, algo, 0, 0, inst.K)
+        plain = gpu_values(g, algo, 0, 0, inst.K, plain=True)
+    assert_equal_values(got, want, f"algo {algo} seed {seed}")
+    assert_equal_values(plain, want, f"plain algo {algo} seed {seed}")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_query_small_config_all_seeds_sssp_from_hub(evq, algo):
+    # the sources of the small config: vertex 0 (the R-MAT hub) over seeds 6..20
+    for seed in range(6, 21):
+        inst = synth.config_instance("small", seed=seed)
+        want = oracle.window_values(inst, algo, 0, 0, inst.K)
+        with _graph(evq, inst) as g:
+            got = gpu_values(g, algo, 0, 0, inst.K)
+        assert_equal_values(got, want, f"algo {algo} seed {seed}")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("K,b,L", [(20, 3, 17), (40, 0, 40), (64, 0, 64), (70, 2, 64), (100, 0, 100),
+                                   (128, 0, 128), (128, 27, 100), (128, 60, 9), (12, 11, 1)])
+def test_query_lane_layouts(evq, algo, K, b, L):
+    inst = synth.rmat_instance(11, 12000, K, 12, 12, wmin=1, wmax=30, seed=K + b)
+    src = synth.pick_sources(inst, 1, seed=K)[0]
+    want = oracle.window_values(inst, algo, src, b, L)
+    with _graph(evq, inst) as g:
+        got = gpu_values(g, algo, src, b, L)
+        plain = gpu_values(g, algo, src, b, L, plain=True)
+    assert_equal_values(got, want, f"algo {algo} K {K} window [{b},{b + L})")
+    assert_equal_values(plain, want, f"plain algo {algo} K {K} window [{b},{b + L})")
+
+
+def test_worked_example(evq):
+    gd = load_golden("p6_worked_example.json")
+    inst = instance_from(gd)
+    with _graph(evq, inst) as g:
+        rc, ru = gpu_bounds(g, oracle.SSSP, 0, 0, 2)
+        vals = gpu_values(g, oracle.SSSP, 0, 0, 2)
+    assert rc.tolist() == gd["expect"]["r_cap"]
+    assert ru.tolist() == gd["expect"]["r_cup"]
+    assert vals.tolist() == gd["expect"]["values"]
+
+
+# ------------------------------------------------------------------ edge cases
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_empty_batches_all_stable(evq, algo):
+    inst = empty_batches_instance(synth.config_instance("small", seed=7))
+    want = oracle.window_values(inst, algo, 0, 0, inst.K)
+    with _graph(evq, inst) as g:
+        got, st = gpu_values(g, algo, 0, 0, inst.K, stats=True)
+    assert_equal_values(got, want)
+    assert st["n_unstable"] == 0
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_tiny_and_degenerate_graphs(evq, algo):
+    cases = [
+        synth.Instance(1, np.zeros((0, 3), np.uint32), [np.zeros((0, 3), np.uint32)],
+                       [np.zeros((0, 3), np.uint32)]),
+        synth.Instance(1, np.array([[0, 0, 5]], np.uint32), [np.zeros((0, 3), np.uint32)] * 2,
+                       [np.zeros((0, 3), np.uint32)] * 2),
+        # every edge deleted in the first batch
+        synth.Instance(3, np.array([[0, 1, 2], [1, 2, 2]], np.uint32),
+                       [np.array([[0, 1, 2], [1, 2, 2]], np.uint32)], [np.zeros((0, 3), np.uint32)]),
+        # source without out-edges
+        synth.Instance(4, np.array([[1, 2, 3], [2, 0, 4]], np.uint32), [np.zeros((0, 3), np.uint32)] * 3,
+                       [np.array([[3, 1, 1]], np.uint32), np.zeros((0, 3), np.uint32),
+                        np.zeros((0, 3), np.uint32)]),
+    ]
+    for ci, inst in enumerate(cases):
+        want = oracle.window_values(inst, algo, 0, 0, inst.K)
+        with _graph(evq, inst) as g:
+            got = gpu_values(g, algo, 0, 0, inst.K)
+        assert_equal_values(got, want, f"case {ci}")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_random_multigraphs(evq, algo):
+    for seed in range(12):
+        rng = np.random.default_rng(seed)
+        V = int(rng.integers(2, 300))
+        K = int(rng.choice([1, 2, 5, 33, 64, 65, 128]))
+        inst = synth.random_instance(V, int(rng.integers(0, 4 * V)), K, int(rng.integers(0, 6)),
+                                     int(rng.integers(0, 6)), int(rng.choice([1, 3, 50])), seed)
+        b = int(rng.integers(0, K))
+        L = int(rng.integers(1, K - b + 1))
+        s = int(rng.integers(0, V))
+        want = oracle.window_values(inst, algo, s, b, L)
+        with _graph(evq, inst) as g:
+            got = gpu_values(g, algo, s, b, L)
+        assert_equal_values(got, want, f"seed {seed} V {V} K {K} [{b},{b + L}) s {s}")
+
+
+def test_invalid_arguments_return_codes(evq):
+    inst = synth.config_instance("small", seed=1)
+    with _graph(evq, inst) as g:
+        for args in [(0, 4096, 0, 8), (0, 0, 0, 9), (0, 0, 8, 1), (0, 0, 3, 0)]:
+            with pytest.raises(evq.EvqError) as ei:
+                g.query(*args)
+            assert ei.value.status == evq.EVQ_ERANGE
+        with pytest.raises(evq.EvqError) as ei:
+            g.query(7, 0, 0, 8)
+        assert ei.value.status == evq.EVQ_EINVAL
+
+
+def test_determinism_repeat(evq):
+    inst = synth.config_instance("small", seed=2)
+    with _graph(evq, inst) as g:
+        a = gpu_values(g, oracle.SSSP, 0, 0, 8)
+        for _ in range(3):
+            assert np.array_equal(a, gpu_values(g, oracle.SSSP, 0, 0, 8))
