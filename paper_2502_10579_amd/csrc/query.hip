@@ -26,14 +26,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr uint32_t kRowChunk = 1024;   // union-row edges per compaction task
-constexpr uint32_t kRelaxChunk = 64;   // reduced-subgraph edges per relaxation task
+constexpr uint32_t kRelaxChunk = 8;    // reduced-subgraph edges per relaxation task
 
-__global__ void k_reset_pair(FrontierCounters* c, int p) {
-    if (threadIdx.x == 0) {
-        c->small[p] = 0;
-        c->big[p] = 0;
-    }
-}
 
 template <int NLW>
 struct Rec {
@@ -199,22 +193,12 @@ struct RelaxArgs {
     const uint32_t* rptr;
     const void* recs;
     uint32_t* X;
-    uint32_t* stamps;
-    uint64_t* tasks[2];
+    uint32_t* bitmap;  // next-frontier bits over compact ids
+    uint64_t* tasks;   // (chunk << 32 | compact id), rewritten by each compaction
     FrontierCounters* cnt;
     unsigned long long* stats;  // [1] edge visits, [2] lane relaxations, [3] seed edges
+    uint32_t nU;
 };
-
-// Push the group leaders' vertices (compact ids) as relaxation tasks.
-__device__ __forceinline__ void push_task(const RelaxArgs& r, uint32_t c, bool want, uint32_t stamp, int np) {
-    bool fresh = claim(r.stamps, c, want, stamp);
-    uint32_t nch = 0;
-    if (fresh) {
-        uint32_t deg = r.rptr[c + 1] - r.rptr[c];
-        nch = (deg + kRelaxChunk - 1) / kRelaxChunk;
-    }
-    wave_append_tasks(nch, c, r.tasks[np], &r.cnt->small[np]);
-}
 
 template <int LG>
 __device__ __forceinline__ bool group_any(bool x) {
@@ -224,16 +208,6 @@ __device__ __forceinline__ bool group_any(bool x) {
     return ((bal >> (g * LG)) & low_mask(LG)) != 0;
 }
 
-template <int LG>
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        uint32_t o = __shfl_xor(v, d, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
 template <bool ST>
 __device__ __forceinline__ void add_stat(unsigned long long* p, uint32_t v) {
     if (!ST) return;
@@ -241,8 +215,54 @@ __device__ __forceinline__ void add_stat(unsigned long long* p, uint32_t v) {
     if (lane_id() == 0 && s) atomicAdd(p, (unsigned long long)s);
 }
 
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bitmap of improved compact ids -> relaxation tasks of parity p, one task per
+// kRelaxChunk reduced-subgraph edges of each improved vertex.
+__global__ void __launch_bounds__(kBlock) k_relax_compact(RelaxArgs r, int p, int first) {
+    if (!first && r.cnt->packed[p ^ 1] == 0ull) return;
+    __shared__ uint32_t buf[kBlock / 64][64 * 32];
+    const uint32_t nwords = (r.nU + 31) >> 5;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t nw = gridDim.x * (kBlock / 64);
+    for (uint32_t wb = gw * 64; wb < nwords; wb += nw * 64) {
+        const uint32_t wi = wb + lane;
+        uint32_t word = 0;
+        if (wi < nwords) {
+            word = r.bitmap[wi];
+            if (word) r.bitmap[wi] = 0;
+        }
+        const uint32_t pc = (uint32_t)__popc(word);
+        const uint32_t incl = wave_incl_scan(pc);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        uint32_t k = incl - pc;
+        for (uint32_t m = word; m; m &= m - 1) buf[wave][k++] = wi * 32 + (uint32_t)__builtin_ctz(m);
+        wave_lds_sync();
+        for (uint32_t s0 = 0; s0 < tot; s0 += 64) {
+            const uint32_t j = s0 + lane;
+            uint32_t c = 0, deg = 0;
+            if (j < tot) {
+                c = buf[wave][j];
+                deg = r.rptr[c + 1] - r.rptr[c];
+            }
+            const uint32_t nt = (deg + kRelaxChunk - 1) / kRelaxChunk;
+            uint32_t item, edge;
+            wave_reserve2(nt, deg, &r.cnt->packed[p], item, edge);
+            for (uint32_t q = 0; q < nt; ++q) r.tasks[item + q] = ((uint64_t)q << 32) | c;
+        }
+        wave_lds_sync();
+    }
+}
+
 // Seeding pass (the parfor over the reduced addition batches in Algorithm 2):
 // each window-partial edge u -> v with v in U improves v's lanes from R_cap[u].
+// Lanes first test one partial edge each; the survivors are then applied with
+// one LG-lane group per edge.
 template <int A, int MW, int LG, bool ST>
 __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32_t* __restrict__ p_src,
                                                        const uint32_t* __restrict__ p_eid, uint32_t n_partial,
@@ -250,105 +270,128 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
                                                        const uint32_t* __restrict__ wgt,
                                                        const uint64_t* __restrict__ mask,
                                                        const uint32_t* __restrict__ cid_of,
-                                                       const uint32_t* __restrict__ rcap, uint32_t b, uint32_t L,
-                                                       uint32_t stamp) {
+                                                       const uint32_t* __restrict__ rcap, uint32_t b, uint32_t L) {
     using T = Lanes<LG>;
-    const int lane = lane_id();
-    const int g = LG >= 64 ? 0 : lane / LG;
-    const int i0 = LG >= 64 ? lane : lane % LG;
+    const uint32_t lane = lane_id();
+    const int g = LG >= 64 ? 0 : (int)lane / LG;
+    const int i0 = LG >= 64 ? (int)lane : (int)lane % LG;
     const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint32_t nw = gridDim.x * (kBlock / 64);
-    for (uint32_t qb = gw * T::G; qb < n_partial; qb += nw * T::G) {
-        uint32_t q = qb + g;
+    for (uint32_t qb = gw * 64; qb < n_partial; qb += nw * 64) {
+        const uint32_t q = qb + lane;
         bool act = q < n_partial;
         uint32_t cv = 0, cand = 0;
         uint64_t lanes[T::NLW];
+#pragma unroll
+        for (int j = 0; j < T::NLW; ++j) lanes[j] = 0;
         if (act) {
-            uint32_t e = p_eid[q];
+            const uint32_t e = p_eid[q];
             cv = cid_of[col[e]];
             act = cv != kNone;
             if (act) {
                 edge_lanes<MW, T::NLW>(mask, e, false, b, L, lanes);
                 act = lanes_partial<T::NLW>(lanes, L);
-                cand = Alg<A>::extend(rcap[p_src[q]], wgt[e]);
+                if (act) cand = Alg<A>::extend(rcap[p_src[q]], wgt[e]);
             }
         }
-        add_stat<ST>(&r.stats[3], (act && i0 == 0) ? 1u : 0u);
-        bool imp = false;
-#pragma unroll
-        for (int s = 0; s < T::SPL; ++s) {
-            const int i = i0 + 64 * s;
-            bool bit = act && ((lanes[s] >> (i & 63)) & 1ull);
-            if (bit) {
-                uint32_t* p = &r.X[(uint64_t)cv * T::S + i];
-                if (Alg<A>::better(cand, *p)) {
-                    Alg<A>::improve_nr(p, cand);
-                    imp = true;
-                }
-            }
-        }
-        bool gi = group_any<LG>(imp);
-        push_task(r, cv, gi && i0 == 0, stamp, 0);
-    }
-}
-
-template <int A, int LG, bool ST>
-__global__ void __launch_bounds__(kBlock) k_relax(RelaxArgs r, int p, uint32_t stamp) {
-    using T = Lanes<LG>;
-    const uint32_t n = r.cnt->small[p];
-    const uint64_t* __restrict__ tasks = r.tasks[p];
-    const Rec<T::NLW>* __restrict__ recs = static_cast<const Rec<T::NLW>*>(r.recs);
-    const int lane = lane_id();
-    const int g = LG >= 64 ? 0 : lane / LG;
-    const int i0 = LG >= 64 ? lane : lane % LG;
-    const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const uint32_t nw = gridDim.x * (kBlock / 64);
-    for (uint32_t tb = gw * T::G; tb < n; tb += nw * T::G) {
-        uint32_t ti = tb + g;
-        bool tact = ti < n;
-        uint32_t c = 0, e0 = 0, e1 = 0;
-        if (tact) {
-            uint64_t tk = tasks[ti];
-            if (T::G == 1) tk = ((uint64_t)uniform((uint32_t)(tk >> 32)) << 32) | uniform((uint32_t)tk);
-            c = (uint32_t)tk;
-            uint32_t ch = (uint32_t)(tk >> 32);
-            uint32_t rb = r.rptr[c], re = r.rptr[c + 1];
-            e0 = rb + ch * kRelaxChunk;
-            e1 = e0 + kRelaxChunk < re ? e0 + kRelaxChunk : re;
-        }
-        uint32_t xu[T::SPL];
-#pragma unroll
-        for (int s = 0; s < T::SPL; ++s) xu[s] = tact ? r.X[(uint64_t)c * T::S + i0 + 64 * s] : Alg<A>::unreached;
-        const uint32_t ne = e1 - e0;
-        const uint32_t maxne = T::G == 1 ? ne : wave_max<LG>(ne);
-        uint32_t lanes_done = 0;
-        for (uint32_t k = 0; k < maxne; ++k) {
-            bool ea = k < ne;
-            Rec<T::NLW> rec;
-            if (ea) rec = recs[e0 + k];
-            else {
-                rec.dst = 0;
-                rec.w = 0;
-#pragma unroll
-                for (int j = 0; j < T::NLW; ++j) rec.lanes[j] = 0;
-            }
+        uint64_t bal = __ballot(act);
+        add_stat<ST>(&r.stats[3], lane == 0 ? (uint32_t)__popcll(bal) : 0u);
+        while (bal) {
+            // group g takes the g-th remaining survivor
+            uint64_t rest = bal;
+            for (int k = 0; k < g && rest; ++k) rest &= rest - 1;
+            const bool has = rest != 0;
+            const int src = has ? __ffsll((unsigned long long)rest) - 1 : 0;
+            const uint32_t gcv = (uint32_t)__shfl((int)cv, src, 64);
+            const uint32_t gcand = (uint32_t)__shfl((int)cand, src, 64);
             bool imp = false;
 #pragma unroll
             for (int s = 0; s < T::SPL; ++s) {
+                const uint64_t lw = ((uint64_t)(uint32_t)__shfl((int)(lanes[s] >> 32), src, 64) << 32) |
+                                    (uint32_t)__shfl((int)(uint32_t)lanes[s], src, 64);
                 const int i = i0 + 64 * s;
-                bool bit = ea && ((rec.lanes[s] >> (i & 63)) & 1ull);
-                if (bit) {
-                    ++lanes_done;
-                    uint32_t cand = Alg<A>::extend(xu[s], rec.w);
-                    uint32_t* p = &r.X[(uint64_t)rec.dst * T::S + i];
-                    if (Alg<A>::better(cand, *p)) {
-                        Alg<A>::improve_nr(p, cand);
+                if (has && ((lw >> (i & 63)) & 1ull)) {
+                    uint32_t* px = &r.X[(uint64_t)gcv * T::S + i];
+                    if (Alg<A>::better(gcand, *px)) {
+                        Alg<A>::improve_nr(px, gcand);
                         imp = true;
                     }
                 }
             }
-            bool gi = group_any<LG>(imp);
-            push_task(r, rec.dst, gi && i0 == 0, stamp, p ^ 1);
+            if (group_any<LG>(imp) && i0 == 0) mark(r.bitmap, gcv);
+            for (int k = 0; k < T::G && bal; ++k) bal &= bal - 1;
+        }
+    }
+}
+
+// One iteration of Algorithm 2's loop over the snapshot-oblivious frontier.
+// Each LG-lane group takes one task (<= kRelaxChunk edges of one vertex);
+// the task's edge records and destination rows are loaded before any update.
+template <int A, int LG, bool ST>
+__global__ void __launch_bounds__(kBlock) k_relax(RelaxArgs r, int p, uint32_t* slot) {
+    using T = Lanes<LG>;
+    const unsigned long long cx = expand_prologue(r.cnt, p, slot);
+    const uint32_t n = items_of(cx);
+    if (n == 0) return;
+    const uint64_t* __restrict__ tasks = r.tasks;
+    const Rec<T::NLW>* __restrict__ recs = static_cast<const Rec<T::NLW>*>(r.recs);
+    const uint32_t lane = lane_id();
+    const int g = LG >= 64 ? 0 : (int)lane / LG;
+    const int i0 = LG >= 64 ? (int)lane : (int)lane % LG;
+    const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t nw = gridDim.x * (kBlock / 64);
+    for (uint32_t tb = gw * T::G; tb < n; tb += nw * T::G) {
+        const uint32_t ti = tb + g;
+        uint32_t c = 0, e0 = 0, ne = 0;
+        if (ti < n) {
+            uint64_t tk = tasks[ti];
+            if (T::G == 1) tk = ((uint64_t)uniform((uint32_t)(tk >> 32)) << 32) | uniform((uint32_t)tk);
+            c = (uint32_t)tk;
+            const uint32_t rb = r.rptr[c], re = r.rptr[c + 1];
+            e0 = rb + (uint32_t)(tk >> 32) * kRelaxChunk;
+            ne = re - e0 < kRelaxChunk ? re - e0 : kRelaxChunk;
+        }
+        uint32_t xu[T::SPL];
+#pragma unroll
+        for (int s = 0; s < T::SPL; ++s) xu[s] = ne ? r.X[(uint64_t)c * T::S + i0 + 64 * s] : Alg<A>::unreached;
+        Rec<T::NLW> rec[kRelaxChunk];
+        uint32_t cur[kRelaxChunk][T::SPL];
+        uint32_t lanes_done = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kRelaxChunk; ++k) {
+            if (k < ne) {
+                rec[k] = recs[e0 + k];
+            } else {
+                rec[k].dst = 0;
+                rec[k].w = 0;
+#pragma unroll
+                for (int j = 0; j < T::NLW; ++j) rec[k].lanes[j] = 0;
+            }
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kRelaxChunk; ++k)
+#pragma unroll
+            for (int s = 0; s < T::SPL; ++s) {
+                const int i = i0 + 64 * s;
+                const bool bit = (rec[k].lanes[s] >> (i & 63)) & 1ull;
+                cur[k][s] = bit ? r.X[(uint64_t)rec[k].dst * T::S + i] : Alg<A>::unreached;
+            }
+#pragma unroll
+        for (uint32_t k = 0; k < kRelaxChunk; ++k) {
+            bool imp = false;
+#pragma unroll
+            for (int s = 0; s < T::SPL; ++s) {
+                const int i = i0 + 64 * s;
+                if ((rec[k].lanes[s] >> (i & 63)) & 1ull) {
+                    ++lanes_done;
+                    const uint32_t cand = Alg<A>::extend(xu[s], rec[k].w);
+                    if (Alg<A>::better(cand, cur[k][s])) {
+                        Alg<A>::improve_nr(&r.X[(uint64_t)rec[k].dst * T::S + i], cand);
+                        imp = true;
+                    }
+                }
+            }
+            if (group_any<LG>(imp) && i0 == 0) mark(r.bitmap, rec[k].dst);
         }
         if (ST) {
             add_stat<true>(&r.stats[1], i0 == 0 ? ne : 0u);
@@ -375,32 +418,45 @@ __global__ void k_xinit_plain(uint32_t V, uint32_t source, uint32_t unreached, u
         X[k] = (k / LG) == source ? at_source : unreached;
 }
 
-__global__ void k_push_one(RelaxArgs r, uint32_t c, uint32_t stamp) {
-    if (threadIdx.x >= 64) return;
-    push_task(r, c, lane_id() == 0, stamp, 0);
+__global__ void k_mark_one(uint32_t* bitmap, uint32_t c) {
+    if (threadIdx.x == 0) bitmap[c >> 5] |= 1u << (c & 31);
 }
 
-// values[v * L + i]: one LG-lane group per vertex.
-template <int LG>
-__global__ void __launch_bounds__(kBlock) k_writeback(uint32_t V, uint32_t L, const uint32_t* __restrict__ cid_of,
-                                                      const uint32_t* __restrict__ rcap,
-                                                      const uint32_t* __restrict__ X, uint32_t* __restrict__ out) {
-    using T = Lanes<LG>;
-    const int lane = lane_id();
-    const int g = LG >= 64 ? 0 : lane / LG;
-    const int i0 = LG >= 64 ? lane : lane % LG;
-    const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
-    const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
-    for (uint64_t vb = gw * T::G; vb < V; vb += nw * T::G) {
-        uint64_t v = vb + g;
-        if (v >= V) continue;
-        uint32_t c = cid_of ? cid_of[v] : kNone;
-        uint32_t base = rcap ? rcap[v] : 0u;
-#pragma unroll
-        for (int s = 0; s < T::SPL; ++s) {
-            uint32_t i = i0 + 64 * s;
-            if (i < L) out[v * L + i] = c == kNone ? base : X[(uint64_t)c * T::S + i];
+// values[v * L + i], four values per lane (L % 4 == 0, 16-byte aligned rows).
+__global__ void __launch_bounds__(kBlock) k_writeback4(uint32_t V, uint32_t L, uint32_t S,
+                                                       const uint32_t* __restrict__ cid_of,
+                                                       const uint32_t* __restrict__ rcap,
+                                                       const uint32_t* __restrict__ X, uint32_t* __restrict__ out) {
+    const uint32_t Lq = L >> 2;
+    const uint32_t rows = kBlock / Lq;
+    const uint32_t r = threadIdx.x / Lq, j = threadIdx.x - r * Lq;
+    if (r >= rows) return;
+    uint4* __restrict__ o4 = reinterpret_cast<uint4*>(out);
+    const uint4* __restrict__ x4 = reinterpret_cast<const uint4*>(X);
+    for (uint64_t v = (uint64_t)blockIdx.x * rows + r; v < V; v += (uint64_t)gridDim.x * rows) {
+        const uint32_t c = cid_of ? cid_of[v] : kNone;
+        uint4 val;
+        if (c == kNone) {
+            const uint32_t b = rcap[v];
+            val = make_uint4(b, b, b, b);
+        } else {
+            val = x4[(uint64_t)c * (S >> 2) + j];
         }
+        o4[v * Lq + j] = val;
+    }
+}
+
+// values[v * L + i], one value per lane (any L).
+__global__ void __launch_bounds__(kBlock) k_writeback1(uint32_t V, uint32_t L, uint32_t S,
+                                                       const uint32_t* __restrict__ cid_of,
+                                                       const uint32_t* __restrict__ rcap,
+                                                       const uint32_t* __restrict__ X, uint32_t* __restrict__ out) {
+    const uint64_t n = (uint64_t)V * L;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t v = k / L;
+        const uint32_t i = (uint32_t)(k - v * L);
+        const uint32_t c = cid_of ? cid_of[v] : kNone;
+        out[k] = c == kNone ? rcap[v] : X[(uint64_t)c * S + i];
     }
 }
 
@@ -522,69 +578,52 @@ Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup,
 }
 
 template <int A, int LG, bool ST>
-uint64_t relax_loop(RelaxArgs ra, uint32_t& stamp, Mailbox& mb, hipStream_t s, uint64_t max_iters) {
-    int p = 0;
-    uint64_t iters = 0;
-    for (;;) {
-        EVQ_HIP(hipMemcpyAsync(mb.h, dev_small_cnt(ra.cnt, p), 4, hipMemcpyDeviceToHost, s));
-        EVQ_HIP(hipStreamSynchronize(s));
-        const uint32_t n = mb.h[0];
-        if (n == 0) break;
-        if (++iters > max_iters) fail(EVQ_ENOCONV, "snapshot relaxation exceeded its iteration cap");
-        ++stamp;
-        const uint32_t waves = (n + Lanes<LG>::G - 1) / Lanes<LG>::G;
-        EVQ_LAUNCH("relax", (k_relax<A, LG, ST>), grid_for(waves, kBlock / 64, 32768), kBlock, s, ra, p, stamp);
-        EVQ_LAUNCH("relax_reset", k_reset_pair, 1, 64, s, ra.cnt, p);
-        p ^= 1;
-    }
-    if (p != 0) EVQ_LAUNCH("relax_reset", k_reset_pair, 1, 64, s, ra.cnt, p);
-    return iters;
-}
-
-template <int A, int LG, bool ST>
 void relax_phase(const Graph& g, const Window& W, const uint32_t* rcap, const Reduced& red, uint32_t* X, bool plain,
-                 uint32_t source, const SolveWorkspace& ws, Arena& ar, uint32_t& stamp, Mailbox& mb, hipStream_t s,
-                 QueryOut& qo) {
+                 uint32_t source, Frontier& f, Arena& ar, hipStream_t s, QueryOut& qo) {
     using T = Lanes<LG>;
-    const uint64_t cap = (uint64_t)red.nU + red.nRE / kRelaxChunk + 64;
     RelaxArgs ra;
     ra.rptr = red.rptr;
     ra.recs = red.recs;
     ra.X = X;
-    ra.stamps = ws.stamps;
-    ra.tasks[0] = ar.alloc<uint64_t>(cap);
-    ra.tasks[1] = ar.alloc<uint64_t>(cap);
-    ra.cnt = ws.cnt;
-    ra.stats = ws.stats;
-    ++stamp;
+    ra.bitmap = f.bitmap;
+    ra.tasks = ar.alloc<uint64_t>((uint64_t)red.nU + red.nRE / kRelaxChunk + 64);
+    ra.cnt = f.cnt;
+    ra.stats = f.stats;
+    ra.nU = red.nU;
     if (plain) {
         EVQ_LAUNCH("relax_xinit", k_xinit_plain<LG>, grid_for((uint64_t)red.nU * LG, 256 * 4), 256, s, g.V, source,
                    Alg<A>::unreached, Alg<A>::at_source, X);
-        EVQ_LAUNCH("relax_seed", k_push_one, 1, 64, s, ra, source, stamp);
+        EVQ_LAUNCH("relax_seed", k_mark_one, 1, 64, s, f.bitmap, source);
     } else {
         EVQ_LAUNCH("relax_xinit", k_xinit<LG>, grid_for((uint64_t)red.nU * LG, 256 * 4), 256, s, red.ulist, red.nU,
                    rcap, X);
         if (g.n_partial) {
-            const uint32_t waves = (uint32_t)((g.n_partial + T::G - 1) / T::G);
+            const uint32_t waves = (uint32_t)((g.n_partial + 63) / 64);
 #define EVQ_SEED(MW_)                                                                                             \
-    EVQ_LAUNCH("relax_seed", (k_relax_seed<A, MW_, LG, ST>), grid_for(waves, kBlock / 64, 32768), kBlock, s, ra,  \
-               g.p_src, g.p_eid, (uint32_t)g.n_partial, g.col, g.wgt, g.mask, red.cid_of, rcap, W.b, W.L, stamp)
+    EVQ_LAUNCH("relax_seed", (k_relax_seed<A, MW_, LG, ST>), grid_for(waves, kBlock / 64, 8192), kBlock, s, ra,   \
+               g.p_src, g.p_eid, (uint32_t)g.n_partial, g.col, g.wgt, g.mask, red.cid_of, rcap, W.b, W.L)
             if (g.MW == 1) EVQ_SEED(1);
             else EVQ_SEED(2);
 #undef EVQ_SEED
         }
     }
-    qo.st.iters_relax = relax_loop<A, LG, ST>(ra, stamp, mb, s, (uint64_t)g.V + 2);
+    const uint32_t nwords = (red.nU + 31) >> 5;
+    const uint32_t cblocks = grid_for((nwords + 63) / 64, kBlock / 64, 4096);
+    const uint32_t rblocks = grid_for(((uint64_t)red.nU + red.nRE / kRelaxChunk + T::G - 1) / T::G, kBlock / 64, 4096);
+    auto issue = [&](uint64_t, int p, bool first, uint32_t* slot) {
+        EVQ_LAUNCH("relax_compact", k_relax_compact, cblocks, kBlock, s, ra, p, first ? 1 : 0);
+        EVQ_LAUNCH("relax", (k_relax<A, LG, ST>), rblocks, kBlock, s, ra, p, slot);
+    };
+    qo.st.iters_relax = drive_loop(issue, f.p, s, (uint64_t)g.V + 2, "snapshot relaxation");
 }
 
 template <int A>
 void relax_dispatch(uint32_t LG, bool st, const Graph& g, const Window& W, const uint32_t* rcap, const Reduced& red,
-                    uint32_t* X, bool plain, uint32_t source, const SolveWorkspace& ws, Arena& ar, uint32_t& stamp,
-                    Mailbox& mb, hipStream_t s, QueryOut& qo) {
-#define EVQ_RX(LG_)                                                                                  \
-    case LG_:                                                                                        \
-        if (st) relax_phase<A, LG_, true>(g, W, rcap, red, X, plain, source, ws, ar, stamp, mb, s, qo); \
-        else relax_phase<A, LG_, false>(g, W, rcap, red, X, plain, source, ws, ar, stamp, mb, s, qo);   \
+                    uint32_t* X, bool plain, uint32_t source, Frontier& f, Arena& ar, hipStream_t s, QueryOut& qo) {
+#define EVQ_RX(LG_)                                                                          \
+    case LG_:                                                                                \
+        if (st) relax_phase<A, LG_, true>(g, W, rcap, red, X, plain, source, f, ar, s, qo); \
+        else relax_phase<A, LG_, false>(g, W, rcap, red, X, plain, source, f, ar, s, qo);   \
         break;
     switch (LG) {
         EVQ_RX(8)
@@ -596,21 +635,27 @@ void relax_dispatch(uint32_t LG, bool st, const Graph& g, const Window& W, const
 #undef EVQ_RX
 }
 
+void relax_algo(uint32_t algo, uint32_t LG, bool st, const Graph& g, const Window& W, const uint32_t* rcap,
+                const Reduced& red, uint32_t* X, bool plain, uint32_t source, Frontier& f, Arena& ar, hipStream_t s,
+                QueryOut& qo) {
+    switch (algo) {
+    case EVQ_SSSP: relax_dispatch<EVQ_SSSP>(LG, st, g, W, rcap, red, X, plain, source, f, ar, s, qo); break;
+    case EVQ_BFS: relax_dispatch<EVQ_BFS>(LG, st, g, W, rcap, red, X, plain, source, f, ar, s, qo); break;
+    case EVQ_SSWP: relax_dispatch<EVQ_SSWP>(LG, st, g, W, rcap, red, X, plain, source, f, ar, s, qo); break;
+    default: relax_dispatch<EVQ_SSNP>(LG, st, g, W, rcap, red, X, plain, source, f, ar, s, qo); break;
+    }
+}
+
 void writeback(uint32_t LG, uint32_t V, uint32_t L, const uint32_t* cid_of, const uint32_t* rcap, const uint32_t* X,
                uint32_t* out, hipStream_t s) {
-    const uint32_t G = LG >= 64 ? 1 : 64 / LG;
-    const uint64_t waves = ((uint64_t)V + G - 1) / G;
-    const uint32_t blocks = grid_for(waves, kBlock / 64, 65535);
-#define EVQ_WB(LG_) \
-    case LG_: EVQ_LAUNCH("writeback", k_writeback<LG_>, blocks, kBlock, s, V, L, cid_of, rcap, X, out); break;
-    switch (LG) {
-        EVQ_WB(8)
-        EVQ_WB(16)
-        EVQ_WB(32)
-        EVQ_WB(64)
-        EVQ_WB(128)
+    const bool vec = (L % 4 == 0) && ((uintptr_t)out % 16 == 0);
+    if (vec) {
+        const uint32_t rows = kBlock / (L / 4);
+        EVQ_LAUNCH("writeback", k_writeback4, grid_for(V, rows, 65535), kBlock, s, V, L, LG, cid_of, rcap, X, out);
+    } else {
+        EVQ_LAUNCH("writeback", k_writeback1, grid_for((uint64_t)V * L, kBlock * 4, 65535), kBlock, s, V, L, LG,
+                   cid_of, rcap, X, out);
     }
-#undef EVQ_WB
 }
 
 uint64_t read_stat(const unsigned long long* d, int i, hipStream_t s) {
@@ -631,17 +676,16 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     const bool st = qo.want_stats;
     Timer tm(st, s);
     tm.mark();
-    SolveWorkspace ws = make_solve_workspace(g, ar, s);
+    Frontier f = make_frontier(g, ar, s);
     uint32_t* rcap = d_rcap_out ? d_rcap_out : ar.alloc<uint32_t>(g.V);
     uint32_t* rcup = d_rcup_out ? d_rcup_out : ar.alloc<uint32_t>(g.V);
-    uint32_t stamp = 0;
-    qo.st.iters_cap = solve_cap(g, algo, W, source, rcap, ws, stamp, mb, s, st);
+    qo.st.iters_cap = solve_cap(g, algo, W, source, rcap, f, s, st);
     tm.mark();
     EVQ_HIP(hipMemcpyAsync(rcup, rcap, (uint64_t)g.V * 4, hipMemcpyDeviceToDevice, s));
-    if (st) qo.st.edges_cap = read_stat(ws.stats, 0, s);
-    qo.st.iters_cup = solve_cup(g, algo, W, rcup, ws, stamp, mb, s, st);
+    if (st) qo.st.edges_cap = read_stat(f.stats, 0, s);
+    qo.st.iters_cup = solve_cup(g, algo, W, rcup, f, s, st);
     tm.mark();
-    if (st) qo.st.edges_cup = read_stat(ws.stats, 0, s) - qo.st.edges_cap;
+    if (st) qo.st.edges_cup = read_stat(f.stats, 0, s) - qo.st.edges_cap;
     if (bounds_only) {
         EVQ_HIP(hipStreamSynchronize(s));
         return;
@@ -653,12 +697,7 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     uint32_t* X = nullptr;
     if (red.nU) {
         X = ar.alloc<uint32_t>((uint64_t)red.nU * LG);
-        switch (algo) {
-        case EVQ_SSSP: relax_dispatch<EVQ_SSSP>(LG, st, g, W, rcap, red, X, false, source, ws, ar, stamp, mb, s, qo); break;
-        case EVQ_BFS: relax_dispatch<EVQ_BFS>(LG, st, g, W, rcap, red, X, false, source, ws, ar, stamp, mb, s, qo); break;
-        case EVQ_SSWP: relax_dispatch<EVQ_SSWP>(LG, st, g, W, rcap, red, X, false, source, ws, ar, stamp, mb, s, qo); break;
-        default: relax_dispatch<EVQ_SSNP>(LG, st, g, W, rcap, red, X, false, source, ws, ar, stamp, mb, s, qo); break;
-        }
+        relax_algo(algo, LG, st, g, W, rcap, red, X, false, source, f, ar, s, qo);
     }
     tm.mark();
     writeback(LG, g.V, W.L, red.cid_of, rcap, X, d_values, s);
@@ -671,9 +710,9 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
         qo.st.ms_writeback = tm.ms(4, 5);
         qo.st.n_unstable = red.nU;
         qo.st.n_relax_edges = red.nRE;
-        qo.st.edge_visits_relax = read_stat(ws.stats, 1, s);
-        qo.st.lane_relaxations = read_stat(ws.stats, 2, s);
-        qo.st.n_seed_edges = read_stat(ws.stats, 3, s);
+        qo.st.edge_visits_relax = read_stat(f.stats, 1, s);
+        qo.st.lane_relaxations = read_stat(f.stats, 2, s);
+        qo.st.n_seed_edges = read_stat(f.stats, 3, s);
         EVQ_HIP(hipStreamSynchronize(s));
         qo.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -688,19 +727,13 @@ void run_plain(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     const bool st = qo.want_stats;
     Timer tm(st, s);
     tm.mark();
-    SolveWorkspace ws = make_solve_workspace(g, ar, s);
-    uint32_t stamp = 0;
+    Frontier f = make_frontier(g, ar, s);
     const uint32_t LG = pick_lg(W.L);
     const uint32_t NLW = LG > 64 ? 2 : 1;
     Reduced red = reduce_graph(g, nullptr, nullptr, true, W, NLW, ar, mb, s);
     tm.mark();
     uint32_t* X = ar.alloc<uint32_t>((uint64_t)g.V * LG);
-    switch (algo) {
-    case EVQ_SSSP: relax_dispatch<EVQ_SSSP>(LG, st, g, W, nullptr, red, X, true, source, ws, ar, stamp, mb, s, qo); break;
-    case EVQ_BFS: relax_dispatch<EVQ_BFS>(LG, st, g, W, nullptr, red, X, true, source, ws, ar, stamp, mb, s, qo); break;
-    case EVQ_SSWP: relax_dispatch<EVQ_SSWP>(LG, st, g, W, nullptr, red, X, true, source, ws, ar, stamp, mb, s, qo); break;
-    default: relax_dispatch<EVQ_SSNP>(LG, st, g, W, nullptr, red, X, true, source, ws, ar, stamp, mb, s, qo); break;
-    }
+    relax_algo(algo, LG, st, g, W, nullptr, red, X, true, source, f, ar, s, qo);
     tm.mark();
     writeback(LG, g.V, W.L, red.cid_of, nullptr, X, d_values, s);
     tm.mark();
@@ -710,8 +743,8 @@ void run_plain(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
         qo.st.ms_writeback = tm.ms(2, 3);
         qo.st.n_unstable = red.nU;
         qo.st.n_relax_edges = red.nRE;
-        qo.st.edge_visits_relax = read_stat(ws.stats, 1, s);
-        qo.st.lane_relaxations = read_stat(ws.stats, 2, s);
+        qo.st.edge_visits_relax = read_stat(f.stats, 1, s);
+        qo.st.lane_relaxations = read_stat(f.stats, 2, s);
         EVQ_HIP(hipStreamSynchronize(s));
         qo.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }

@@ -5,7 +5,9 @@
 #include <map>
 #include <mutex>
 
-#include "evq_internal.h"
+#include <chrono>
+
+#include "frontier.h"
 
 namespace evq {
 
@@ -83,6 +85,42 @@ Mailbox::Mailbox(size_t n) {
 
 Mailbox::~Mailbox() {
     if (h) (void)hipHostFree(h);
+}
+
+// ------------------------------------------------------------------ host slots
+
+HostSlots::HostSlots() {
+    void* p = nullptr;
+    EVQ_HIP(hipHostMalloc(&p, kSlots * sizeof(uint32_t),
+                          hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable));
+    h_ = static_cast<uint32_t*>(p);
+    for (uint32_t i = 0; i < kSlots; ++i) h_[i] = kEmpty;
+    void* d = nullptr;
+    EVQ_HIP(hipHostGetDevicePointer(&d, p, 0));
+    d_ = static_cast<uint32_t*>(d);
+}
+
+HostSlots& HostSlots::get() {
+    thread_local HostSlots* hs = new HostSlots();  // lives as long as the thread
+    return *hs;
+}
+
+void wait_slot(volatile uint32_t* slot, hipStream_t s, const char* what) {
+    if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) != HostSlots::kEmpty) return;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint64_t spin = 1;; ++spin) {
+        if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) != HostSlots::kEmpty) return;
+        if ((spin & 255) != 0) continue;
+        const hipError_t e = hipStreamQuery(s);
+        if (e == hipSuccess) {
+            EVQ_HIP(hipStreamSynchronize(s));
+            if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) != HostSlots::kEmpty) return;
+            fail(EVQ_EDEVICE, std::string(what) + ": the stream drained without publishing a frontier size");
+        }
+        if (e != hipErrorNotReady) fail(EVQ_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(300))
+            fail(EVQ_EDEVICE, std::string(what) + ": no progress for 300 s");
+    }
 }
 
 // ------------------------------------------------------------------ timing

@@ -5,20 +5,39 @@
 // intersection result and first relaxes the window-partial edges, i.e. it adds
 // the edges missing from the intersection graph (Section 6.2).
 //
-// Each iteration expands the current frontier with uint32 atomicMin/atomicMax
-// and builds the next one with wave ballots (one counter atomic per wave).
-// Work split: a wave takes 64 frontier vertices of degree <= kBig and spreads
-// their edges over its lanes through a wave prefix sum; vertices of larger
-// degree are split into kChunk-edge tasks when pushed, one wave per task.
+// One iteration = two kernels:
+//   compaction  next-frontier bitmap -> vertex list fv[] with running edge
+//               offsets fo[] (vertices without edges are dropped);
+//   expansion   the frontier's edges, viewed as one range [0, T), are cut
+//               into equal contiguous slices, one per wave; a wave finds its
+//               first vertex with a 64-ary search over fo[] and then walks 64
+//               edges per step, each lane locating its edge's vertex with a
+//               binary search over 64 offsets held in registers.
+// Values improve with fire-and-forget uint32 atomicMin/atomicMax after a plain
+// read shows the candidate is better; improved vertices set their bit.
 #include "bounds.h"
 
 namespace evq {
 
 namespace {
 
-constexpr uint32_t kBig = 256;
-constexpr uint32_t kChunk = 256;
 constexpr int kBlock = 256;
+constexpr uint32_t kExpandBlocks = 2048;
+
+struct SolveArgs {
+    const uint32_t* row_ptr;
+    const uint32_t* row_split;
+    const uint32_t* col;
+    const uint32_t* wgt;
+    const uint64_t* mask;
+    uint32_t* R;
+    uint32_t* bitmap;
+    uint32_t* fv;  // frontier vertices
+    uint32_t* fo;  // their first edge offset in the frontier's edge range
+    FrontierCounters* cnt;
+    unsigned long long* stats;
+    uint32_t V;
+};
 
 // MODE: 0 = intersection over all K snapshots (only the all-present prefix of
 // each row), 1 = intersection over a sub-window, 2 = union.
@@ -42,126 +61,137 @@ __device__ __forceinline__ uint32_t row_end(const SolveArgs& a, uint32_t v) {
     return MODE == 0 ? a.row_split[v] : a.row_ptr[v + 1];
 }
 
-// Push the lanes' improved vertices into the next frontier (all lanes call).
-template <int MODE>
-__device__ __forceinline__ void push(const SolveArgs& a, uint32_t v, bool want, uint32_t stamp, int np) {
-    bool fresh = claim(a.stamps, v, want, stamp);
-    uint32_t deg = 0;
-    if (fresh) deg = row_end<MODE>(a, v) - a.row_ptr[v];
-    bool small = fresh && deg > 0 && deg <= kBig;
-    wave_append(small, v, a.list[np], &a.cnt->small[np]);
-    uint32_t nch = (fresh && deg > kBig) ? (deg + kChunk - 1) / kChunk : 0u;
-    wave_append_tasks(nch, v, a.big[np], &a.cnt->big[np]);
-}
-
 template <int A, int MODE, int MW>
-__device__ __forceinline__ bool relax(const SolveArgs& a, uint32_t e, uint32_t split, uint32_t x, const Mask<MW>& W,
-                                      bool act, uint32_t& v) {
-    v = 0;
-    if (!act) return false;
-    if (MODE != 0 && e >= split && !partial_in<MODE, MW>(a.mask, e, W)) return false;
-    v = a.col[e];
-    uint32_t cand = Alg<A>::extend(x, a.wgt[e]);
-    if (!Alg<A>::better(cand, a.R[v])) return false;
-    return Alg<A>::better(cand, Alg<A>::improve(&a.R[v], cand));
+__device__ __forceinline__ void relax(const SolveArgs& a, uint32_t e, uint32_t split, uint32_t x, const Mask<MW>& W) {
+    if (MODE != 0 && e >= split && !partial_in<MODE, MW>(a.mask, e, W)) return;
+    const uint32_t v = a.col[e];
+    const uint32_t cand = Alg<A>::extend(x, a.wgt[e]);
+    if (!Alg<A>::better(cand, a.R[v])) return;
+    Alg<A>::improve_nr(&a.R[v], cand);
+    mark(a.bitmap, v);
 }
 
 template <bool ST>
-__device__ __forceinline__ void count_visits(const SolveArgs& a, bool act) {
+__device__ __forceinline__ void count_visits(const SolveArgs& a, uint32_t n) {
     if (!ST) return;
-    uint64_t bal = __ballot(act);
-    if (lane_id() == 0 && bal) atomicAdd(&a.stats[0], (unsigned long long)__popcll(bal));
+    uint32_t s = wave_sum(n);
+    if (lane_id() == 0 && s) atomicAdd(&a.stats[0], (unsigned long long)s);
 }
 
-template <int A, int MODE, int MW, bool ST>
-__global__ void __launch_bounds__(kBlock) k_expand_small(SolveArgs a, Mask<MW> W, int p, uint32_t stamp) {
-    const uint32_t n = a.cnt->small[p];
-    const uint32_t* __restrict__ cur = a.list[p];
-    const int lane = lane_id();
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bitmap -> (fv, fo) of parity p, clearing the bits it reads.  A wave takes 64
+// bitmap words, stages their vertex ids in LDS, then reads the degrees of up
+// to 64 vertices at a time.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_compact_frontier(SolveArgs a, int p, int first) {
+    if (!first && a.cnt->packed[p ^ 1] == 0ull) return;  // the previous expansion set no bits
+    __shared__ uint32_t buf[kBlock / 64][64 * 32];
+    const uint32_t nwords = (a.V + 31) >> 5;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint32_t nw = gridDim.x * (kBlock / 64);
-    for (uint32_t chunk = gw; chunk * 64u < n; chunk += nw) {
-        uint32_t idx = chunk * 64u + lane;
-        bool valid = idx < n;
-        uint32_t u = valid ? cur[idx] : 0u;
-        uint32_t beg = 0, split = 0, deg = 0, x = 0;
-        if (valid) {
-            beg = a.row_ptr[u];
-            split = a.row_split[u];
-            deg = row_end<MODE>(a, u) - beg;
-            x = a.R[u];
+    for (uint32_t wb = gw * 64; wb < nwords; wb += nw * 64) {
+        const uint32_t wi = wb + lane;
+        uint32_t word = 0;
+        if (wi < nwords) {
+            word = a.bitmap[wi];
+            if (word) a.bitmap[wi] = 0;
         }
-        uint32_t incl = wave_incl_scan(deg);
-        uint32_t excl = incl - deg;
-        uint32_t total = __shfl(incl, 63, 64);
-        for (uint32_t base = 0; base < total; base += 64) {
-            uint32_t t = base + lane;
-            bool act = t < total;
-            int j = 0;
-#pragma unroll
-            for (int step = 32; step >= 1; step >>= 1) {
-                uint32_t o = __shfl(excl, j + step, 64);
-                if (o <= t) j += step;
+        const uint32_t pc = (uint32_t)__popc(word);
+        const uint32_t incl = wave_incl_scan(pc);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        uint32_t k = incl - pc;
+        for (uint32_t m = word; m; m &= m - 1) buf[wave][k++] = wi * 32 + (uint32_t)__builtin_ctz(m);
+        wave_lds_sync();
+        for (uint32_t s0 = 0; s0 < tot; s0 += 64) {
+            const uint32_t j = s0 + lane;
+            uint32_t v = 0, deg = 0;
+            if (j < tot) {
+                v = buf[wave][j];
+                deg = row_end<MODE>(a, v) - a.row_ptr[v];
             }
-            uint32_t e = __shfl(beg, j, 64) + (t - __shfl(excl, j, 64));
-            uint32_t sp = __shfl(split, j, 64);
-            uint32_t xs = __shfl(x, j, 64);
-            count_visits<ST>(a, act);
-            uint32_t v;
-            bool want = relax<A, MODE, MW>(a, e, sp, xs, W, act, v);
-            push<MODE>(a, v, want, stamp, p ^ 1);
+            const uint32_t keep = deg > 0 ? 1u : 0u;
+            uint32_t item, edge;
+            wave_reserve2(keep, deg, &a.cnt->packed[p], item, edge);
+            if (keep) {
+                a.fv[item] = v;
+                a.fo[item] = edge;
+            }
         }
+        wave_lds_sync();
     }
 }
 
 template <int A, int MODE, int MW, bool ST>
-__global__ void __launch_bounds__(kBlock) k_expand_big(SolveArgs a, Mask<MW> W, int p, uint32_t stamp) {
-    const uint32_t n = a.cnt->big[p];
-    const uint64_t* __restrict__ tasks = a.big[p];
-    const int lane = lane_id();
-    const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const uint32_t nw = gridDim.x * (kBlock / 64);
-    for (uint32_t t = gw; t < n; t += nw) {
-        uint64_t tk = tasks[t];
-        uint32_t u = (uint32_t)tk, c = (uint32_t)(tk >> 32);
-        uint32_t beg = a.row_ptr[u], split = a.row_split[u];
-        uint32_t end = row_end<MODE>(a, u);
-        uint32_t e0 = beg + c * kChunk;
-        uint32_t e1 = e0 + kChunk < end ? e0 + kChunk : end;
-        uint32_t x = a.R[u];
-        for (uint32_t e = e0; e < e1; e += 64) {
-            bool act = e + lane < e1;
-            count_visits<ST>(a, act);
-            uint32_t v;
-            bool want = relax<A, MODE, MW>(a, e + lane, split, x, W, act, v);
-            push<MODE>(a, v, want, stamp, p ^ 1);
+__global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int p, uint32_t* slot) {
+    const unsigned long long cx = expand_prologue(a.cnt, p, slot);
+    const uint32_t n = items_of(cx), T = edges_of(cx);
+    if (T == 0) return;
+    const uint32_t lane = lane_id();
+    const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
+    const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
+    uint64_t Rw = (T + nw - 1) / nw;
+    Rw = (Rw + 63) & ~63ull;
+    const uint64_t a0 = gw * Rw;
+    if (a0 >= T) return;
+    const uint32_t a1 = (uint32_t)(a0 + Rw < T ? a0 + Rw : T);
+    count_visits<ST>(a, lane == 0 ? a1 - (uint32_t)a0 : 0u);
+    uint32_t cur = wave_search(a.fo, n, (uint32_t)a0);
+    for (uint32_t base = (uint32_t)a0; base < a1; base += 64) {
+        const uint32_t idx = cur + lane;
+        const uint32_t off = idx < n ? a.fo[idx] : 0xFFFFFFFFu;
+        uint32_t rb = 0, sp = 0, xv = 0;
+        if (off <= base + 63) {  // only the vertices this step can touch
+            const uint32_t v = a.fv[idx];
+            rb = a.row_ptr[v];
+            sp = a.row_split[v];
+            xv = a.R[v];
         }
+        const uint32_t t = base + lane;
+        int j = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const uint32_t o = __shfl(off, j + step, 64);
+            if (o <= t) j += step;
+        }
+        const uint32_t e = __shfl(rb, j, 64) + (t - __shfl(off, j, 64));
+        const uint32_t spj = __shfl(sp, j, 64);
+        const uint32_t xs = __shfl(xv, j, 64);
+        if (t < a1) relax<A, MODE, MW>(a, e, spj, xs, W);
+        // next step starts at the owner of base + 64: one of cur .. cur + 64,
+        // since every listed vertex has at least one edge
+        const uint32_t nb = base + 64;
+        const uint32_t have = (uint32_t)__popcll(__ballot(off <= nb));
+        uint32_t adv = have - 1;
+        if (have == 64 && cur + 64 < n && a.fo[cur + 64] <= nb) adv = 64;
+        cur += adv;
     }
 }
 
 // Start of a solve from one source vertex.
-template <int MODE>
-__global__ void k_seed_source(SolveArgs a, uint32_t source, uint32_t at_source, uint32_t stamp) {
-    if (threadIdx.x >= 64) return;
-    bool want = lane_id() == 0;
-    if (want) a.R[source] = at_source;
-    push<MODE>(a, source, want, stamp, 0);
+__global__ void k_seed_source(uint32_t* R, uint32_t* bitmap, uint32_t source, uint32_t at_source) {
+    if (threadIdx.x == 0) {
+        R[source] = at_source;
+        bitmap[source >> 5] |= 1u << (source & 31);
+    }
 }
 
 // Union solve, first step: relax every edge present in some but not all
 // snapshots of the window, from the values in R (the intersection result).
 template <int A, int MW, bool ST>
 __global__ void __launch_bounds__(kBlock) k_seed_partial(SolveArgs a, Mask<MW> W, const uint32_t* __restrict__ p_src,
-                                                         const uint32_t* __restrict__ p_eid, uint32_t n_partial,
-                                                         uint32_t stamp) {
+                                                         const uint32_t* __restrict__ p_eid, uint32_t n_partial) {
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t base = blockIdx.x * kBlock; base < n_partial; base += stride) {
-        uint32_t q = base + threadIdx.x;
-        bool act = q < n_partial;
-        uint32_t e = 0, u = 0;
-        if (act) {
-            e = p_eid[q];
-            u = p_src[q];
+        const uint32_t q = base + threadIdx.x;
+        bool act = false;
+        if (q < n_partial) {
+            const uint32_t e = p_eid[q];
             Mask<MW> m = load_mask<MW>(a.mask, e);
             bool any = false, all = true;
 #pragma unroll
@@ -170,137 +200,38 @@ __global__ void __launch_bounds__(kBlock) k_seed_partial(SolveArgs a, Mask<MW> W
                 all &= (m.w[j] & W.w[j]) == W.w[j];
             }
             act = any && !all;
+            if (act) {
+                const uint32_t v = a.col[e];
+                const uint32_t cand = Alg<A>::extend(a.R[p_src[q]], a.wgt[e]);
+                if (Alg<A>::better(cand, a.R[v])) {
+                    Alg<A>::improve_nr(&a.R[v], cand);
+                    mark(a.bitmap, v);
+                }
+            }
         }
-        count_visits<ST>(a, act);
-        uint32_t v = 0;
-        bool want = false;
-        if (act) {
-            v = a.col[e];
-            uint32_t cand = Alg<A>::extend(a.R[u], a.wgt[e]);
-            want = Alg<A>::better(cand, a.R[v]) && Alg<A>::better(cand, Alg<A>::improve(&a.R[v], cand));
-        }
-        push<2>(a, v, want, stamp, 0);
+        count_visits<ST>(a, act ? 1u : 0u);
     }
-}
-
-__global__ void k_reset_counters(FrontierCounters* c, int p) {
-    if (threadIdx.x == 0) {
-        c->small[p] = 0;
-        c->big[p] = 0;
-    }
-}
-
-__global__ void k_init_query(FrontierCounters* c, unsigned long long* stats, int nstats) {
-    if (threadIdx.x == 0) {
-        c->small[0] = c->small[1] = 0;
-        c->big[0] = c->big[1] = 0;
-    }
-    if ((int)threadIdx.x < nstats) stats[threadIdx.x] = 0;
 }
 
 template <int A, int MODE, int MW, bool ST>
-struct Loop {
-    static uint64_t run(const SolveArgs& a, const Mask<MW>& W, uint32_t& stamp, Mailbox& mb, hipStream_t s,
-                        uint64_t max_iters) {
-        int p = 0;
-        uint64_t iters = 0;
-        for (;;) {
-            uint32_t ns = mb.h[0], nb = mb.h[1];
-            if (ns + nb == 0) break;
-            if (++iters > max_iters) fail(EVQ_ENOCONV, "bound solve exceeded its iteration cap");
-            ++stamp;
-            if (ns) {
-                uint32_t blocks = grid_for(ns, 64 * (kBlock / 64), 16384);
-                EVQ_LAUNCH("solve_expand_small", (k_expand_small<A, MODE, MW, ST>), blocks, kBlock, s, a, W, p, stamp);
-            }
-            if (nb) {
-                uint32_t blocks = grid_for(nb, kBlock / 64, 16384);
-                EVQ_LAUNCH("solve_expand_big", (k_expand_big<A, MODE, MW, ST>), blocks, kBlock, s, a, W, p, stamp);
-            }
-            EVQ_LAUNCH("solve_reset", k_reset_counters, 1, 64, s, a.cnt, p);
-            p ^= 1;
-            EVQ_HIP(hipMemcpyAsync(mb.h, dev_small_cnt(a.cnt, p), 4, hipMemcpyDeviceToHost, s));
-            EVQ_HIP(hipMemcpyAsync(mb.h + 1, dev_big_cnt(a.cnt, p), 4, hipMemcpyDeviceToHost, s));
-            EVQ_HIP(hipStreamSynchronize(s));
-        }
-        // the final (empty) list sits at parity p; move it to parity 0 for the next phase
-        if (p != 0) EVQ_LAUNCH("solve_reset", k_reset_counters, 1, 64, s, a.cnt, p);
-        return iters;
-    }
-};
-
-template <int A, int MW, bool ST>
-uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, SolveArgs a, uint32_t& stamp, Mailbox& mb,
-                     hipStream_t s) {
-    Mask<MW> Wm;
-    for (int j = 0; j < MW; ++j) Wm.w[j] = W.w[j];
-    fill_u32(a.R, g.V, Alg<A>::unreached, s);
-    ++stamp;
-    if (W.full) EVQ_LAUNCH("solve_seed_source", k_seed_source<0>, 1, 64, s, a, source, Alg<A>::at_source, stamp);
-    else EVQ_LAUNCH("solve_seed_source", k_seed_source<1>, 1, 64, s, a, source, Alg<A>::at_source, stamp);
-    EVQ_HIP(hipMemcpyAsync(mb.h, dev_small_cnt(a.cnt, 0), 4, hipMemcpyDeviceToHost, s));
-    EVQ_HIP(hipMemcpyAsync(mb.h + 1, dev_big_cnt(a.cnt, 0), 4, hipMemcpyDeviceToHost, s));
-    EVQ_HIP(hipStreamSynchronize(s));
-    if (W.full) return Loop<A, 0, MW, ST>::run(a, Wm, stamp, mb, s, (uint64_t)g.V + 2);
-    return Loop<A, 1, MW, ST>::run(a, Wm, stamp, mb, s, (uint64_t)g.V + 2);
+uint64_t frontier_loop(SolveArgs a, const Mask<MW>& W, Frontier& f, hipStream_t s, uint64_t max_iters) {
+    const uint32_t nwords = (a.V + 31) >> 5;
+    const uint32_t cblocks = grid_for((nwords + 63) / 64, kBlock / 64, 4096);
+    auto issue = [&](uint64_t, int p, bool first, uint32_t* slot) {
+        EVQ_LAUNCH("solve_compact", k_compact_frontier<MODE>, cblocks, kBlock, s, a, p, first ? 1 : 0);
+        EVQ_LAUNCH("solve_expand", (k_expand<A, MODE, MW, ST>), kExpandBlocks, kBlock, s, a, W, p, slot);
+    };
+    return drive_loop(issue, f.p, s, max_iters, "bound solve");
 }
 
-template <int A, int MW, bool ST>
-uint64_t solve_cup_t(const Graph& g, const Window& W, SolveArgs a, uint32_t& stamp, Mailbox& mb, hipStream_t s) {
-    Mask<MW> Wm;
-    for (int j = 0; j < MW; ++j) Wm.w[j] = W.w[j];
-    ++stamp;
-    if (g.n_partial) {
-        uint32_t blocks = grid_for(g.n_partial, kBlock, 16384);
-        EVQ_LAUNCH("solve_seed_partial", (k_seed_partial<A, MW, ST>), blocks, kBlock, s, a, Wm, g.p_src, g.p_eid,
-                   (uint32_t)g.n_partial, stamp);
-    }
-    EVQ_HIP(hipMemcpyAsync(mb.h, dev_small_cnt(a.cnt, 0), 4, hipMemcpyDeviceToHost, s));
-    EVQ_HIP(hipMemcpyAsync(mb.h + 1, dev_big_cnt(a.cnt, 0), 4, hipMemcpyDeviceToHost, s));
-    EVQ_HIP(hipStreamSynchronize(s));
-    return Loop<A, 2, MW, ST>::run(a, Wm, stamp, mb, s, (uint64_t)g.V + 2);
+template <int MW>
+Mask<MW> window_mask(const Window& W) {
+    Mask<MW> m;
+    for (int j = 0; j < MW; ++j) m.w[j] = W.w[j];
+    return m;
 }
 
-template <int MW, bool ST>
-uint64_t dispatch_cap(uint32_t algo, const Graph& g, const Window& W, uint32_t source, const SolveArgs& a,
-                      uint32_t& stamp, Mailbox& mb, hipStream_t s) {
-    switch (algo) {
-    case EVQ_SSSP: return solve_cap_t<EVQ_SSSP, MW, ST>(g, W, source, a, stamp, mb, s);
-    case EVQ_BFS: return solve_cap_t<EVQ_BFS, MW, ST>(g, W, source, a, stamp, mb, s);
-    case EVQ_SSWP: return solve_cap_t<EVQ_SSWP, MW, ST>(g, W, source, a, stamp, mb, s);
-    default: return solve_cap_t<EVQ_SSNP, MW, ST>(g, W, source, a, stamp, mb, s);
-    }
-}
-
-template <int MW, bool ST>
-uint64_t dispatch_cup(uint32_t algo, const Graph& g, const Window& W, const SolveArgs& a, uint32_t& stamp,
-                      Mailbox& mb, hipStream_t s) {
-    switch (algo) {
-    case EVQ_SSSP: return solve_cup_t<EVQ_SSSP, MW, ST>(g, W, a, stamp, mb, s);
-    case EVQ_BFS: return solve_cup_t<EVQ_BFS, MW, ST>(g, W, a, stamp, mb, s);
-    case EVQ_SSWP: return solve_cup_t<EVQ_SSWP, MW, ST>(g, W, a, stamp, mb, s);
-    default: return solve_cup_t<EVQ_SSNP, MW, ST>(g, W, a, stamp, mb, s);
-    }
-}
-
-}  // namespace
-
-SolveWorkspace make_solve_workspace(const Graph& g, Arena& ar, hipStream_t s) {
-    SolveWorkspace w;
-    w.stamps = ar.alloc<uint32_t>(g.V);
-    w.list[0] = ar.alloc<uint32_t>(g.V);
-    w.list[1] = ar.alloc<uint32_t>(g.V);
-    w.cap_big = g.E / kChunk + g.E / (kBig + 1) + 64;
-    w.big[0] = ar.alloc<uint64_t>(w.cap_big);
-    w.big[1] = ar.alloc<uint64_t>(w.cap_big);
-    w.cnt = ar.alloc<FrontierCounters>(1);
-    w.stats = ar.alloc<unsigned long long>(8);
-    fill_u32(w.stamps, g.V, 0u, s);
-    EVQ_LAUNCH("query_init", k_init_query, 1, 64, s, w.cnt, w.stats, 8);
-    return w;
-}
-
-SolveArgs solve_args(const Graph& g, const SolveWorkspace& w, uint32_t* R) {
+SolveArgs make_args(const Graph& g, const Frontier& f, uint32_t* R) {
     SolveArgs a;
     a.row_ptr = g.row_ptr;
     a.row_split = g.row_split;
@@ -308,32 +239,87 @@ SolveArgs solve_args(const Graph& g, const SolveWorkspace& w, uint32_t* R) {
     a.wgt = g.wgt;
     a.mask = g.mask;
     a.R = R;
-    a.stamps = w.stamps;
-    a.list[0] = w.list[0];
-    a.list[1] = w.list[1];
-    a.big[0] = w.big[0];
-    a.big[1] = w.big[1];
-    a.cnt = w.cnt;
-    a.stats = w.stats;
+    a.bitmap = f.bitmap;
+    a.fv = f.fv;
+    a.fo = f.fo;
+    a.cnt = f.cnt;
+    a.stats = f.stats;
+    a.V = g.V;
     return a;
 }
 
-uint64_t solve_cap(const Graph& g, uint32_t algo, const Window& W, uint32_t source, uint32_t* R,
-                   const SolveWorkspace& w, uint32_t& stamp, Mailbox& mb, hipStream_t s, bool stats) {
-    SolveArgs a = solve_args(g, w, R);
-    if (g.MW == 1) return stats ? dispatch_cap<1, true>(algo, g, W, source, a, stamp, mb, s)
-                                : dispatch_cap<1, false>(algo, g, W, source, a, stamp, mb, s);
-    return stats ? dispatch_cap<2, true>(algo, g, W, source, a, stamp, mb, s)
-                 : dispatch_cap<2, false>(algo, g, W, source, a, stamp, mb, s);
+template <int A, int MW, bool ST>
+uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t* R, Frontier& f, hipStream_t s) {
+    SolveArgs a = make_args(g, f, R);
+    fill_u32(R, g.V, Alg<A>::unreached, s);
+    EVQ_LAUNCH("solve_seed_source", k_seed_source, 1, 64, s, R, f.bitmap, source, Alg<A>::at_source);
+    if (W.full) return frontier_loop<A, 0, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
+    return frontier_loop<A, 1, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
 }
 
-uint64_t solve_cup(const Graph& g, uint32_t algo, const Window& W, uint32_t* R, const SolveWorkspace& w,
-                   uint32_t& stamp, Mailbox& mb, hipStream_t s, bool stats) {
-    SolveArgs a = solve_args(g, w, R);
-    if (g.MW == 1) return stats ? dispatch_cup<1, true>(algo, g, W, a, stamp, mb, s)
-                                : dispatch_cup<1, false>(algo, g, W, a, stamp, mb, s);
-    return stats ? dispatch_cup<2, true>(algo, g, W, a, stamp, mb, s)
-                 : dispatch_cup<2, false>(algo, g, W, a, stamp, mb, s);
+template <int A, int MW, bool ST>
+uint64_t solve_cup_t(const Graph& g, const Window& W, uint32_t* R, Frontier& f, hipStream_t s) {
+    SolveArgs a = make_args(g, f, R);
+    if (g.n_partial)
+        EVQ_LAUNCH("solve_seed_partial", (k_seed_partial<A, MW, ST>), grid_for(g.n_partial, kBlock, 16384), kBlock, s,
+                   a, window_mask<MW>(W), g.p_src, g.p_eid, (uint32_t)g.n_partial);
+    return frontier_loop<A, 2, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
+}
+
+template <int MW, bool ST>
+uint64_t dispatch_cap(uint32_t algo, const Graph& g, const Window& W, uint32_t source, uint32_t* R, Frontier& f,
+                      hipStream_t s) {
+    switch (algo) {
+    case EVQ_SSSP: return solve_cap_t<EVQ_SSSP, MW, ST>(g, W, source, R, f, s);
+    case EVQ_BFS: return solve_cap_t<EVQ_BFS, MW, ST>(g, W, source, R, f, s);
+    case EVQ_SSWP: return solve_cap_t<EVQ_SSWP, MW, ST>(g, W, source, R, f, s);
+    default: return solve_cap_t<EVQ_SSNP, MW, ST>(g, W, source, R, f, s);
+    }
+}
+
+template <int MW, bool ST>
+uint64_t dispatch_cup(uint32_t algo, const Graph& g, const Window& W, uint32_t* R, Frontier& f, hipStream_t s) {
+    switch (algo) {
+    case EVQ_SSSP: return solve_cup_t<EVQ_SSSP, MW, ST>(g, W, R, f, s);
+    case EVQ_BFS: return solve_cup_t<EVQ_BFS, MW, ST>(g, W, R, f, s);
+    case EVQ_SSWP: return solve_cup_t<EVQ_SSWP, MW, ST>(g, W, R, f, s);
+    default: return solve_cup_t<EVQ_SSNP, MW, ST>(g, W, R, f, s);
+    }
+}
+
+__global__ void k_init_frontier(FrontierCounters* c, unsigned long long* st, int n) {
+    if (threadIdx.x == 0) c->packed[0] = c->packed[1] = 0ull;
+    if ((int)threadIdx.x < n) st[threadIdx.x] = 0ull;
+}
+
+}  // namespace
+
+Frontier make_frontier(const Graph& g, Arena& ar, hipStream_t s) {
+    Frontier f;
+    const uint64_t nwords = ((uint64_t)g.V + 31) / 32;
+    f.bitmap = ar.alloc<uint32_t>(nwords);
+    f.fv = ar.alloc<uint32_t>(g.V);
+    f.fo = ar.alloc<uint32_t>(g.V);
+    f.cnt = ar.alloc<FrontierCounters>(1);
+    f.stats = ar.alloc<unsigned long long>(8);
+    fill_u32(f.bitmap, nwords, 0u, s);
+    EVQ_LAUNCH("query_init", k_init_frontier, 1, 64, s, f.cnt, f.stats, 8);
+    f.p = 0;
+    return f;
+}
+
+uint64_t solve_cap(const Graph& g, uint32_t algo, const Window& W, uint32_t source, uint32_t* R, Frontier& f,
+                   hipStream_t s, bool stats) {
+    if (g.MW == 1) return stats ? dispatch_cap<1, true>(algo, g, W, source, R, f, s)
+                                : dispatch_cap<1, false>(algo, g, W, source, R, f, s);
+    return stats ? dispatch_cap<2, true>(algo, g, W, source, R, f, s)
+                 : dispatch_cap<2, false>(algo, g, W, source, R, f, s);
+}
+
+uint64_t solve_cup(const Graph& g, uint32_t algo, const Window& W, uint32_t* R, Frontier& f, hipStream_t s,
+                   bool stats) {
+    if (g.MW == 1) return stats ? dispatch_cup<1, true>(algo, g, W, R, f, s) : dispatch_cup<1, false>(algo, g, W, R, f, s);
+    return stats ? dispatch_cup<2, true>(algo, g, W, R, f, s) : dispatch_cup<2, false>(algo, g, W, R, f, s);
 }
 
 }  // namespace evq
