@@ -99,6 +99,7 @@ typedef struct {
     uint64_t edges_cap, edges_cup;        /* edge visits of the two bound solves */
     uint64_t edge_visits_relax;           /* edge visits of the multi-snapshot relaxation */
     uint64_t lane_relaxations;            /* (edge visit, snapshot) pairs evaluated there */
+    uint64_t updates_cap, updates_cup;    /* improving value updates of the two bound solves */
 } evq_query_stats;
 
 /*

@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libevq.so")
+LIB_PATH = os.environ.get("EVQ_LIBRARY") or os.path.join(_HERE, "libevq.so")
 
 SSSP, BFS, SSWP, SSNP = 0, 1, 2, 3
 ALGOS = {"sssp": SSSP, "bfs": BFS, "sswp": SSWP, "ssnp": SSNP}
@@ -46,7 +46,8 @@ class QueryStats(ctypes.Structure):
                                                "ms_writeback")] + \
                [(n, ctypes.c_uint64) for n in ("n_unstable", "n_seed_edges", "n_relax_edges", "iters_cap",
                                                "iters_cup", "iters_relax", "edges_cap", "edges_cup",
-                                               "edge_visits_relax", "lane_relaxations")]
+                                               "edge_visits_relax", "lane_relaxations", "updates_cap",
+                                               "updates_cup")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -147,7 +148,7 @@ class Graph:
         return cls(inst.num_vertices, inst.base, inst.dels, inst.adds, stream)
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.evq_free(self._h)
             self._h = None
 

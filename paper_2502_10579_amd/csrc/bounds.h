@@ -10,16 +10,23 @@ namespace evq {
 
 // Device buffers of one query's frontier loops.
 struct Frontier {
-    uint32_t* bitmap = nullptr;  // next-frontier bits over V vertices (all clear between phases)
-    uint32_t* fv = nullptr;      // frontier vertices (V entries)
-    uint32_t* fo = nullptr;      // their running edge offsets (V entries)
+    uint8_t* flags = nullptr;    // next-frontier flags over V vertices (all clear between phases)
+    uint32_t* fo = nullptr;      // frontier items (V entries each): running edge offset,
+    uint32_t* fd = nullptr;      //   row begin minus that offset,
+    uint32_t* fs = nullptr;      //   end of the row's all-present prefix,
+    uint32_t* fv = nullptr;      //   the vertex
     FrontierCounters* cnt = nullptr;
     unsigned long long* stats = nullptr;  // [0] bound-solve edge visits, [1..] relaxer counters
+    unsigned long long* aux = nullptr;    // 128 bytes of scratch counters for the reduction
     int p = 0;                            // parity of the next compaction (continues across phases)
+    uint32_t delta = 0;                   // near/far step of the bound solves (0: off)
 };
 
+// Near/far step for a query: EVQ_DELTA overrides, else a per-algorithm default.
+uint32_t choose_delta(uint32_t algo);
 
-Frontier make_frontier(const Graph& g, Arena& ar, hipStream_t s);
+
+Frontier make_frontier(const Graph& g, Workspace& ws, hipStream_t s);
 
 // R := values on the window's intersection graph.  Returns the iteration count.
 uint64_t solve_cap(const Graph& g, uint32_t algo, const Window& W, uint32_t source, uint32_t* R, Frontier& f,

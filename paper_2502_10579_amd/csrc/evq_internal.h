@@ -68,15 +68,41 @@ class Arena {
     uint64_t bytes_ = 0;
 };
 
+// Query workspace: device buffers kept between queries on one host thread
+// and stream, grown on demand (growth waits for the stream).  Queries on one
+// stream are ordered, so reuse is safe.
+class Workspace {
+  public:
+    enum Slot {
+        kFlags, kFo, kFd, kFs, kFv, kControl, kRcap, kRcup, kCidOf, kUlist, kCuo, kRv, kRc, kRuo, kKc, kRecs,
+        kTasks, kX, kSlots
+    };
+    static Workspace& get(hipStream_t s);
+    void* raw(Slot slot, uint64_t bytes);
+    template <typename T>
+    T* buf(Slot slot, uint64_t n) {
+        return static_cast<T*>(raw(slot, n * sizeof(T)));
+    }
+    bool fresh_flags = true;  // flags must be cleared before use
+    bool in_use = false;      // a query is running on it (a failed one leaves flags unknown)
+
+  private:
+    explicit Workspace(hipStream_t s) : s_(s) {}
+    hipStream_t s_;
+    void* p_[kSlots] = {};
+    uint64_t cap_[kSlots] = {};
+};
+
 void* dev_alloc(uint64_t bytes);  // hipMalloc; throws EVQ_ENOMEM
 void dev_free(void* p);
 void init_mempool(int device);
 
-// Small pinned host mailbox used to read counters back.
+// Small pinned host mailbox used to read counters back (one per host thread).
 struct Mailbox {
     uint32_t* h = nullptr;
     explicit Mailbox(size_t n);
     ~Mailbox();
+    static Mailbox& get();
 };
 
 // ------------------------------------------------------------------ launches

@@ -1,12 +1,12 @@
 // Frontier plumbing shared by the bound solver and the multi-snapshot relaxer.
 //
-// An iteration's improvements only set bits in a bitmap of the next frontier
-// (fire-and-forget atomicOr, after a plain read shows the bit clear), so no
-// vertex is listed twice and no counter is hit per improvement.  A compaction
-// kernel turns the bitmap into the next work list in vertex order, clearing
-// the bits it reads, with one packed 64-bit counter reservation per wave
-// (items in the high word, edges in the low word) so that the list and the
-// running edge offsets stay in the same order.
+// An iteration's improvements only set a byte flag per vertex of the next
+// frontier (an idempotent plain store), so no vertex is listed twice and no
+// counter is hit per improvement.  A compaction kernel turns the flags into
+// the next work list in vertex order, clearing the flags it reads, with one
+// packed 64-bit counter reservation per block (items in the high word, edges
+// in the low word) so that the list and the running edge offsets stay in the
+// same order.
 //
 // Counters are double-buffered by iteration parity p: the compaction of
 // iteration i adds into cnt[p]; the expansion of iteration i reads cnt[p],
@@ -22,40 +22,47 @@ namespace evq {
 
 struct FrontierCounters {
     unsigned long long packed[2];  // (items << 32) | edges, by parity
+    uint32_t far[2];               // ids left for a later threshold, by parity
+    uint32_t fmin[2];              // smallest order key among those ids, by parity
+    uint32_t thr;                  // near/far threshold of the bound solves (order keys below it are near)
+    uint32_t delta;                // threshold step (0: every id is near)
 };
 
 __device__ __forceinline__ uint32_t items_of(unsigned long long x) { return (uint32_t)(x >> 32); }
 __device__ __forceinline__ uint32_t edges_of(unsigned long long x) { return (uint32_t)x; }
 
-__device__ __forceinline__ void mark(uint32_t* __restrict__ bitmap, uint32_t v) {
-    uint32_t* w = bitmap + (v >> 5);
-    const uint32_t bit = 1u << (v & 31);
-    if (!(*w & bit)) __hip_atomic_fetch_or(w, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Next-frontier membership is one byte per id: marking is an idempotent plain
+// byte store, so an improvement costs no second atomic.
+__device__ __forceinline__ void mark(uint8_t* __restrict__ flags, uint32_t v) { flags[v] = 1; }
 
-// Wave-wide reservation of (items, edges) on a packed counter: returns this
-// lane's first item slot and first edge offset.  Every lane must call it.
-__device__ __forceinline__ void wave_reserve2(uint32_t n, uint32_t ne, unsigned long long* cnt, uint32_t& item,
-                                              uint32_t& edge) {
-    const uint32_t in = wave_incl_scan(n), ie = wave_incl_scan(ne);
-    const uint32_t tn = __shfl(in, 63, 64), te = __shfl(ie, 63, 64);
-    unsigned long long base = 0;
-    if (lane_id() == 63 && (tn | te)) base = atomicAdd(cnt, ((unsigned long long)tn << 32) | te);
-    const uint32_t bi = (uint32_t)(__shfl((int)(base >> 32), 63, 64));
-    const uint32_t be = (uint32_t)(__shfl((int)(uint32_t)base, 63, 64));
-    item = bi + in - n;
-    edge = be + ie - ne;
-}
+// Bytes of the flag array for n ids (a multiple of the 8 ids a lane reads).
+inline uint64_t flag_bytes(uint64_t n) { return (n + 7) & ~uint64_t(7); }
 
 // Expansion prologue: read this iteration's counts, clear the other parity,
 // publish the item count to the host slot.
+// When nothing was near but ids were deferred, the threshold moves to the
+// smallest deferred order key plus delta, so the next compaction releases the
+// best of them.
 __device__ __forceinline__ unsigned long long expand_prologue(FrontierCounters* c, int p, uint32_t* slot) {
     const unsigned long long x = c->packed[p];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t f = c->far[p];
+        if (items_of(x) == 0 && f) {
+            const uint64_t t = (uint64_t)c->fmin[p] + c->delta;
+            c->thr = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
+        }
         c->packed[p ^ 1] = 0ull;
-        __hip_atomic_store(slot, items_of(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        c->far[p ^ 1] = 0u;
+        c->fmin[p ^ 1] = 0xFFFFFFFFu;
+        __hip_atomic_store(slot, items_of(x) + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     return x;
+}
+
+// A compaction may skip its scan when the previous iteration had no work and
+// deferred nothing: then no bit can be set.
+__device__ __forceinline__ bool nothing_pending(const FrontierCounters* c, int p, int first) {
+    return !first && c->packed[p ^ 1] == 0ull && c->far[p ^ 1] == 0u;
 }
 
 // Largest i in [0, n) with off[i] <= x (off ascending, off[0] == 0), found by
@@ -78,6 +85,139 @@ __device__ __forceinline__ uint32_t wave_search(const uint32_t* __restrict__ off
     const bool ok = idx < hi && off[idx] <= x;
     const uint64_t b = __ballot(ok);
     return lo + 63u - (uint32_t)__clzll((unsigned long long)b);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Flag compaction shared by the frontier loops.  A block of kCompactBlock
+// threads takes kCompactIds consecutive ids (8 flag bytes per lane), clears
+// their flags, stages the set ids in LDS, reads every id's work size with all
+// loads in flight at once, and reserves (items, edges) for the whole block
+// with one packed atomic.  size_of(id, items, edges, key) gives an id's work
+// and returns false to defer the id: its flag stays set, it is counted in
+// *far and its order key enters the minimum *fmin.  emit(id, item, edge,
+// items, edges) writes an id's work.  Ids appear in ascending order within a
+// block.
+constexpr int kCompactBlock = 512;
+constexpr int kCompactWaves = kCompactBlock / 64;
+constexpr int kIdsPerWave = 512;
+constexpr int kCompactIds = kCompactWaves * kIdsPerWave;
+constexpr int kIdSteps = kIdsPerWave / 64;
+
+template <typename SizeFn, typename EmitFn>
+__device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint32_t n, unsigned long long* cnt,
+                                              uint32_t* far, uint32_t* fmin, SizeFn size_of, EmitFn emit) {
+    __shared__ uint32_t ids[kCompactWaves][kIdsPerWave];
+    __shared__ uint32_t keep[kCompactWaves][64];
+    __shared__ uint32_t wtot[kCompactWaves][4];
+    __shared__ unsigned long long bbase;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint2* __restrict__ f8 = reinterpret_cast<uint2*>(flags);
+    for (uint64_t b0 = (uint64_t)blockIdx.x * kCompactIds; b0 < n; b0 += (uint64_t)gridDim.x * kCompactIds) {
+        const uint32_t w0 = (uint32_t)b0 + wave * kIdsPerWave;  // first id of this wave
+        const uint32_t g0 = w0 + lane * 8;                       // first id of this lane
+        uint2 fl = make_uint2(0u, 0u);
+        if (g0 < n) fl = f8[g0 >> 3];
+        uint32_t word = 0;  // bit k: id g0 + k is flagged
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            word |= ((fl.x >> (8 * k)) & 0xFFu) ? (1u << k) : 0u;
+            word |= ((fl.y >> (8 * k)) & 0xFFu) ? (1u << (k + 4)) : 0u;
+        }
+        const uint32_t pc = (uint32_t)__popc(word);
+        const uint32_t incl = wave_incl_scan(pc);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        uint32_t id[kIdSteps], ni[kIdSteps], ne[kIdSteps], pi[kIdSteps], pe[kIdSteps];
+        uint32_t ti = 0, te = 0, tf = 0, tk = 0xFFFFFFFFu;
+        if (tot) {
+            keep[wave][lane] = 0;
+            uint32_t k = incl - pc;
+            for (uint32_t m = word; m; m &= m - 1) ids[wave][k++] = g0 + (uint32_t)__builtin_ctz(m);
+            wave_lds_sync();
+            uint32_t nf = 0, kmin = 0xFFFFFFFFu;
+#pragma unroll
+            for (int s = 0; s < kIdSteps; ++s) {
+                const uint32_t j = s * 64 + lane;
+                id[s] = 0;
+                ni[s] = 0;
+                ne[s] = 0;
+                if (j < tot) {
+                    id[s] = ids[wave][j];
+                    uint32_t key = 0;
+                    if (!size_of(id[s], ni[s], ne[s], key)) {  // deferred: its flag stays set
+                        ni[s] = ne[s] = 0;
+                        ++nf;
+                        kmin = key < kmin ? key : kmin;
+                        const uint32_t r = id[s] - w0;
+                        atomicOr(&keep[wave][r >> 3], 1u << (r & 7));
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < kIdSteps; ++s) {
+                const uint32_t a = wave_incl_scan(ni[s]), b = wave_incl_scan(ne[s]);
+                pi[s] = ti + a - ni[s];
+                pe[s] = te + b - ne[s];
+                ti += __shfl(a, 63, 64);
+                te += __shfl(b, 63, 64);
+            }
+            tf = wave_sum(nf);
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const uint32_t o = __shfl_xor(kmin, d, 64);
+                kmin = o < kmin ? o : kmin;
+            }
+            tk = kmin;
+            wave_lds_sync();
+            if (word) {
+                const uint32_t kb = keep[wave][lane];
+                uint2 out = make_uint2(0u, 0u);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    out.x |= ((kb >> k) & 1u) << (8 * k);
+                    out.y |= ((kb >> (k + 4)) & 1u) << (8 * k);
+                }
+                f8[g0 >> 3] = out;
+            }
+        }
+        if (lane == 0) {
+            wtot[wave][0] = ti;
+            wtot[wave][1] = te;
+            wtot[wave][2] = tf;
+            wtot[wave][3] = tk;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long sum = 0;
+            uint32_t fsum = 0, kmin = 0xFFFFFFFFu;
+            for (int w = 0; w < kCompactWaves; ++w) {
+                sum += ((unsigned long long)wtot[w][0] << 32) | wtot[w][1];
+                fsum += wtot[w][2];
+                kmin = wtot[w][3] < kmin ? wtot[w][3] : kmin;
+            }
+            bbase = sum ? atomicAdd(cnt, sum) : 0ull;
+            if (fsum) {
+                atomicAdd(far, fsum);
+                atomicMin(fmin, kmin);
+            }
+        }
+        __syncthreads();
+        if (ti) {
+            uint32_t bi = (uint32_t)(bbase >> 32), be = (uint32_t)bbase;
+            for (uint32_t w = 0; w < wave; ++w) {
+                bi += wtot[w][0];
+                be += wtot[w][1];
+            }
+#pragma unroll
+            for (int s = 0; s < kIdSteps; ++s)
+                if (ni[s]) emit(id[s], bi + pi[s], be + pe[s], ni[s], ne[s]);
+        }
+        __syncthreads();
+    }
 }
 
 // Host side: launch-ahead driver of a frontier loop.

@@ -78,122 +78,216 @@ __device__ __forceinline__ bool lanes_partial(const uint64_t (&x)[NLW], uint32_t
     return any && !all;
 }
 
-// ------------------------------------------------------------------ K3: unstable set
+// ------------------------------------------------------------------ K3: unstable set and reduced subgraph
 
-__global__ void k_flag_unstable(const uint32_t* __restrict__ rcap, const uint32_t* __restrict__ rcup, uint32_t V,
-                                uint32_t* __restrict__ flag) {
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x)
-        flag[v] = rcap[v] != rcup[v] ? 1u : 0u;
-}
+constexpr int kUBlock = 512;
+constexpr int kUPerThread = 8;
+constexpr int kUPerBlock = kUBlock * kUPerThread;
 
-__global__ void k_flag_all(uint32_t V, uint32_t* __restrict__ flag) {
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x)
-        flag[v] = 1u;
-}
-
-__global__ void k_assign(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ cidx, uint32_t V,
-                         uint32_t* __restrict__ cid_of, uint32_t* __restrict__ ulist) {
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x) {
-        if (flag[v]) {
-            cid_of[v] = cidx[v];
-            ulist[cidx[v]] = (uint32_t)v;
-        } else {
-            cid_of[v] = kNone;
+// Block-wide exclusive scan of three counters (one value triple per thread).
+__device__ __forceinline__ void block_scan3(const uint32_t (&v)[3], uint32_t (&pre)[3], uint32_t (&tot)[3]) {
+    __shared__ uint32_t ws[kUBlock / 64][3];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t inc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        inc[q] = wave_incl_scan(v[q]);
+        if (lane == 63) ws[wave][q] = inc[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        uint32_t bq = 0, tq = 0;
+        for (uint32_t w = 0; w < kUBlock / 64; ++w) {
+            if (w < wave) bq += ws[w][q];
+            tq += ws[w][q];
         }
+        pre[q] = bq + inc[q] - v[q];
+        tot[q] = tq;
+    }
+    __syncthreads();
+}
+
+// Counters of the reduction: compact ids, and rows (U vertices with edges)
+// packed with their total edge count so rows and edge offsets share an order.
+struct UCounters {
+    unsigned long long ids;
+    unsigned long long rows;  // (rows << 32) | edges
+};
+
+// U = {v : R_cap[v] != R_cup[v]} (all vertices when rcap is null).  Every U
+// vertex gets a compact id c (ascending within a block), ulist[c] = v and the
+// start cuo[c] of its union row in a buffer holding all of U's rows back to
+// back; cid_of[v] = kNone for the others.  U vertices with edges are also
+// listed as rows: rv (vertex), rc (compact id), ruo (row start).
+__global__ void __launch_bounds__(kUBlock) k_unstable(const uint32_t* __restrict__ rcap,
+                                                      const uint32_t* __restrict__ rcup, uint32_t V,
+                                                      const uint32_t* __restrict__ row_ptr,
+                                                      uint32_t* __restrict__ cid_of, uint32_t* __restrict__ ulist,
+                                                      uint32_t* __restrict__ cuo, uint32_t* __restrict__ rv,
+                                                      uint32_t* __restrict__ rc, uint32_t* __restrict__ ruo,
+                                                      UCounters* cnt) {
+    __shared__ unsigned long long base_id, base_row;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * kUPerBlock; b0 < V; b0 += (uint64_t)gridDim.x * kUPerBlock) {
+        const uint64_t v0 = b0 + (uint64_t)threadIdx.x * kUPerThread;
+        uint32_t bits = 0;
+        uint32_t deg[kUPerThread];
+        uint32_t val[3] = {0, 0, 0};  // ids, rows, edges
+#pragma unroll
+        for (int k = 0; k < kUPerThread; ++k) {
+            deg[k] = 0;
+            const uint64_t v = v0 + k;
+            if (v < V && (!rcap || rcap[v] != rcup[v])) {
+                bits |= 1u << k;
+                deg[k] = row_ptr[v + 1] - row_ptr[v];
+                val[0] += 1;
+                val[1] += deg[k] ? 1u : 0u;
+                val[2] += deg[k];
+            }
+        }
+        uint32_t pre[3], tot[3];
+        block_scan3(val, pre, tot);
+        if (threadIdx.x == 0) {
+            base_id = tot[0] ? atomicAdd(&cnt->ids, (unsigned long long)tot[0]) : 0ull;
+            base_row = tot[1] ? atomicAdd(&cnt->rows, ((unsigned long long)tot[1] << 32) | tot[2]) : 0ull;
+        }
+        __syncthreads();
+        uint32_t id = (uint32_t)base_id + pre[0];
+        uint32_t row = (uint32_t)(base_row >> 32) + pre[1];
+        uint32_t edge = (uint32_t)base_row + pre[2];
+#pragma unroll
+        for (int k = 0; k < kUPerThread; ++k) {
+            const uint64_t v = v0 + k;
+            if (v >= V) break;
+            if ((bits >> k) & 1u) {
+                cid_of[v] = id;
+                ulist[id] = (uint32_t)v;
+                cuo[id] = edge;
+                if (deg[k]) {
+                    rv[row] = (uint32_t)v;
+                    rc[row] = id;
+                    ruo[row] = edge;
+                    ++row;
+                    edge += deg[k];
+                }
+                ++id;
+            } else {
+                cid_of[v] = kNone;
+            }
+        }
+        __syncthreads();
     }
 }
 
-// Compaction tasks: ceil(deg / kRowChunk) (at least one) per vertex of U.
-__global__ void k_task_count(const uint32_t* __restrict__ ulist, uint32_t nU, const uint32_t* __restrict__ row_ptr,
-                             uint32_t* __restrict__ tcnt) {
-    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nU; c += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t u = ulist[c];
-        uint32_t deg = row_ptr[u + 1] - row_ptr[u];
-        uint32_t n = (deg + kRowChunk - 1) / kRowChunk;
-        tcnt[c] = n ? n : 1u;
-    }
-}
-
-__global__ void k_task_fill(const uint32_t* __restrict__ tcnt, const uint32_t* __restrict__ toff, uint32_t nU,
-                            uint64_t* __restrict__ tasks) {
-    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nU; c += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t o = toff[c];
-        for (uint32_t k = 0; k < tcnt[c]; ++k) tasks[o + k] = ((uint64_t)k << 32) | (uint32_t)c;
-    }
-}
-
-struct CompactArgs {
+struct ReduceArgs {
     const uint32_t* row_ptr;
     const uint32_t* row_split;
     const uint32_t* col;
     const uint32_t* wgt;
     const uint64_t* mask;
-    const uint32_t* ulist;
+    const uint32_t* rv;
+    const uint32_t* rc;
+    const uint32_t* ruo;
     const uint32_t* cid_of;
-    const uint64_t* tasks;
-    uint32_t n_tasks;
-    uint32_t b, L;
+    uint32_t* kc;  // kept edges per compact id (must start at zero)
+    void* recs;
+    uint32_t nR, TU, b, L;
 };
 
-// Pass 1 (count) and pass 2 (fill) over the union rows of U: keep the edges
-// present in some snapshot of the window whose destination is in U.
-template <int MW, int NLW, bool FILL>
-__global__ void __launch_bounds__(kBlock) k_reduce_rows(CompactArgs a, uint32_t* __restrict__ ecnt,
-                                                        const uint32_t* __restrict__ eoff, Rec<NLW>* __restrict__ out) {
-    const int lane = lane_id();
-    const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const uint32_t nw = gridDim.x * (kBlock / 64);
-    for (uint32_t t = gw; t < a.n_tasks; t += nw) {
-        uint64_t tk = a.tasks[t];
-        uint32_t c = (uint32_t)tk, ch = (uint32_t)(tk >> 32);
-        uint32_t u = a.ulist[c];
-        uint32_t beg = a.row_ptr[u], end = a.row_ptr[u + 1], split = a.row_split[u];
-        uint32_t e0 = beg + ch * kRowChunk;
-        uint32_t e1 = e0 + kRowChunk < end ? e0 + kRowChunk : end;
-        uint32_t at = FILL ? eoff[t] : 0u;
-        for (uint32_t e = e0; e < e1; e += 64) {
-            uint32_t ee = e + lane;
-            bool keep = false;
-            uint64_t lanes[NLW];
-            uint32_t cd = 0;
-            if (ee < e1) {
-                cd = a.cid_of[a.col[ee]];
-                if (cd != kNone) {
-                    edge_lanes<MW, NLW>(a.mask, ee, ee < split, a.b, a.L, lanes);
-                    bool any = false;
-#pragma unroll
-                    for (int j = 0; j < NLW; ++j) any |= lanes[j] != 0;
-                    keep = any;
-                }
-            }
-            uint64_t bal = __ballot(keep);
-            if (FILL && keep) {
-                Rec<NLW> r;
-                r.dst = cd;
-                r.w = a.wgt[ee];
-#pragma unroll
-                for (int j = 0; j < NLW; ++j) r.lanes[j] = lanes[j];
-                out[at + (uint32_t)__popcll(bal & lanemask_lt())] = r;
-            }
-            at += (uint32_t)__popcll(bal);
+// The reduced subgraph, built from U's rows (Section 6.2): every edge of a U
+// vertex's union row present in some snapshot of the window whose destination
+// is also in U, stored as (dst compact id, w, window lane bits) from the
+// row's start in a buffer of all U rows.  The rows' edges are walked as one
+// range [0, TU) cut into equal slices per wave; each run of lanes in one row
+// reserves its slots with one atomic.
+template <int MW, int NLW>
+__global__ void __launch_bounds__(kBlock) k_reduce(ReduceArgs a) {
+    Rec<NLW>* __restrict__ out = static_cast<Rec<NLW>*>(a.recs);
+    const uint32_t lane = lane_id();
+    const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
+    const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
+    uint64_t Rw = (a.TU + nw - 1) / nw;
+    Rw = (Rw + 63) & ~63ull;
+    const uint64_t b0 = gw * Rw;
+    if (b0 >= a.TU) return;
+    const uint32_t end = (uint32_t)(b0 + Rw < a.TU ? b0 + Rw : a.TU);
+    uint32_t cur = wave_search(a.ruo, a.nR, (uint32_t)b0);
+    for (uint32_t base = (uint32_t)b0; base < end; base += 64) {
+        const uint32_t idx = cur + lane;
+        const uint32_t off = idx < a.nR ? a.ruo[idx] : 0xFFFFFFFFu;
+        uint32_t rb = 0, sp = 0, cc = 0, ro = 0;
+        if (off <= base + 63) {
+            const uint32_t u = a.rv[idx];
+            rb = a.row_ptr[u];
+            sp = a.row_split[u];
+            cc = a.rc[idx];
+            ro = off;
         }
-        if (!FILL && lane == 0) ecnt[t] = at;
+        const uint32_t t = base + lane;
+        int o = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const uint32_t q = __shfl(off, o + step, 64);
+            if (q <= t) o += step;
+        }
+        const uint32_t rstart = __shfl(ro, o, 64);
+        const uint32_t e = __shfl(rb, o, 64) + (t - rstart);
+        const uint32_t split = __shfl(sp, o, 64);
+        const uint32_t c = __shfl(cc, o, 64);
+        bool keep = false;
+        uint32_t cd = 0;
+        uint64_t lanes[NLW];
+#pragma unroll
+        for (int j = 0; j < NLW; ++j) lanes[j] = 0;
+        if (t < end) {
+            cd = a.cid_of[a.col[e]];
+            if (cd != kNone) {
+                edge_lanes<MW, NLW>(a.mask, e, e < split, a.b, a.L, lanes);
+                bool any = false;
+#pragma unroll
+                for (int j = 0; j < NLW; ++j) any |= lanes[j] != 0;
+                keep = any;
+            }
+        }
+        // lanes of one row form a contiguous run; its last kept lane reserves
+        const uint64_t kmask = __ballot(keep);
+        const int prev = __shfl_up(o, 1, 64);  // every lane takes part in the shuffle
+        const uint64_t head = __ballot(lane == 0 || prev != o);
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const uint32_t start = 63u - (uint32_t)__clzll((unsigned long long)(head & upto));
+        const uint64_t after = head & ~upto;
+        const uint32_t stop = after ? (uint32_t)__ffsll((unsigned long long)after) - 2u : 63u;
+        const uint64_t run = (stop == 63 ? ~0ull : ((2ull << stop) - 1ull)) & ~((1ull << start) - 1ull);
+        const uint64_t rk = kmask & run;
+        const uint32_t leader = rk ? 63u - (uint32_t)__clzll((unsigned long long)rk) : 0u;
+        uint32_t old = 0;
+        if (keep && lane == leader) old = atomicAdd(&a.kc[c], (uint32_t)__popcll(rk));
+        old = (uint32_t)__shfl((int)old, (int)leader, 64);
+        if (keep) {
+            Rec<NLW> r;
+            r.dst = cd;
+            r.w = a.wgt[e];
+#pragma unroll
+            for (int j = 0; j < NLW; ++j) r.lanes[j] = lanes[j];
+            out[rstart + old + (uint32_t)__popcll(rk & lanemask_lt())] = r;
+        }
+        // next step starts at the owner of base + 64 (every listed row has edges)
+        const uint32_t nb = base + 64;
+        const uint32_t have = (uint32_t)__popcll(__ballot(off <= nb));
+        uint32_t adv = have - 1;
+        if (have == 64 && cur + 64 < a.nR && a.ruo[cur + 64] <= nb) adv = 64;
+        cur += adv;
     }
-}
-
-__global__ void k_rptr(const uint32_t* __restrict__ toff, const uint32_t* __restrict__ eoff, uint32_t nU,
-                       uint32_t* __restrict__ rptr) {
-    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c <= nU; c += (uint64_t)gridDim.x * blockDim.x)
-        rptr[c] = eoff[toff[c]];
 }
 
 // ------------------------------------------------------------------ K4: multi-snapshot relaxation
 
 struct RelaxArgs {
-    const uint32_t* rptr;
+    const uint32_t* cuo;  // row start of each compact id in recs
+    const uint32_t* kc;   // its reduced-subgraph edge count
     const void* recs;
     uint32_t* X;
-    uint32_t* bitmap;  // next-frontier bits over compact ids
+    uint8_t* flags;    // next-frontier flags over compact ids
     uint64_t* tasks;   // (chunk << 32 | compact id), rewritten by each compaction
     FrontierCounters* cnt;
     unsigned long long* stats;  // [1] edge visits, [2] lane relaxations, [3] seed edges
@@ -215,48 +309,20 @@ __device__ __forceinline__ void add_stat(unsigned long long* p, uint32_t v) {
     if (lane_id() == 0 && s) atomicAdd(p, (unsigned long long)s);
 }
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Bitmap of improved compact ids -> relaxation tasks of parity p, one task per
 // kRelaxChunk reduced-subgraph edges of each improved vertex.
-__global__ void __launch_bounds__(kBlock) k_relax_compact(RelaxArgs r, int p, int first) {
-    if (!first && r.cnt->packed[p ^ 1] == 0ull) return;
-    __shared__ uint32_t buf[kBlock / 64][64 * 32];
-    const uint32_t nwords = (r.nU + 31) >> 5;
-    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const uint32_t nw = gridDim.x * (kBlock / 64);
-    for (uint32_t wb = gw * 64; wb < nwords; wb += nw * 64) {
-        const uint32_t wi = wb + lane;
-        uint32_t word = 0;
-        if (wi < nwords) {
-            word = r.bitmap[wi];
-            if (word) r.bitmap[wi] = 0;
-        }
-        const uint32_t pc = (uint32_t)__popc(word);
-        const uint32_t incl = wave_incl_scan(pc);
-        const uint32_t tot = __shfl(incl, 63, 64);
-        uint32_t k = incl - pc;
-        for (uint32_t m = word; m; m &= m - 1) buf[wave][k++] = wi * 32 + (uint32_t)__builtin_ctz(m);
-        wave_lds_sync();
-        for (uint32_t s0 = 0; s0 < tot; s0 += 64) {
-            const uint32_t j = s0 + lane;
-            uint32_t c = 0, deg = 0;
-            if (j < tot) {
-                c = buf[wave][j];
-                deg = r.rptr[c + 1] - r.rptr[c];
-            }
-            const uint32_t nt = (deg + kRelaxChunk - 1) / kRelaxChunk;
-            uint32_t item, edge;
-            wave_reserve2(nt, deg, &r.cnt->packed[p], item, edge);
-            for (uint32_t q = 0; q < nt; ++q) r.tasks[item + q] = ((uint64_t)q << 32) | c;
-        }
-        wave_lds_sync();
-    }
+__global__ void __launch_bounds__(kCompactBlock) k_relax_compact(RelaxArgs r, int p, int first) {
+    if (nothing_pending(r.cnt, p, first)) return;
+    compact_flags(
+        r.flags, r.nU, &r.cnt->packed[p], &r.cnt->far[p], &r.cnt->fmin[p],
+        [&](uint32_t c, uint32_t& items, uint32_t& edges, uint32_t&) {
+            edges = r.kc[c];
+            items = (edges + kRelaxChunk - 1) / kRelaxChunk;
+            return true;
+        },
+        [&](uint32_t c, uint32_t item, uint32_t, uint32_t items, uint32_t) {
+            for (uint32_t q = 0; q < items; ++q) r.tasks[item + q] = ((uint64_t)q << 32) | c;
+        });
 }
 
 // Seeding pass (the parfor over the reduced addition batches in Algorithm 2):
@@ -318,7 +384,7 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
                     }
                 }
             }
-            if (group_any<LG>(imp) && i0 == 0) mark(r.bitmap, gcv);
+            if (group_any<LG>(imp) && i0 == 0) mark(r.flags, gcv);
             for (int k = 0; k < T::G && bal; ++k) bal &= bal - 1;
         }
     }
@@ -347,7 +413,7 @@ __global__ void __launch_bounds__(kBlock) k_relax(RelaxArgs r, int p, uint32_t* 
             uint64_t tk = tasks[ti];
             if (T::G == 1) tk = ((uint64_t)uniform((uint32_t)(tk >> 32)) << 32) | uniform((uint32_t)tk);
             c = (uint32_t)tk;
-            const uint32_t rb = r.rptr[c], re = r.rptr[c + 1];
+            const uint32_t rb = r.cuo[c], re = rb + r.kc[c];
             e0 = rb + (uint32_t)(tk >> 32) * kRelaxChunk;
             ne = re - e0 < kRelaxChunk ? re - e0 : kRelaxChunk;
         }
@@ -391,7 +457,7 @@ __global__ void __launch_bounds__(kBlock) k_relax(RelaxArgs r, int p, uint32_t* 
                     }
                 }
             }
-            if (group_any<LG>(imp) && i0 == 0) mark(r.bitmap, rec[k].dst);
+            if (group_any<LG>(imp) && i0 == 0) mark(r.flags, rec[k].dst);
         }
         if (ST) {
             add_stat<true>(&r.stats[1], i0 == 0 ? ne : 0u);
@@ -418,8 +484,8 @@ __global__ void k_xinit_plain(uint32_t V, uint32_t source, uint32_t unreached, u
         X[k] = (k / LG) == source ? at_source : unreached;
 }
 
-__global__ void k_mark_one(uint32_t* bitmap, uint32_t c) {
-    if (threadIdx.x == 0) bitmap[c >> 5] |= 1u << (c & 31);
+__global__ void k_mark_one(uint8_t* flags, uint32_t c) {
+    if (threadIdx.x == 0) flags[c] = 1;
 }
 
 // values[v * L + i], four values per lane (L % 4 == 0, 16-byte aligned rows).
@@ -494,106 +560,94 @@ struct Timer {
     }
 };
 
-uint32_t read_u32(const uint32_t* d, Mailbox& mb, hipStream_t s) {
-    EVQ_HIP(hipMemcpyAsync(mb.h + 3, d, 4, hipMemcpyDeviceToHost, s));
-    EVQ_HIP(hipStreamSynchronize(s));
-    return mb.h[3];
-}
-
 struct Reduced {
-    uint32_t nU = 0;
-    uint64_t nRE = 0;
+    uint32_t nU = 0, nR = 0;
+    uint64_t TU = 0;
     uint32_t* cid_of = nullptr;
     uint32_t* ulist = nullptr;
-    uint32_t* rptr = nullptr;
+    uint32_t* cuo = nullptr;
+    uint32_t* kc = nullptr;
     void* recs = nullptr;
 };
 
-// Builds U's compact ids and the reduced relaxation CSR.  all_vertices: U = V.
+// Builds U's compact ids and the reduced subgraph.  all_vertices: U = V.
+// One host read-back (|U|, rows, edges) sizes the subgraph buffer.
 Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup, bool all_vertices, const Window& W,
-                     uint32_t NLW, Arena& ar, Mailbox& mb, hipStream_t s) {
+                     uint32_t NLW, const Frontier& f, Workspace& ws, Mailbox& mb, hipStream_t s) {
     Reduced r;
     const uint32_t V = g.V;
-    uint32_t* flag = ar.alloc<uint32_t>((uint64_t)V + 1);
-    uint32_t* cidx = ar.alloc<uint32_t>((uint64_t)V + 1);
-    if (all_vertices) EVQ_LAUNCH("compact_flag", k_flag_all, grid_for(V, 256), 256, s, V, flag);
-    else EVQ_LAUNCH("compact_flag", k_flag_unstable, grid_for(V, 256), 256, s, rcap, rcup, V, flag);
-    scan_exclusive(flag, cidx, V, cidx + V, s, ar);
-    r.nU = read_u32(cidx + V, mb, s);
-    r.cid_of = ar.alloc<uint32_t>(V);
-    if (r.nU == 0) {
-        fill_u32(r.cid_of, V, kNone, s);
-        return r;
+    r.cid_of = ws.buf<uint32_t>(Workspace::kCidOf, V);
+    r.ulist = ws.buf<uint32_t>(Workspace::kUlist, V);
+    r.cuo = ws.buf<uint32_t>(Workspace::kCuo, V);
+    uint32_t* rv = ws.buf<uint32_t>(Workspace::kRv, V);
+    uint32_t* rc = ws.buf<uint32_t>(Workspace::kRc, V);
+    uint32_t* ruo = ws.buf<uint32_t>(Workspace::kRuo, V);
+    UCounters* uc = reinterpret_cast<UCounters*>(f.aux);
+    fill_u32(reinterpret_cast<uint32_t*>(uc), sizeof(UCounters) / 4, 0u, s);
+    EVQ_LAUNCH("compact_unstable", k_unstable, grid_for(V, kUPerBlock, 65535), kUBlock, s,
+               all_vertices ? nullptr : rcap, rcup, V, g.row_ptr, r.cid_of, r.ulist, r.cuo, rv, rc, ruo, uc);
+    EVQ_HIP(hipMemcpyAsync(mb.h, uc, sizeof(UCounters), hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipStreamSynchronize(s));
+    const unsigned long long* hc = reinterpret_cast<const unsigned long long*>(mb.h);
+    r.nU = (uint32_t)hc[0];
+    r.nR = (uint32_t)(hc[1] >> 32);
+    r.TU = (uint32_t)hc[1];
+    if (r.nU == 0) return r;
+    r.kc = ws.buf<uint32_t>(Workspace::kKc, r.nU);
+    fill_u32(r.kc, r.nU, 0u, s);
+    r.recs = ws.raw(Workspace::kRecs, (r.TU + 1) * (NLW == 1 ? sizeof(Rec<1>) : sizeof(Rec<2>)));
+    if (r.TU) {
+        ReduceArgs a;
+        a.row_ptr = g.row_ptr;
+        a.row_split = g.row_split;
+        a.col = g.col;
+        a.wgt = g.wgt;
+        a.mask = g.mask;
+        a.rv = rv;
+        a.rc = rc;
+        a.ruo = ruo;
+        a.cid_of = r.cid_of;
+        a.kc = r.kc;
+        a.recs = r.recs;
+        a.nR = r.nR;
+        a.TU = (uint32_t)r.TU;
+        a.b = W.b;
+        a.L = W.L;
+        const uint32_t blocks = grid_for((r.TU + 63) / 64, kBlock / 64, 2048);
+        if (g.MW == 1) EVQ_LAUNCH("compact_reduce", (k_reduce<1, 1>), blocks, kBlock, s, a);
+        else if (NLW == 1) EVQ_LAUNCH("compact_reduce", (k_reduce<2, 1>), blocks, kBlock, s, a);
+        else EVQ_LAUNCH("compact_reduce", (k_reduce<2, 2>), blocks, kBlock, s, a);
     }
-    r.ulist = ar.alloc<uint32_t>(r.nU);
-    EVQ_LAUNCH("compact_assign", k_assign, grid_for(V, 256), 256, s, flag, cidx, V, r.cid_of, r.ulist);
-    ar.release(flag);
-    ar.release(cidx);
-
-    uint32_t* tcnt = ar.alloc<uint32_t>((uint64_t)r.nU + 1);
-    uint32_t* toff = ar.alloc<uint32_t>((uint64_t)r.nU + 1);
-    EVQ_LAUNCH("compact_task_count", k_task_count, grid_for(r.nU, 256), 256, s, r.ulist, r.nU, g.row_ptr, tcnt);
-    scan_exclusive(tcnt, toff, r.nU, toff + r.nU, s, ar);
-    const uint32_t T = read_u32(toff + r.nU, mb, s);
-    uint64_t* tasks = ar.alloc<uint64_t>(T);
-    EVQ_LAUNCH("compact_task_fill", k_task_fill, grid_for(r.nU, 256), 256, s, tcnt, toff, r.nU, tasks);
-
-    CompactArgs a;
-    a.row_ptr = g.row_ptr;
-    a.row_split = g.row_split;
-    a.col = g.col;
-    a.wgt = g.wgt;
-    a.mask = g.mask;
-    a.ulist = r.ulist;
-    a.cid_of = r.cid_of;
-    a.tasks = tasks;
-    a.n_tasks = T;
-    a.b = W.b;
-    a.L = W.L;
-    uint32_t* ecnt = ar.alloc<uint32_t>((uint64_t)T + 1);
-    uint32_t* eoff = ar.alloc<uint32_t>((uint64_t)T + 1);
-    const uint32_t blocks = grid_for(T, kBlock / 64, 32768);
-#define EVQ_REDUCE(MW_, NLW_)                                                                                      \
-    do {                                                                                                           \
-        EVQ_LAUNCH("compact_count", (k_reduce_rows<MW_, NLW_, false>), blocks, kBlock, s, a, ecnt,                \
-                   (const uint32_t*)nullptr, (Rec<NLW_>*)nullptr);                                                 \
-        scan_exclusive(ecnt, eoff, T, eoff + T, s, ar);                                                            \
-        r.nRE = read_u32(eoff + T, mb, s);                                                                         \
-        r.recs = ar.raw((r.nRE + 1) * sizeof(Rec<NLW_>));                                                          \
-        EVQ_LAUNCH("compact_fill", (k_reduce_rows<MW_, NLW_, true>), blocks, kBlock, s, a, ecnt,                  \
-                   (const uint32_t*)eoff, (Rec<NLW_>*)r.recs);                                                     \
-    } while (0)
-    if (g.MW == 1) EVQ_REDUCE(1, 1);
-    else if (NLW == 1) EVQ_REDUCE(2, 1);
-    else EVQ_REDUCE(2, 2);
-#undef EVQ_REDUCE
-    r.rptr = ar.alloc<uint32_t>((uint64_t)r.nU + 1);
-    EVQ_LAUNCH("compact_rptr", k_rptr, grid_for((uint64_t)r.nU + 1, 256), 256, s, toff, eoff, r.nU, r.rptr);
-    ar.release(tcnt);
-    ar.release(tasks);
-    ar.release(ecnt);
-    ar.release(eoff);
-    ar.release(toff);
     return r;
+}
+
+uint64_t sum_u32(const uint32_t* d, uint32_t n, hipStream_t s) {
+    std::vector<uint32_t> h(n);
+    EVQ_HIP(hipMemcpyAsync(h.data(), d, (uint64_t)n * 4, hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipStreamSynchronize(s));
+    uint64_t t = 0;
+    for (uint32_t x : h) t += x;
+    return t;
 }
 
 template <int A, int LG, bool ST>
 void relax_phase(const Graph& g, const Window& W, const uint32_t* rcap, const Reduced& red, uint32_t* X, bool plain,
-                 uint32_t source, Frontier& f, Arena& ar, hipStream_t s, QueryOut& qo) {
+                 uint32_t source, Frontier& f, Workspace& ws, hipStream_t s, QueryOut& qo) {
     using T = Lanes<LG>;
     RelaxArgs ra;
-    ra.rptr = red.rptr;
+    ra.cuo = red.cuo;
+    ra.kc = red.kc;
     ra.recs = red.recs;
     ra.X = X;
-    ra.bitmap = f.bitmap;
-    ra.tasks = ar.alloc<uint64_t>((uint64_t)red.nU + red.nRE / kRelaxChunk + 64);
+    ra.flags = f.flags;
+    ra.tasks = ws.buf<uint64_t>(Workspace::kTasks, (uint64_t)red.nU + red.TU / kRelaxChunk + 64);
     ra.cnt = f.cnt;
     ra.stats = f.stats;
     ra.nU = red.nU;
     if (plain) {
         EVQ_LAUNCH("relax_xinit", k_xinit_plain<LG>, grid_for((uint64_t)red.nU * LG, 256 * 4), 256, s, g.V, source,
                    Alg<A>::unreached, Alg<A>::at_source, X);
-        EVQ_LAUNCH("relax_seed", k_mark_one, 1, 64, s, f.bitmap, source);
+        EVQ_LAUNCH("relax_seed", k_mark_one, 1, 64, s, f.flags, source);
     } else {
         EVQ_LAUNCH("relax_xinit", k_xinit<LG>, grid_for((uint64_t)red.nU * LG, 256 * 4), 256, s, red.ulist, red.nU,
                    rcap, X);
@@ -607,11 +661,10 @@ void relax_phase(const Graph& g, const Window& W, const uint32_t* rcap, const Re
 #undef EVQ_SEED
         }
     }
-    const uint32_t nwords = (red.nU + 31) >> 5;
-    const uint32_t cblocks = grid_for((nwords + 63) / 64, kBlock / 64, 4096);
-    const uint32_t rblocks = grid_for(((uint64_t)red.nU + red.nRE / kRelaxChunk + T::G - 1) / T::G, kBlock / 64, 4096);
+    const uint32_t cblocks = grid_for(red.nU, kCompactIds, 4096);
+    const uint32_t rblocks = grid_for(((uint64_t)red.nU + red.TU / kRelaxChunk + T::G - 1) / T::G, kBlock / 64, 4096);
     auto issue = [&](uint64_t, int p, bool first, uint32_t* slot) {
-        EVQ_LAUNCH("relax_compact", k_relax_compact, cblocks, kBlock, s, ra, p, first ? 1 : 0);
+        EVQ_LAUNCH("relax_compact", k_relax_compact, cblocks, kCompactBlock, s, ra, p, first ? 1 : 0);
         EVQ_LAUNCH("relax", (k_relax<A, LG, ST>), rblocks, kBlock, s, ra, p, slot);
     };
     qo.st.iters_relax = drive_loop(issue, f.p, s, (uint64_t)g.V + 2, "snapshot relaxation");
@@ -619,11 +672,11 @@ void relax_phase(const Graph& g, const Window& W, const uint32_t* rcap, const Re
 
 template <int A>
 void relax_dispatch(uint32_t LG, bool st, const Graph& g, const Window& W, const uint32_t* rcap, const Reduced& red,
-                    uint32_t* X, bool plain, uint32_t source, Frontier& f, Arena& ar, hipStream_t s, QueryOut& qo) {
+                    uint32_t* X, bool plain, uint32_t source, Frontier& f, Workspace& ws, hipStream_t s, QueryOut& qo) {
 #define EVQ_RX(LG_)                                                                          \
     case LG_:                                                                                \
-        if (st) relax_phase<A, LG_, true>(g, W, rcap, red, X, plain, source, f, ar, s, qo); \
-        else relax_phase<A, LG_, false>(g, W, rcap, red, X, plain, source, f, ar, s, qo);   \
+        if (st) relax_phase<A, LG_, true>(g, W, rcap, red, X, plain, source, f, ws, s, qo); \
+        else relax_phase<A, LG_, false>(g, W, rcap, red, X, plain, source, f, ws, s, qo);   \
         break;
     switch (LG) {
         EVQ_RX(8)
@@ -636,13 +689,13 @@ void relax_dispatch(uint32_t LG, bool st, const Graph& g, const Window& W, const
 }
 
 void relax_algo(uint32_t algo, uint32_t LG, bool st, const Graph& g, const Window& W, const uint32_t* rcap,
-                const Reduced& red, uint32_t* X, bool plain, uint32_t source, Frontier& f, Arena& ar, hipStream_t s,
+                const Reduced& red, uint32_t* X, bool plain, uint32_t source, Frontier& f, Workspace& ws, hipStream_t s,
                 QueryOut& qo) {
     switch (algo) {
-    case EVQ_SSSP: relax_dispatch<EVQ_SSSP>(LG, st, g, W, rcap, red, X, plain, source, f, ar, s, qo); break;
-    case EVQ_BFS: relax_dispatch<EVQ_BFS>(LG, st, g, W, rcap, red, X, plain, source, f, ar, s, qo); break;
-    case EVQ_SSWP: relax_dispatch<EVQ_SSWP>(LG, st, g, W, rcap, red, X, plain, source, f, ar, s, qo); break;
-    default: relax_dispatch<EVQ_SSNP>(LG, st, g, W, rcap, red, X, plain, source, f, ar, s, qo); break;
+    case EVQ_SSSP: relax_dispatch<EVQ_SSSP>(LG, st, g, W, rcap, red, X, plain, source, f, ws, s, qo); break;
+    case EVQ_BFS: relax_dispatch<EVQ_BFS>(LG, st, g, W, rcap, red, X, plain, source, f, ws, s, qo); break;
+    case EVQ_SSWP: relax_dispatch<EVQ_SSWP>(LG, st, g, W, rcap, red, X, plain, source, f, ws, s, qo); break;
+    default: relax_dispatch<EVQ_SSNP>(LG, st, g, W, rcap, red, X, plain, source, f, ws, s, qo); break;
     }
 }
 
@@ -658,6 +711,18 @@ void writeback(uint32_t LG, uint32_t V, uint32_t L, const uint32_t* cid_of, cons
     }
 }
 
+}  // namespace
+
+uint32_t choose_delta(uint32_t algo) {
+    static const char* names[4] = {"EVQ_DELTA_SSSP", "EVQ_DELTA_BFS", "EVQ_DELTA_SSWP", "EVQ_DELTA_SSNP"};
+    const char* e = getenv(names[algo & 3]);
+    if (!e) e = getenv("EVQ_DELTA");
+    if (e) return (uint32_t)strtoul(e, nullptr, 10);
+    return 0u;
+}
+
+namespace {
+
 uint64_t read_stat(const unsigned long long* d, int i, hipStream_t s) {
     unsigned long long h = 0;
     EVQ_HIP(hipMemcpyAsync(&h, d + i, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -671,37 +736,46 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
                uint32_t* d_rcap_out, uint32_t* d_rcup_out, bool bounds_only, QueryOut& qo, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     init_mempool(g.device);
-    Arena ar(s);
-    Mailbox mb(8);
+    Workspace& ws = Workspace::get(s);
+    Mailbox& mb = Mailbox::get();
     const bool st = qo.want_stats;
     Timer tm(st, s);
     tm.mark();
-    Frontier f = make_frontier(g, ar, s);
-    uint32_t* rcap = d_rcap_out ? d_rcap_out : ar.alloc<uint32_t>(g.V);
-    uint32_t* rcup = d_rcup_out ? d_rcup_out : ar.alloc<uint32_t>(g.V);
+    Frontier f = make_frontier(g, ws, s);
+    f.delta = choose_delta(algo);
+    uint32_t* rcap = d_rcap_out ? d_rcap_out : ws.buf<uint32_t>(Workspace::kRcap, g.V);
+    uint32_t* rcup = d_rcup_out ? d_rcup_out : ws.buf<uint32_t>(Workspace::kRcup, g.V);
     qo.st.iters_cap = solve_cap(g, algo, W, source, rcap, f, s, st);
     tm.mark();
     EVQ_HIP(hipMemcpyAsync(rcup, rcap, (uint64_t)g.V * 4, hipMemcpyDeviceToDevice, s));
-    if (st) qo.st.edges_cap = read_stat(f.stats, 0, s);
+    if (st) {
+        qo.st.edges_cap = read_stat(f.stats, 0, s);
+        qo.st.updates_cap = read_stat(f.stats, 4, s);
+    }
     qo.st.iters_cup = solve_cup(g, algo, W, rcup, f, s, st);
     tm.mark();
-    if (st) qo.st.edges_cup = read_stat(f.stats, 0, s) - qo.st.edges_cap;
+    if (st) {
+        qo.st.edges_cup = read_stat(f.stats, 0, s) - qo.st.edges_cap;
+        qo.st.updates_cup = read_stat(f.stats, 4, s) - qo.st.updates_cap;
+    }
     if (bounds_only) {
         EVQ_HIP(hipStreamSynchronize(s));
+        ws.in_use = false;
         return;
     }
     const uint32_t LG = pick_lg(W.L);
     const uint32_t NLW = LG > 64 ? 2 : 1;
-    Reduced red = reduce_graph(g, rcap, rcup, false, W, NLW, ar, mb, s);
+    Reduced red = reduce_graph(g, rcap, rcup, false, W, NLW, f, ws, mb, s);
     tm.mark();
     uint32_t* X = nullptr;
     if (red.nU) {
-        X = ar.alloc<uint32_t>((uint64_t)red.nU * LG);
-        relax_algo(algo, LG, st, g, W, rcap, red, X, false, source, f, ar, s, qo);
+        X = ws.buf<uint32_t>(Workspace::kX, (uint64_t)red.nU * LG);
+        relax_algo(algo, LG, st, g, W, rcap, red, X, false, source, f, ws, s, qo);
     }
     tm.mark();
     writeback(LG, g.V, W.L, red.cid_of, rcap, X, d_values, s);
     tm.mark();
+    ws.in_use = false;
     if (st) {
         qo.st.ms_cap = tm.ms(0, 1);
         qo.st.ms_cup = tm.ms(1, 2);
@@ -709,7 +783,7 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
         qo.st.ms_relax = tm.ms(3, 4);
         qo.st.ms_writeback = tm.ms(4, 5);
         qo.st.n_unstable = red.nU;
-        qo.st.n_relax_edges = red.nRE;
+        qo.st.n_relax_edges = red.nU ? sum_u32(red.kc, red.nU, s) : 0;
         qo.st.edge_visits_relax = read_stat(f.stats, 1, s);
         qo.st.lane_relaxations = read_stat(f.stats, 2, s);
         qo.st.n_seed_edges = read_stat(f.stats, 3, s);
@@ -722,27 +796,28 @@ void run_plain(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
                hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     init_mempool(g.device);
-    Arena ar(s);
-    Mailbox mb(8);
+    Workspace& ws = Workspace::get(s);
+    Mailbox& mb = Mailbox::get();
     const bool st = qo.want_stats;
     Timer tm(st, s);
     tm.mark();
-    Frontier f = make_frontier(g, ar, s);
+    Frontier f = make_frontier(g, ws, s);
     const uint32_t LG = pick_lg(W.L);
     const uint32_t NLW = LG > 64 ? 2 : 1;
-    Reduced red = reduce_graph(g, nullptr, nullptr, true, W, NLW, ar, mb, s);
+    Reduced red = reduce_graph(g, nullptr, nullptr, true, W, NLW, f, ws, mb, s);
     tm.mark();
-    uint32_t* X = ar.alloc<uint32_t>((uint64_t)g.V * LG);
-    relax_algo(algo, LG, st, g, W, nullptr, red, X, true, source, f, ar, s, qo);
+    uint32_t* X = ws.buf<uint32_t>(Workspace::kX, (uint64_t)g.V * LG);
+    relax_algo(algo, LG, st, g, W, nullptr, red, X, true, source, f, ws, s, qo);
     tm.mark();
     writeback(LG, g.V, W.L, red.cid_of, nullptr, X, d_values, s);
     tm.mark();
+    ws.in_use = false;
     if (st) {
         qo.st.ms_compact = tm.ms(0, 1);
         qo.st.ms_relax = tm.ms(1, 2);
         qo.st.ms_writeback = tm.ms(2, 3);
         qo.st.n_unstable = red.nU;
-        qo.st.n_relax_edges = red.nRE;
+        qo.st.n_relax_edges = red.nU ? sum_u32(red.kc, red.nU, s) : 0;
         qo.st.edge_visits_relax = read_stat(f.stats, 1, s);
         qo.st.lane_relaxations = read_stat(f.stats, 2, s);
         EVQ_HIP(hipStreamSynchronize(s));

@@ -51,6 +51,32 @@ void init_mempool(int device) {
     done.push_back(device);
 }
 
+Workspace& Workspace::get(hipStream_t s) {
+    thread_local std::vector<std::pair<std::pair<int, hipStream_t>, Workspace*>> all;  // per thread
+    int dev = 0;
+    EVQ_HIP(hipGetDevice(&dev));
+    for (auto& kv : all)
+        if (kv.first.first == dev && kv.first.second == s) return *kv.second;
+    all.push_back({{dev, s}, new Workspace(s)});
+    return *all.back().second;
+}
+
+void* Workspace::raw(Slot slot, uint64_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (cap_[slot] >= bytes) return p_[slot];
+    if (p_[slot]) {
+        EVQ_HIP(hipStreamSynchronize(s_));
+        dev_free(p_[slot]);
+        p_[slot] = nullptr;
+        cap_[slot] = 0;
+    }
+    const uint64_t want = ((bytes + bytes / 4) + 4095) & ~uint64_t(4095);
+    p_[slot] = dev_alloc(want);
+    cap_[slot] = want;
+    if (slot == kFlags) fresh_flags = true;
+    return p_[slot];
+}
+
 void* Arena::raw(uint64_t bytes) {
     void* p = nullptr;
     uint64_t n = (bytes + 255) & ~uint64_t(255);
@@ -87,6 +113,11 @@ Mailbox::~Mailbox() {
     if (h) (void)hipHostFree(h);
 }
 
+Mailbox& Mailbox::get() {
+    thread_local Mailbox* mb = new Mailbox(16);  // lives as long as the thread
+    return *mb;
+}
+
 // ------------------------------------------------------------------ host slots
 
 HostSlots::HostSlots() {
@@ -108,9 +139,12 @@ HostSlots& HostSlots::get() {
 void wait_slot(volatile uint32_t* slot, hipStream_t s, const char* what) {
     if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) != HostSlots::kEmpty) return;
     const auto t0 = std::chrono::steady_clock::now();
-    for (uint64_t spin = 1;; ++spin) {
+    auto next_check = t0 + std::chrono::microseconds(200);
+    for (;;) {
         if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) != HostSlots::kEmpty) return;
-        if ((spin & 255) != 0) continue;
+        const auto now = std::chrono::steady_clock::now();
+        if (now < next_check) continue;
+        next_check = now + std::chrono::microseconds(200);
         const hipError_t e = hipStreamQuery(s);
         if (e == hipSuccess) {
             EVQ_HIP(hipStreamSynchronize(s));

@@ -6,8 +6,9 @@
 // the edges missing from the intersection graph (Section 6.2).
 //
 // One iteration = two kernels:
-//   compaction  next-frontier bitmap -> vertex list fv[] with running edge
-//               offsets fo[] (vertices without edges are dropped);
+//   compaction  next-frontier flags -> frontier items in vertex order: the
+//               running edge offset and the row position of each vertex with
+//               edges, so the expansion reads them contiguously;
 //   expansion   the frontier's edges, viewed as one range [0, T), are cut
 //               into equal contiguous slices, one per wave; a wave finds its
 //               first vertex with a 64-ary search over fo[] and then walks 64
@@ -22,7 +23,28 @@ namespace evq {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr uint32_t kExpandBlocks = 2048;
+// Tuning knobs (compile-time): blocks of the expansion grid, independent edge
+// walks per wave, streaming (non-temporal) loads of the edge arrays.
+#ifndef EVQ_EXPAND_BLOCKS
+#define EVQ_EXPAND_BLOCKS 2048
+#endif
+#ifndef EVQ_WALKERS
+#define EVQ_WALKERS 2
+#endif
+#ifndef EVQ_NT_EDGES
+#define EVQ_NT_EDGES 0
+#endif
+constexpr uint32_t kExpandBlocks = EVQ_EXPAND_BLOCKS;
+constexpr int kWalkers = EVQ_WALKERS;
+
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+#if EVQ_NT_EDGES
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 
 struct SolveArgs {
     const uint32_t* row_ptr;
@@ -31,9 +53,11 @@ struct SolveArgs {
     const uint32_t* wgt;
     const uint64_t* mask;
     uint32_t* R;
-    uint32_t* bitmap;
-    uint32_t* fv;  // frontier vertices
-    uint32_t* fo;  // their first edge offset in the frontier's edge range
+    uint8_t* flags;
+    uint32_t* fo;  // frontier item: first edge offset in the frontier's edge range
+    uint32_t* fd;  // row begin minus that offset (edge id = frontier offset + fd)
+    uint32_t* fs;  // end of the row's all-present prefix
+    uint32_t* fv;  // the vertex (its value is read when expanded: fresher values save work)
     FrontierCounters* cnt;
     unsigned long long* stats;
     uint32_t V;
@@ -56,6 +80,11 @@ __device__ __forceinline__ bool partial_in(const uint64_t* __restrict__ mask, ui
     return all;
 }
 
+template <int A>
+__device__ __forceinline__ uint32_t order_key(uint32_t x) {
+    return A == EVQ_SSWP ? ~x : x;
+}
+
 template <int MODE>
 __device__ __forceinline__ uint32_t row_end(const SolveArgs& a, uint32_t v) {
     return MODE == 0 ? a.row_split[v] : a.row_ptr[v + 1];
@@ -68,7 +97,7 @@ __device__ __forceinline__ void relax(const SolveArgs& a, uint32_t e, uint32_t s
     const uint32_t cand = Alg<A>::extend(x, a.wgt[e]);
     if (!Alg<A>::better(cand, a.R[v])) return;
     Alg<A>::improve_nr(&a.R[v], cand);
-    mark(a.bitmap, v);
+    mark(a.flags, v);
 }
 
 template <bool ST>
@@ -78,106 +107,142 @@ __device__ __forceinline__ void count_visits(const SolveArgs& a, uint32_t n) {
     if (lane_id() == 0 && s) atomicAdd(&a.stats[0], (unsigned long long)s);
 }
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Flags -> frontier items of parity p, clearing the flags it reads; vertices
+// without edges in this solve's graph are dropped.
+// With near/far scheduling on (delta > 0), a vertex whose order key (its
+// value, complemented for widest paths, so smaller is better) is not below the
+// threshold keeps its flag for a later iteration.
+template <int A, int MODE>
+__global__ void __launch_bounds__(kCompactBlock) k_compact_frontier(SolveArgs a, int p, int first) {
+    if (nothing_pending(a.cnt, p, first)) return;
+    const uint32_t thr = a.cnt->thr;
+    const bool nf = a.cnt->delta != 0;
+    compact_flags(
+        a.flags, a.V, &a.cnt->packed[p], &a.cnt->far[p], &a.cnt->fmin[p],
+        [&](uint32_t v, uint32_t& items, uint32_t& edges, uint32_t& key) {
+            edges = row_end<MODE>(a, v) - a.row_ptr[v];
+            items = edges ? 1u : 0u;
+            if (!nf || !edges) return true;
+            key = order_key<A>(a.R[v]);
+            return key < thr;
+        },
+        [&](uint32_t v, uint32_t item, uint32_t edge, uint32_t, uint32_t) {
+            a.fo[item] = edge;
+            a.fd[item] = a.row_ptr[v] - edge;
+            if (MODE != 0) a.fs[item] = a.row_split[v];
+            a.fv[item] = v;
+        });
 }
 
-// Bitmap -> (fv, fo) of parity p, clearing the bits it reads.  A wave takes 64
-// bitmap words, stages their vertex ids in LDS, then reads the degrees of up
-// to 64 vertices at a time.
-template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_compact_frontier(SolveArgs a, int p, int first) {
-    if (!first && a.cnt->packed[p ^ 1] == 0ull) return;  // the previous expansion set no bits
-    __shared__ uint32_t buf[kBlock / 64][64 * 32];
-    const uint32_t nwords = (a.V + 31) >> 5;
-    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const uint32_t nw = gridDim.x * (kBlock / 64);
-    for (uint32_t wb = gw * 64; wb < nwords; wb += nw * 64) {
-        const uint32_t wi = wb + lane;
-        uint32_t word = 0;
-        if (wi < nwords) {
-            word = a.bitmap[wi];
-            if (word) a.bitmap[wi] = 0;
-        }
-        const uint32_t pc = (uint32_t)__popc(word);
-        const uint32_t incl = wave_incl_scan(pc);
-        const uint32_t tot = __shfl(incl, 63, 64);
-        uint32_t k = incl - pc;
-        for (uint32_t m = word; m; m &= m - 1) buf[wave][k++] = wi * 32 + (uint32_t)__builtin_ctz(m);
-        wave_lds_sync();
-        for (uint32_t s0 = 0; s0 < tot; s0 += 64) {
-            const uint32_t j = s0 + lane;
-            uint32_t v = 0, deg = 0;
-            if (j < tot) {
-                v = buf[wave][j];
-                deg = row_end<MODE>(a, v) - a.row_ptr[v];
-            }
-            const uint32_t keep = deg > 0 ? 1u : 0u;
-            uint32_t item, edge;
-            wave_reserve2(keep, deg, &a.cnt->packed[p], item, edge);
-            if (keep) {
-                a.fv[item] = v;
-                a.fo[item] = edge;
-            }
-        }
-        wave_lds_sync();
-    }
-}
+// One 64-edge step of a walker over the frontier's edge range: the lane's
+// edge t = base + lane, its source vertex's CSR position and value.
+struct Step {
+    uint32_t e, split, x, v, cand;
+    bool act, want;
+};
 
 template <int A, int MODE, int MW, bool ST>
 __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int p, uint32_t* slot) {
+    constexpr int NW = kWalkers;
     const unsigned long long cx = expand_prologue(a.cnt, p, slot);
     const uint32_t n = items_of(cx), T = edges_of(cx);
     if (T == 0) return;
     const uint32_t lane = lane_id();
     const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
     const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
-    uint64_t Rw = (T + nw - 1) / nw;
+    // a wave owns NW equal sub-slices of [0, T), each a multiple of 64 edges
+    uint64_t Rw = (T + nw * NW - 1) / (nw * NW);
     Rw = (Rw + 63) & ~63ull;
-    const uint64_t a0 = gw * Rw;
-    if (a0 >= T) return;
-    const uint32_t a1 = (uint32_t)(a0 + Rw < T ? a0 + Rw : T);
-    count_visits<ST>(a, lane == 0 ? a1 - (uint32_t)a0 : 0u);
-    uint32_t cur = wave_search(a.fo, n, (uint32_t)a0);
-    for (uint32_t base = (uint32_t)a0; base < a1; base += 64) {
-        const uint32_t idx = cur + lane;
-        const uint32_t off = idx < n ? a.fo[idx] : 0xFFFFFFFFu;
-        uint32_t rb = 0, sp = 0, xv = 0;
-        if (off <= base + 63) {  // only the vertices this step can touch
-            const uint32_t v = a.fv[idx];
-            rb = a.row_ptr[v];
-            sp = a.row_split[v];
-            xv = a.R[v];
-        }
-        const uint32_t t = base + lane;
-        int j = 0;
+    uint32_t base[NW], end[NW], cur[NW];
 #pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            const uint32_t o = __shfl(off, j + step, 64);
-            if (o <= t) j += step;
+    for (int j = 0; j < NW; ++j) {
+        const uint64_t b0 = (gw * NW + j) * Rw;
+        base[j] = (uint32_t)(b0 < T ? b0 : T);
+        end[j] = (uint32_t)(b0 + Rw < T ? b0 + Rw : T);
+    }
+    if (base[0] >= end[0]) return;
+    count_visits<ST>(a, lane == 0 ? end[NW - 1] - base[0] : 0u);
+#pragma unroll
+    for (int j = 0; j < NW; ++j) cur[j] = base[j] < end[j] ? wave_search(a.fo, n, base[j]) : 0u;
+    while (base[0] < end[0]) {
+        Step st[NW];
+        uint32_t off[NW];
+        // loads of every walker first, so their latencies overlap
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            st[j].act = false;
+            st[j].want = false;
+            off[j] = 0xFFFFFFFFu;
+            if (base[j] >= end[j]) continue;
+            const uint32_t idx = cur[j] + lane;
+            off[j] = idx < n ? stream_load(a.fo + idx) : 0xFFFFFFFFu;
+            uint32_t dl = 0, sp = 0, xv = 0;
+            if (off[j] <= base[j] + 63) {
+                dl = stream_load(a.fd + idx);
+                if (MODE != 0) sp = stream_load(a.fs + idx);
+                xv = a.R[stream_load(a.fv + idx)];
+            }
+            const uint32_t t = base[j] + lane;
+            int o = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const uint32_t q = __shfl(off[j], o + step, 64);
+                if (q <= t) o += step;
+            }
+            st[j].e = t + __shfl(dl, o, 64);
+            st[j].split = MODE != 0 ? __shfl(sp, o, 64) : 0u;
+            st[j].x = __shfl(xv, o, 64);
+            st[j].act = t < end[j];
         }
-        const uint32_t e = __shfl(rb, j, 64) + (t - __shfl(off, j, 64));
-        const uint32_t spj = __shfl(sp, j, 64);
-        const uint32_t xs = __shfl(xv, j, 64);
-        if (t < a1) relax<A, MODE, MW>(a, e, spj, xs, W);
-        // next step starts at the owner of base + 64: one of cur .. cur + 64,
-        // since every listed vertex has at least one edge
-        const uint32_t nb = base + 64;
-        const uint32_t have = (uint32_t)__popcll(__ballot(off <= nb));
-        uint32_t adv = have - 1;
-        if (have == 64 && cur + 64 < n && a.fo[cur + 64] <= nb) adv = 64;
-        cur += adv;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            if (!st[j].act) continue;
+            if (MODE != 0 && st[j].e >= st[j].split && !partial_in<MODE, MW>(a.mask, st[j].e, W)) continue;
+            st[j].v = stream_load(a.col + st[j].e);
+            st[j].cand = Alg<A>::extend(st[j].x, stream_load(a.wgt + st[j].e));
+            st[j].want = true;
+        }
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+            if (st[j].want) st[j].want = Alg<A>::better(st[j].cand, a.R[st[j].v]);
+        // then the updates
+        uint32_t nup = 0;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            if (!st[j].want) continue;
+            Alg<A>::improve_nr(&a.R[st[j].v], st[j].cand);
+            mark(a.flags, st[j].v);
+            ++nup;
+        }
+        if (ST) {
+            const uint32_t su = wave_sum(nup);
+            if (lane == 0 && su) atomicAdd(&a.stats[4], (unsigned long long)su);
+        }
+        // advance: the next step starts at the owner of base + 64
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            if (base[j] >= end[j]) continue;
+            const uint32_t nb = base[j] + 64;
+            const uint32_t have = (uint32_t)__popcll(__ballot(off[j] <= nb));
+            uint32_t adv = have - 1;
+            if (have == 64 && cur[j] + 64 < n && a.fo[cur[j] + 64] <= nb) adv = 64;
+            cur[j] += adv;
+            base[j] = nb;
+        }
     }
 }
 
-// Start of a solve from one source vertex.
-__global__ void k_seed_source(uint32_t* R, uint32_t* bitmap, uint32_t source, uint32_t at_source) {
+// Start of a solve: the threshold starts one step above the best key.
+__global__ void k_solve_start(FrontierCounters* c, uint32_t delta, uint32_t* R, uint8_t* flags, uint32_t source,
+                              uint32_t at_source) {
     if (threadIdx.x == 0) {
-        R[source] = at_source;
-        bitmap[source >> 5] |= 1u << (source & 31);
+        c->delta = delta;
+        c->thr = delta ? delta : 0xFFFFFFFFu;
+        c->fmin[0] = c->fmin[1] = 0xFFFFFFFFu;
+        if (R) {
+            R[source] = at_source;
+            flags[source] = 1;
+        }
     }
 }
 
@@ -205,7 +270,7 @@ __global__ void __launch_bounds__(kBlock) k_seed_partial(SolveArgs a, Mask<MW> W
                 const uint32_t cand = Alg<A>::extend(a.R[p_src[q]], a.wgt[e]);
                 if (Alg<A>::better(cand, a.R[v])) {
                     Alg<A>::improve_nr(&a.R[v], cand);
-                    mark(a.bitmap, v);
+                    mark(a.flags, v);
                 }
             }
         }
@@ -215,10 +280,9 @@ __global__ void __launch_bounds__(kBlock) k_seed_partial(SolveArgs a, Mask<MW> W
 
 template <int A, int MODE, int MW, bool ST>
 uint64_t frontier_loop(SolveArgs a, const Mask<MW>& W, Frontier& f, hipStream_t s, uint64_t max_iters) {
-    const uint32_t nwords = (a.V + 31) >> 5;
-    const uint32_t cblocks = grid_for((nwords + 63) / 64, kBlock / 64, 4096);
+    const uint32_t cblocks = grid_for(a.V, kCompactIds, 4096);
     auto issue = [&](uint64_t, int p, bool first, uint32_t* slot) {
-        EVQ_LAUNCH("solve_compact", k_compact_frontier<MODE>, cblocks, kBlock, s, a, p, first ? 1 : 0);
+        EVQ_LAUNCH("solve_compact", (k_compact_frontier<A, MODE>), cblocks, kCompactBlock, s, a, p, first ? 1 : 0);
         EVQ_LAUNCH("solve_expand", (k_expand<A, MODE, MW, ST>), kExpandBlocks, kBlock, s, a, W, p, slot);
     };
     return drive_loop(issue, f.p, s, max_iters, "bound solve");
@@ -239,9 +303,11 @@ SolveArgs make_args(const Graph& g, const Frontier& f, uint32_t* R) {
     a.wgt = g.wgt;
     a.mask = g.mask;
     a.R = R;
-    a.bitmap = f.bitmap;
-    a.fv = f.fv;
+    a.flags = f.flags;
     a.fo = f.fo;
+    a.fd = f.fd;
+    a.fs = f.fs;
+    a.fv = f.fv;
     a.cnt = f.cnt;
     a.stats = f.stats;
     a.V = g.V;
@@ -252,7 +318,7 @@ template <int A, int MW, bool ST>
 uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t* R, Frontier& f, hipStream_t s) {
     SolveArgs a = make_args(g, f, R);
     fill_u32(R, g.V, Alg<A>::unreached, s);
-    EVQ_LAUNCH("solve_seed_source", k_seed_source, 1, 64, s, R, f.bitmap, source, Alg<A>::at_source);
+    EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, f.delta, R, f.flags, source, Alg<A>::at_source);
     if (W.full) return frontier_loop<A, 0, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
     return frontier_loop<A, 1, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
 }
@@ -260,6 +326,7 @@ uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t*
 template <int A, int MW, bool ST>
 uint64_t solve_cup_t(const Graph& g, const Window& W, uint32_t* R, Frontier& f, hipStream_t s) {
     SolveArgs a = make_args(g, f, R);
+    EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, f.delta, (uint32_t*)nullptr, f.flags, 0u, 0u);
     if (g.n_partial)
         EVQ_LAUNCH("solve_seed_partial", (k_seed_partial<A, MW, ST>), grid_for(g.n_partial, kBlock, 16384), kBlock, s,
                    a, window_mask<MW>(W), g.p_src, g.p_eid, (uint32_t)g.n_partial);
@@ -288,21 +355,34 @@ uint64_t dispatch_cup(uint32_t algo, const Graph& g, const Window& W, uint32_t* 
 }
 
 __global__ void k_init_frontier(FrontierCounters* c, unsigned long long* st, int n) {
-    if (threadIdx.x == 0) c->packed[0] = c->packed[1] = 0ull;
+    if (threadIdx.x == 0) {
+        c->packed[0] = c->packed[1] = 0ull;
+        c->far[0] = c->far[1] = 0u;
+        c->fmin[0] = c->fmin[1] = 0xFFFFFFFFu;
+        c->thr = 0xFFFFFFFFu;
+        c->delta = 0u;
+    }
     if ((int)threadIdx.x < n) st[threadIdx.x] = 0ull;
 }
 
 }  // namespace
 
-Frontier make_frontier(const Graph& g, Arena& ar, hipStream_t s) {
+Frontier make_frontier(const Graph& g, Workspace& ws, hipStream_t s) {
     Frontier f;
-    const uint64_t nwords = ((uint64_t)g.V + 31) / 32;
-    f.bitmap = ar.alloc<uint32_t>(nwords);
-    f.fv = ar.alloc<uint32_t>(g.V);
-    f.fo = ar.alloc<uint32_t>(g.V);
-    f.cnt = ar.alloc<FrontierCounters>(1);
-    f.stats = ar.alloc<unsigned long long>(8);
-    fill_u32(f.bitmap, nwords, 0u, s);
+    const uint64_t nflag = flag_bytes(g.V);
+    f.flags = ws.buf<uint8_t>(Workspace::kFlags, nflag);
+    f.fo = ws.buf<uint32_t>(Workspace::kFo, g.V);
+    f.fd = ws.buf<uint32_t>(Workspace::kFd, g.V);
+    f.fs = ws.buf<uint32_t>(Workspace::kFs, g.V);
+    f.fv = ws.buf<uint32_t>(Workspace::kFv, g.V);
+    char* ctl = ws.buf<char>(Workspace::kControl, 512);
+    f.cnt = reinterpret_cast<FrontierCounters*>(ctl);
+    f.stats = reinterpret_cast<unsigned long long*>(ctl + 128);
+    f.aux = reinterpret_cast<unsigned long long*>(ctl + 256);
+    // flags are clear after every completed loop; clear them after a failure
+    if (ws.fresh_flags || ws.in_use) fill_u32(reinterpret_cast<uint32_t*>(f.flags), nflag / 4, 0u, s);
+    ws.fresh_flags = false;
+    ws.in_use = true;
     EVQ_LAUNCH("query_init", k_init_frontier, 1, 64, s, f.cnt, f.stats, 8);
     f.p = 0;
     return f;

@@ -231,3 +231,22 @@ def test_determinism_repeat(evq):
         a = gpu_values(g, oracle.SSSP, 0, 0, 8)
         for _ in range(3):
             assert np.array_equal(a, gpu_values(g, oracle.SSSP, 0, 0, 8))
+
+
+@pytest.mark.parametrize("delta", [1, 7, 60])
+@pytest.mark.parametrize("algo", ALGOS)
+def test_near_far_scheduling(evq, algo, delta, monkeypatch):
+    # near/far ordering of the bound solves changes the schedule, never the values
+    monkeypatch.setenv("EVQ_DELTA", str(delta))
+    for seed in (1, 2):
+        inst = synth.config_instance("small", seed=seed)
+        trip, bits = oracle.replay(inst)
+        want = oracle.window_values(inst, algo, 0, 0, inst.K, replayed=(trip, bits))
+        rc_o, ru_o = oracle.bounds(inst.num_vertices, trip, bits, algo, 0, 0, inst.K)
+        with _graph(evq, inst) as g:
+            got = gpu_values(g, algo, 0, 0, inst.K)
+            rc, ru = gpu_bounds(g, algo, 0, 0, inst.K)
+            sub = gpu_values(g, algo, 0, 2, 5)
+        assert_equal_values(got, want, f"delta {delta} seed {seed}")
+        assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
+        assert_equal_values(sub, want[:, 2:7], f"delta {delta} seed {seed} window [2,7)")
