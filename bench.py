@@ -43,12 +43,28 @@ def snapshot_edge_counts(ex, K):
     return counts
 
 
-def relax_algorithmic_bytes(st, L):
-    """Bytes the multi-snapshot relaxer must move: per edge visit one record
-    (dst, w, lane mask), per lane relaxation one 4-byte read of the destination
-    value, per frontier task the source row of L values."""
-    rec = 16 if L <= 64 else 24
-    return st["edge_visits_relax"] * rec + st["lane_relaxations"] * 4
+def algorithmic_bytes(kernel, st, L, V):
+    """Bytes a kernel's work must move at minimum, from the query's counters.
+
+    Bound-solve expansion: per edge visit the edge's (col, w) pair and one
+    4-byte value read; per improving update one 4-byte atomic write; per
+    frontier vertex its 16-byte item (edge offset, row position, vertex) and
+    its value.  Relaxer: per edge visit one record (dst, w, lane mask), per
+    (edge, snapshot) evaluation one 4-byte destination read.  Writeback: the
+    V x L output, two 4-byte reads per vertex and the unstable rows.
+    """
+    if kernel == "solve_expand_cap_all":
+        return 12 * st["edges_cap"] + 4 * st["updates_cap"] + 16 * st["items_cap"]
+    if kernel == "solve_expand_cap":
+        return 12 * st["edges_cap"] + 4 * st["updates_cap"] + 20 * st["items_cap"]
+    if kernel == "solve_expand_cup":
+        return 12 * st["edges_cup"] + 4 * st["updates_cup"] + 20 * st["items_cup"]
+    if kernel == "relax":
+        rec = 16 if L <= 64 else 24
+        return rec * st["edge_visits_relax"] + 4 * st["lane_relaxations"]
+    if kernel == "writeback":
+        return 4 * V * L + 8 * V + 4 * L * st["n_unstable"]
+    return None
 
 
 def main():
@@ -131,18 +147,22 @@ def main():
         kernels = evq.timing_report()
         evq.timing_enable(False)
         evq.timing_reset()
-        dom = max(kernels.items(), key=lambda kv: kv[1][1])
-        log("[bench] kernel times (3 queries): " +
+        log("[bench] kernel times per query: " +
             ", ".join(f"{k}={v[1] / reps:.3f}ms/{v[0] // reps}" for k, v in sorted(kernels.items(),
                                                                                  key=lambda kv: -kv[1][1])))
-        if "relax" in kernels:
-            launches, tot_ms = kernels["relax"]
-            byts = relax_algorithmic_bytes(st, L) * reps
-            ach = byts / (tot_ms / 1000.0) / 1e9
-            roof = {"bound": "hbm", "kernel": "relax", "achieved": round(ach, 2), "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-                    "avg_launch_us": round(tot_ms * 1000.0 / launches, 3),
-                    "dominant_kernel": dom[0]}
+        dom, (launches, tot_ms) = max(kernels.items(), key=lambda kv: kv[1][1])
+        byts = algorithmic_bytes(dom, st, L, inst.num_vertices)
+        if byts is not None:
+            ach = byts * reps / (tot_ms / 1000.0) / 1e9
+            roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                    "avg_launch_us": round(tot_ms * 1000.0 / launches, 3), "launches_per_query": launches // reps,
+                    "algorithmic_bytes_per_query": int(byts)}
+        relax_b = algorithmic_bytes("relax", st, L, inst.num_vertices)
+        if "relax" in kernels and relax_b:
+            rl, rt = kernels["relax"]
+            roof_relax = relax_b * reps / (rt / 1000.0) / 1e9
+            log(f"[bench] relaxer: {roof_relax:.1f} GB/s algorithmic over {rl // reps} launches/query")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -150,8 +170,8 @@ def main():
         t = time.perf_counter()
         trip, bits = oracle.replay(inst)
         replay_s = time.perf_counter() - t
-        sample = list(range(b, b + min(L, 16)))
-        nthreads = os.cpu_count() or 1
+        sample = list(range(b, b + L))
+        nthreads = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)) or 1)
         t = time.perf_counter()
         want = oracle.query(inst.num_vertices, trip, bits, algo, source, sample, nthreads)
         cpu_s = time.perf_counter() - t

@@ -100,6 +100,8 @@ typedef struct {
     uint64_t edge_visits_relax;           /* edge visits of the multi-snapshot relaxation */
     uint64_t lane_relaxations;            /* (edge visit, snapshot) pairs evaluated there */
     uint64_t updates_cap, updates_cup;    /* improving value updates of the two bound solves */
+    uint64_t items_cap, items_cup;        /* frontier vertices expanded by the two bound solves */
+    uint64_t seed_visits_cup;             /* partial edges examined to seed the union solve */
 } evq_query_stats;
 
 /*

@@ -20,6 +20,7 @@ struct Frontier {
     unsigned long long* aux = nullptr;    // 128 bytes of scratch counters for the reduction
     int p = 0;                            // parity of the next compaction (continues across phases)
     uint32_t delta = 0;                   // near/far step of the bound solves (0: off)
+    uint64_t items = 0;                   // frontier items processed so far (published counts)
 };
 
 // Near/far step for a query: EVQ_DELTA overrides, else a per-algorithm default.

@@ -237,15 +237,18 @@ class HostSlots {
 
 // Issues iterations (issue(it, parity, first)) `depth` ahead of the one whose
 // published count it waits for; stops at the first iteration with count 0.
-// Returns the number of non-empty iterations; f_parity is advanced past every
-// issued iteration.
+// Returns the number of non-empty iterations and adds the published counts
+// (items processed) to *items; f_parity is advanced past every issued
+// iteration.
 template <typename IssueFn>
-uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_iters, const char* what);
+uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_iters, const char* what,
+                    uint64_t* items = nullptr);
 
 void wait_slot(volatile uint32_t* slot, hipStream_t s, const char* what);
 
 template <typename IssueFn>
-uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_iters, const char* what) {
+uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_iters, const char* what,
+                    uint64_t* items) {
     constexpr uint64_t kDepth = 3;
     HostSlots& hs = HostSlots::get();
     uint64_t issued = 0, consumed = 0;
@@ -260,6 +263,7 @@ uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_it
         volatile uint32_t* slot = hs.host() + (consumed % HostSlots::kSlots);
         wait_slot(slot, s, what);
         if (*slot == 0) break;
+        if (items) *items += *slot;
         if (++consumed > max_iters) fail(EVQ_ENOCONV, std::string(what) + " exceeded its iteration cap");
     }
     return consumed;

@@ -476,16 +476,18 @@ __global__ void k_xinit(const uint32_t* __restrict__ ulist, uint32_t nU, const u
         X[k] = rcap[ulist[k / LG]];
 }
 
+// Plain evaluation: every vertex starts unreached except the source (compact
+// ids follow the reduction's order, so the source is found through ulist).
 template <int LG>
-__global__ void k_xinit_plain(uint32_t V, uint32_t source, uint32_t unreached, uint32_t at_source,
-                              uint32_t* __restrict__ X) {
-    const uint64_t n = (uint64_t)V * LG;
+__global__ void k_xinit_plain(const uint32_t* __restrict__ ulist, uint32_t nU, uint32_t source, uint32_t unreached,
+                              uint32_t at_source, uint32_t* __restrict__ X) {
+    const uint64_t n = (uint64_t)nU * LG;
     for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
-        X[k] = (k / LG) == source ? at_source : unreached;
+        X[k] = ulist[k / LG] == source ? at_source : unreached;
 }
 
-__global__ void k_mark_one(uint8_t* flags, uint32_t c) {
-    if (threadIdx.x == 0) flags[c] = 1;
+__global__ void k_mark_source(uint8_t* flags, const uint32_t* __restrict__ cid_of, uint32_t source) {
+    if (threadIdx.x == 0) flags[cid_of[source]] = 1;
 }
 
 // values[v * L + i], four values per lane (L % 4 == 0, 16-byte aligned rows).
@@ -645,9 +647,9 @@ void relax_phase(const Graph& g, const Window& W, const uint32_t* rcap, const Re
     ra.stats = f.stats;
     ra.nU = red.nU;
     if (plain) {
-        EVQ_LAUNCH("relax_xinit", k_xinit_plain<LG>, grid_for((uint64_t)red.nU * LG, 256 * 4), 256, s, g.V, source,
-                   Alg<A>::unreached, Alg<A>::at_source, X);
-        EVQ_LAUNCH("relax_seed", k_mark_one, 1, 64, s, f.flags, source);
+        EVQ_LAUNCH("relax_xinit", k_xinit_plain<LG>, grid_for((uint64_t)red.nU * LG, 256 * 4), 256, s, red.ulist,
+                   red.nU, source, Alg<A>::unreached, Alg<A>::at_source, X);
+        EVQ_LAUNCH("relax_seed", k_mark_source, 1, 64, s, f.flags, red.cid_of, source);
     } else {
         EVQ_LAUNCH("relax_xinit", k_xinit<LG>, grid_for((uint64_t)red.nU * LG, 256 * 4), 256, s, red.ulist, red.nU,
                    rcap, X);
@@ -752,11 +754,14 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
         qo.st.edges_cap = read_stat(f.stats, 0, s);
         qo.st.updates_cap = read_stat(f.stats, 4, s);
     }
+    qo.st.items_cap = f.items;
     qo.st.iters_cup = solve_cup(g, algo, W, rcup, f, s, st);
     tm.mark();
+    qo.st.items_cup = f.items - qo.st.items_cap;
     if (st) {
         qo.st.edges_cup = read_stat(f.stats, 0, s) - qo.st.edges_cap;
         qo.st.updates_cup = read_stat(f.stats, 4, s) - qo.st.updates_cap;
+        qo.st.seed_visits_cup = read_stat(f.stats, 5, s);
     }
     if (bounds_only) {
         EVQ_HIP(hipStreamSynchronize(s));

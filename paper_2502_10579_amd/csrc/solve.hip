@@ -274,18 +274,22 @@ __global__ void __launch_bounds__(kBlock) k_seed_partial(SolveArgs a, Mask<MW> W
                 }
             }
         }
-        count_visits<ST>(a, act ? 1u : 0u);
+        if (ST) {
+            const uint32_t sv = wave_sum(act ? 1u : 0u);
+            if (lane_id() == 0 && sv) atomicAdd(&a.stats[5], (unsigned long long)sv);
+        }
     }
 }
 
 template <int A, int MODE, int MW, bool ST>
 uint64_t frontier_loop(SolveArgs a, const Mask<MW>& W, Frontier& f, hipStream_t s, uint64_t max_iters) {
     const uint32_t cblocks = grid_for(a.V, kCompactIds, 4096);
+    static const char* names[3] = {"solve_expand_cap_all", "solve_expand_cap", "solve_expand_cup"};
     auto issue = [&](uint64_t, int p, bool first, uint32_t* slot) {
         EVQ_LAUNCH("solve_compact", (k_compact_frontier<A, MODE>), cblocks, kCompactBlock, s, a, p, first ? 1 : 0);
-        EVQ_LAUNCH("solve_expand", (k_expand<A, MODE, MW, ST>), kExpandBlocks, kBlock, s, a, W, p, slot);
+        EVQ_LAUNCH(names[MODE], (k_expand<A, MODE, MW, ST>), kExpandBlocks, kBlock, s, a, W, p, slot);
     };
-    return drive_loop(issue, f.p, s, max_iters, "bound solve");
+    return drive_loop(issue, f.p, s, max_iters, "bound solve", &f.items);
 }
 
 template <int MW>

@@ -250,3 +250,18 @@ def test_near_far_scheduling(evq, algo, delta, monkeypatch):
         assert_equal_values(got, want, f"delta {delta} seed {seed}")
         assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
         assert_equal_values(sub, want[:, 2:7], f"delta {delta} seed {seed} window [2,7)")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_query_many_blocks_method_and_plain(evq, algo):
+    # enough vertices that compact ids are assigned by many blocks in any order
+    inst = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=31)
+    src = synth.pick_sources(inst, 1, seed=3)[0]
+    trip, bits = oracle.replay(inst)
+    for (b, L) in [(0, 16), (3, 9)]:
+        want = oracle.window_values(inst, algo, src, b, L, replayed=(trip, bits))
+        with _graph(evq, inst) as g:
+            got = gpu_values(g, algo, src, b, L)
+            plain = gpu_values(g, algo, src, b, L, plain=True)
+        assert_equal_values(got, want, f"algo {algo} [{b},{b + L})")
+        assert_equal_values(plain, want, f"plain algo {algo} [{b},{b + L})")
