@@ -42,10 +42,10 @@ enum { O_SSSP = 0, O_BFS = 1, O_SSWP = 2, O_SSNP = 3 };
 
 typedef struct {
     uint32_t src, dst, w;
-    int32_t present;
-    int32_t since;
+    int16_t since;    /* snapshot the current presence started at */
+    uint8_t present;
+    uint8_t used;     /* 0 = free slot */
     uint64_t bits[2];
-    int64_t used; /* 0 = free slot */
 } rec_t;
 
 typedef struct { rec_t* r; uint64_t mask; uint64_t n; } tmap;
@@ -80,48 +80,87 @@ static void set_bits(uint64_t bits[2], int from, int to) {
     for (int t = from; t < to; ++t) bits[t >> 6] |= 1ULL << (t & 63);
 }
 
+/* Which of P partitions a triple belongs to (each partition replays alone). */
+static uint32_t part_of(uint32_t s, uint32_t d, uint32_t w, uint32_t P) {
+    return (uint32_t)(hash3(s, d, w) >> 40) % P;
+}
+
 /*
  * Replay the batches.  Inputs are (n, 3) uint32 triples; batch i's deletions
  * are dels[del_off[i] .. del_off[i+1]) and its additions likewise.  Output:
  * every distinct triple ever present, with bit t of its two-word mask set iff
  * the triple is in snapshot t.  Returns the triple count (<= cap) or -1.
+ *
+ * A triple's presence depends only on its own events, so the triples are
+ * split into partitions by hash and each thread replays one partition, in
+ * event order, with its own map.
  */
 int64_t oracle_replay(uint32_t K, const uint32_t* base, uint64_t n_base,
                       const uint32_t* dels, const uint64_t* del_off,
                       const uint32_t* adds, const uint64_t* add_off,
                       uint32_t* out_trip, uint64_t* out_bits, uint64_t cap) {
     if (K > 128) return -1;
-    uint64_t total = n_base + add_off[K];
-    uint64_t hcap = 16;
-    while (hcap < 2 * total + 16) hcap <<= 1;
-    tmap m = {(rec_t*)calloc(hcap, sizeof(rec_t)), hcap - 1, 0};
-    if (!m.r) return -1;
-    for (uint64_t j = 0; j < n_base; ++j) {
-        rec_t* r = tmap_find(&m, base[3 * j], base[3 * j + 1], base[3 * j + 2], 1);
-        if (!r->present) { r->present = 1; r->since = 0; }
-    }
-    for (uint32_t i = 0; i < K; ++i) {
-        for (uint64_t j = del_off[i]; j < del_off[i + 1]; ++j) {
-            rec_t* r = tmap_find(&m, dels[3 * j], dels[3 * j + 1], dels[3 * j + 2], 0);
-            if (r && r->present) { set_bits(r->bits, r->since, (int)i); r->present = 0; }
+    const uint32_t P = (uint32_t)omp_get_max_threads();
+    const uint64_t total = n_base + add_off[K];
+    uint64_t* counts = (uint64_t*)calloc(P + 1, sizeof(uint64_t));
+    tmap* maps = (tmap*)calloc(P, sizeof(tmap));
+    int err = 0;
+#pragma omp parallel num_threads(P)
+    {
+        const uint32_t me = (uint32_t)omp_get_thread_num();
+        uint64_t hcap = 16;
+        while (hcap < 2 * (total / P + 1) + 16) hcap <<= 1;
+        tmap m = {(rec_t*)calloc(hcap, sizeof(rec_t)), hcap - 1, 0};
+        if (!m.r) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+            for (uint64_t j = 0; j < n_base; ++j) {
+                const uint32_t* e = base + 3 * j;
+                if (part_of(e[0], e[1], e[2], P) != me) continue;
+                rec_t* r = tmap_find(&m, e[0], e[1], e[2], 1);
+                if (!r->present) { r->present = 1; r->since = 0; }
+            }
+            for (uint32_t i = 0; i < K; ++i) {
+                for (uint64_t j = del_off[i]; j < del_off[i + 1]; ++j) {
+                    const uint32_t* e = dels + 3 * j;
+                    if (part_of(e[0], e[1], e[2], P) != me) continue;
+                    rec_t* r = tmap_find(&m, e[0], e[1], e[2], 0);
+                    if (r && r->present) { set_bits(r->bits, r->since, (int)i); r->present = 0; }
+                }
+                for (uint64_t j = add_off[i]; j < add_off[i + 1]; ++j) {
+                    const uint32_t* e = adds + 3 * j;
+                    if (part_of(e[0], e[1], e[2], P) != me) continue;
+                    rec_t* r = tmap_find(&m, e[0], e[1], e[2], 1);
+                    if (!r->present) { r->present = 1; r->since = (int16_t)i; }
+                }
+            }
+            for (uint64_t i = 0; i <= m.mask; ++i)
+                if (m.r[i].used && m.r[i].present) set_bits(m.r[i].bits, m.r[i].since, (int)K);
         }
-        for (uint64_t j = add_off[i]; j < add_off[i + 1]; ++j) {
-            rec_t* r = tmap_find(&m, adds[3 * j], adds[3 * j + 1], adds[3 * j + 2], 1);
-            if (!r->present) { r->present = 1; r->since = (int)i; }
+        maps[me] = m;
+        counts[me + 1] = m.n;
+#pragma omp barrier
+#pragma omp single
+        {
+            for (uint32_t t = 0; t < P; ++t) counts[t + 1] += counts[t];
         }
+        if (!err && counts[P] <= cap) {
+            uint64_t n = counts[me];
+            for (uint64_t i = 0; m.r && i <= m.mask; ++i) {
+                rec_t* r = &m.r[i];
+                if (!r->used) continue;
+                out_trip[3 * n] = r->src; out_trip[3 * n + 1] = r->dst; out_trip[3 * n + 2] = r->w;
+                out_bits[2 * n] = r->bits[0]; out_bits[2 * n + 1] = r->bits[1];
+                n++;
+            }
+        }
+        free(m.r);
     }
-    if (m.n > cap) { free(m.r); return -1; }
-    uint64_t n = 0;
-    for (uint64_t i = 0; i <= m.mask; ++i) {
-        rec_t* r = &m.r[i];
-        if (!r->used) continue;
-        if (r->present) set_bits(r->bits, r->since, (int)K);
-        out_trip[3 * n] = r->src; out_trip[3 * n + 1] = r->dst; out_trip[3 * n + 2] = r->w;
-        out_bits[2 * n] = r->bits[0]; out_bits[2 * n + 1] = r->bits[1];
-        n++;
-    }
-    free(m.r);
-    return (int64_t)n;
+    int64_t n = (err || counts[P] > cap) ? -1 : (int64_t)counts[P];
+    free(counts);
+    free(maps);
+    return n;
 }
 
 /* ------------------------------------------------------------------ solves */
