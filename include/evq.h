@@ -171,6 +171,82 @@ evq_status evq_query_bounds(const evq_graph* g, uint32_t algo, uint32_t source, 
 evq_status evq_query_plain(const evq_graph* g, uint32_t algo, uint32_t source, uint32_t win_begin,
                            uint32_t win_len, uint32_t* d_values, evq_query_stats* stats, void* stream);
 
+/*
+ * Batched queries (a systems layer over Algorithm 1 and Algorithm 2; the
+ * paper answers one query at a time).  Queries of one algorithm share their
+ * bound solves: up to 64 of them are solved together, one query per lane of
+ * a wave, over the shared versioned graph (values laid out [vertex][64]),
+ * each lane testing the edge masks against its own window.  Each query's
+ * reduction and multi-snapshot relaxation then run on a pool of worker
+ * streams, concurrently, and leave a compact result.
+ */
+typedef struct {
+    uint32_t algo, source, win_begin, win_len;  /* as the arguments of evq_query */
+} evq_query_desc;
+
+/*
+ * Compact result of one query (library-owned device memory until
+ * evq_result_free).  By Theorem 2 every vertex outside the unstable set has
+ * the value d_rcap[v] in every snapshot of the window; unstable vertex
+ * d_unstable[c] has in snapshot win_begin + i the value
+ * d_x[c * row_stride + i] (i < win_len).  d_unstable is in no particular
+ * order.  d_unstable / d_x are NULL when n_unstable == 0.
+ */
+typedef struct {
+    uint32_t algo, source, win_begin, win_len;
+    uint32_t num_vertices;
+    uint32_t n_unstable;
+    uint32_t row_stride;       /* uint32 per row of d_x, >= win_len */
+    uint32_t reserved;
+    const uint32_t* d_rcap;    /* num_vertices values on the window's intersection graph */
+    const uint32_t* d_unstable;
+    const uint32_t* d_x;
+} evq_result;
+
+/* Execution choices of evq_query_batch (0 in a field: the library default). */
+typedef struct {
+    uint32_t lanes;      /* 1: shared bound solves, one query per lane; 2: one bound solve per query */
+    uint32_t chunk;      /* edges per wave task of the shared bound solves: 4, 8 or 16 */
+    uint32_t blocks;     /* workgroups of 256 threads per expansion launch, 64 .. 16384 */
+    uint32_t reserved;
+} evq_batch_config;
+
+/*
+ * Answer n queries.  q: n host descriptors, each validated as evq_query's
+ * arguments before any device work (EVQ_EINVAL / EVQ_ERANGE name the first
+ * bad one).  results: n host structs, filled on success (on failure they are
+ * zeroed and nothing stays allocated).  stats: NULL or n host structs
+ * (per-query counters; the bound-solve fields of queries solved together
+ * are those of their shared solve).  The work runs on the library's worker
+ * streams, after the work already queued on `stream`; `stream` is made to
+ * wait for all of it, so the results are complete when `stream` reaches the
+ * point of the call.  The call itself returns once every frontier loop has
+ * drained.  Queries of any mix of algorithms, sources and windows may be
+ * passed; 1 <= n <= 65536.
+ */
+evq_status evq_query_batch(const evq_graph* g, const evq_query_desc* q, uint32_t n, evq_result* results,
+                           evq_query_stats* stats, void* stream);
+
+/*
+ * Expand a compact result to values[V][win_len] in the caller's device
+ * buffer (the layout of evq_query's d_values).  Ordered on `stream`, which
+ * must be ordered after the stream the result was produced for.
+ * Errors: EVQ_EINVAL (NULL arguments or an empty result), EVQ_EDEVICE.
+ */
+evq_status evq_result_expand(const evq_result* r, uint32_t* d_values, void* stream);
+
+/*
+ * Release a result's device memory, ordered on `stream` (work already queued
+ * there that reads the result completes first; work on other streams must be
+ * ordered before it by the caller).  The struct is zeroed; a zeroed struct
+ * is accepted.  EVQ_EINVAL on NULL.
+ */
+evq_status evq_result_free(evq_result* r, void* stream);
+
+/* Read / replace the execution choices used by evq_query_batch on this process. */
+evq_status evq_batch_config_get(evq_batch_config* c);
+evq_status evq_batch_config_set(const evq_batch_config* c);
+
 /* Release the handle and its device memory.  NULL is allowed. */
 void evq_free(evq_graph* g);
 

@@ -53,6 +53,23 @@ class QueryStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class QueryDesc(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_uint32), ("source", ctypes.c_uint32), ("win_begin", ctypes.c_uint32),
+                ("win_len", ctypes.c_uint32)]
+
+
+class ResultC(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_uint32), ("source", ctypes.c_uint32), ("win_begin", ctypes.c_uint32),
+                ("win_len", ctypes.c_uint32), ("num_vertices", ctypes.c_uint32), ("n_unstable", ctypes.c_uint32),
+                ("row_stride", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("d_rcap", ctypes.c_void_p),
+                ("d_unstable", ctypes.c_void_p), ("d_x", ctypes.c_void_p)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_uint32), ("chunk", ctypes.c_uint32), ("blocks", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
@@ -73,6 +90,17 @@ for _name in ("evq_query", "evq_query_plain"):
 _lib.evq_query_bounds.restype = ctypes.c_int32
 _lib.evq_query_bounds.argtypes = [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _P, _P,
                                   _P]
+_lib.evq_query_batch.restype = ctypes.c_int32
+_lib.evq_query_batch.argtypes = [_P, ctypes.POINTER(QueryDesc), ctypes.c_uint32, ctypes.POINTER(ResultC),
+                                 ctypes.POINTER(QueryStats), _P]
+_lib.evq_result_expand.restype = ctypes.c_int32
+_lib.evq_result_expand.argtypes = [ctypes.POINTER(ResultC), _P, _P]
+_lib.evq_result_free.restype = ctypes.c_int32
+_lib.evq_result_free.argtypes = [ctypes.POINTER(ResultC), _P]
+_lib.evq_batch_config_get.restype = ctypes.c_int32
+_lib.evq_batch_config_get.argtypes = [ctypes.POINTER(BatchConfig)]
+_lib.evq_batch_config_set.restype = ctypes.c_int32
+_lib.evq_batch_config_set.argtypes = [ctypes.POINTER(BatchConfig)]
 _lib.evq_free.restype = None
 _lib.evq_free.argtypes = [_P]
 _lib.evq_last_error.restype = ctypes.c_char_p
@@ -85,8 +113,9 @@ _lib.evq_timing_report.restype = ctypes.c_int
 _lib.evq_timing_report.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int]
 
 EXPORTED = ["evq_build", "evq_graph_info_get", "evq_graph_export", "evq_query", "evq_query_bounds",
-            "evq_query_plain", "evq_free", "evq_last_error", "evq_timing_enable", "evq_timing_reset",
-            "evq_timing_report"]
+            "evq_query_plain", "evq_query_batch", "evq_result_expand", "evq_result_free",
+            "evq_batch_config_get", "evq_batch_config_set", "evq_free", "evq_last_error", "evq_timing_enable",
+            "evq_timing_reset", "evq_timing_report"]
 
 
 class EvqError(RuntimeError):
@@ -218,6 +247,65 @@ class Graph:
         rcup = torch.empty(self.num_vertices, dtype=torch.int32, device="cuda")
         _check(_lib.evq_query_bounds(self._h, algo, source, win_begin, L, _ptr(rcap), _ptr(rcup), _stream(stream)))
         return rcap, rcup
+
+    def query_batch(self, queries, stats=False, stream=None):
+        """Answer many queries (evq_query_batch).  queries: iterable of (algo, source, win_begin, win_len).
+        Returns a list of Result (compact, device-resident), and per-query stats dicts if asked."""
+        qs = list(queries)
+        n = len(qs)
+        descs = (QueryDesc * max(n, 1))()
+        for i, (a, src, b, L) in enumerate(qs):
+            descs[i] = QueryDesc(ALGOS.get(a, a), src, b, L)
+        res = (ResultC * max(n, 1))()
+        st = (QueryStats * max(n, 1))() if stats else None
+        _check(_lib.evq_query_batch(self._h, descs, n, res, st, _stream(stream)))
+        out = [Result(res[i]) for i in range(n)]
+        return (out, [st[i].as_dict() for i in range(n)]) if stats else out
+
+
+class Result:
+    """Compact result of one batched query (evq_result); device memory is released by free() or on deletion."""
+
+    def __init__(self, c):
+        self._c = ResultC()
+        ctypes.memmove(ctypes.byref(self._c), ctypes.byref(c), ctypes.sizeof(ResultC))
+
+    @property
+    def info(self) -> dict:
+        return {k: getattr(self._c, k) for k in ("algo", "source", "win_begin", "win_len", "num_vertices",
+                                                  "n_unstable", "row_stride")}
+
+    def expand(self, out=None, stream=None):
+        """values (V, win_len) int32 tensor (evq_result_expand)."""
+        import torch
+        V, L = self._c.num_vertices, self._c.win_len
+        if out is None:
+            out = torch.empty((V, L), dtype=torch.int32, device="cuda")
+        if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous() or out.numel() != V * L:
+            raise ValueError("out must be a contiguous int32 CUDA tensor of V * L elements")
+        _check(_lib.evq_result_expand(ctypes.byref(self._c), _ptr(out), _stream(stream)))
+        return out
+
+    def free(self, stream=None):
+        if self._c.d_rcap and _lib is not None:
+            _check(_lib.evq_result_free(ctypes.byref(self._c), _stream(stream)))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def batch_config() -> dict:
+    c = BatchConfig()
+    _check(_lib.evq_batch_config_get(ctypes.byref(c)))
+    return {"lanes": c.lanes, "chunk": c.chunk, "blocks": c.blocks}
+
+
+def set_batch_config(lanes=0, chunk=0, blocks=0):
+    """Execution choices of query_batch (0 keeps the current value)."""
+    _check(_lib.evq_batch_config_set(ctypes.byref(BatchConfig(lanes, chunk, blocks, 0))))
 
 
 def to_u32(t) -> np.ndarray:

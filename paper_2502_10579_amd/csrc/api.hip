@@ -1,6 +1,7 @@
 // C ABI of the library: argument validation, error capture and dispatch.
 // Nothing throws across this boundary; every failure becomes an evq_status
 // with a thread-local message.
+#include "batch.h"
 #include "evq_internal.h"
 
 struct evq_graph {
@@ -153,6 +154,104 @@ evq_status evq_query_plain(const evq_graph* h, uint32_t algo, uint32_t source, u
         qo.want_stats = stats != nullptr;
         evq::run_plain(*h->g, algo, source, W, d_values, qo, (hipStream_t)stream);
         if (stats) *stats = qo.st;
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+evq_status evq_query_batch(const evq_graph* h, const evq_query_desc* q, uint32_t n, evq_result* results,
+                           evq_query_stats* stats, void* stream) {
+    g_last_error.clear();
+    if (!h || !h->g) return bad(EVQ_EINVAL, "graph handle is NULL");
+    if (!q || !results) return bad(EVQ_EINVAL, "NULL query or result array");
+    if (n == 0 || n > 65536) return bad(EVQ_ERANGE, "a batch holds 1..65536 queries");
+    std::memset(results, 0, sizeof(evq_result) * n);
+    try {
+        std::vector<evq::BatchQuery> bq(n);
+        for (uint32_t i = 0; i < n; ++i) {
+            evq_status rc = make_window(h, q[i].algo, q[i].source, q[i].win_begin, q[i].win_len, bq[i].W);
+            if (rc != EVQ_OK) {
+                g_last_error = "query " + std::to_string(i) + ": " + g_last_error;
+                return rc;
+            }
+            bq[i].algo = q[i].algo;
+            bq[i].source = q[i].source;
+        }
+        std::vector<evq::Compact> c(n);
+        evq::run_batch(*h->g, bq.data(), n, c.data(), stats, (hipStream_t)stream);
+        for (uint32_t i = 0; i < n; ++i) {
+            evq_result& r = results[i];
+            r.algo = q[i].algo;
+            r.source = q[i].source;
+            r.win_begin = q[i].win_begin;
+            r.win_len = q[i].win_len;
+            r.num_vertices = h->g->V;
+            r.n_unstable = c[i].nU;
+            r.row_stride = c[i].LG;
+            r.d_rcap = c[i].rcap;
+            r.d_unstable = c[i].ulist;
+            r.d_x = c[i].X;
+        }
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+evq_status evq_result_expand(const evq_result* r, uint32_t* d_values, void* stream) {
+    g_last_error.clear();
+    if (!r || !d_values) return bad(EVQ_EINVAL, "NULL argument");
+    if (!r->d_rcap || r->win_len == 0 || r->num_vertices == 0) return bad(EVQ_EINVAL, "empty result");
+    if (r->n_unstable && (!r->d_unstable || !r->d_x || r->row_stride < r->win_len))
+        return bad(EVQ_EINVAL, "malformed result");
+    try {
+        evq::expand_compact(r->num_vertices, r->win_len, r->d_rcap, r->d_unstable, r->d_x, r->n_unstable,
+                            r->row_stride, d_values, (hipStream_t)stream);
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+evq_status evq_result_free(evq_result* r, void* stream) {
+    g_last_error.clear();
+    if (!r) return bad(EVQ_EINVAL, "result is NULL");
+    try {
+        evq::stream_free(const_cast<uint32_t*>(r->d_rcap), (hipStream_t)stream);
+        evq::stream_free(const_cast<uint32_t*>(r->d_unstable), (hipStream_t)stream);
+        std::memset(r, 0, sizeof(*r));
+        return EVQ_OK;
+    } catch (...) {
+        std::memset(r, 0, sizeof(*r));
+        return guard_exc();
+    }
+}
+
+evq_status evq_batch_config_get(evq_batch_config* c) {
+    g_last_error.clear();
+    if (!c) return bad(EVQ_EINVAL, "config is NULL");
+    try {
+        const evq::BatchTuning t = evq::batch_tuning();
+        std::memset(c, 0, sizeof(*c));
+        c->lanes = t.lanes;
+        c->chunk = t.chunk;
+        c->blocks = t.blocks;
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+evq_status evq_batch_config_set(const evq_batch_config* c) {
+    g_last_error.clear();
+    if (!c) return bad(EVQ_EINVAL, "config is NULL");
+    try {
+        evq::BatchTuning t = evq::batch_tuning();
+        if (c->lanes) t.lanes = c->lanes;
+        if (c->chunk) t.chunk = c->chunk;
+        if (c->blocks) t.blocks = c->blocks;
+        evq::set_batch_tuning(t);
         return EVQ_OK;
     } catch (...) {
         return guard_exc();

@@ -75,7 +75,7 @@ class Workspace {
   public:
     enum Slot {
         kFlags, kFo, kFd, kFs, kFv, kControl, kRcap, kRcup, kCidOf, kUlist, kCuo, kRv, kRc, kRuo, kKc, kRecs,
-        kTasks, kX, kSlots
+        kTasks, kX, kBatchCap, kBatchCup, kBatchTable, kSlots
     };
     static Workspace& get(hipStream_t s);
     void* raw(Slot slot, uint64_t bytes);
@@ -95,6 +95,8 @@ class Workspace {
 
 void* dev_alloc(uint64_t bytes);  // hipMalloc; throws EVQ_ENOMEM
 void dev_free(void* p);
+void* stream_alloc(uint64_t bytes, hipStream_t s);  // hipMallocAsync from the device pool; throws EVQ_ENOMEM
+void stream_free(void* p, hipStream_t s);          // hipFreeAsync (NULL allowed)
 void init_mempool(int device);
 
 // Small pinned host mailbox used to read counters back (one per host thread).
@@ -158,6 +160,28 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
                uint32_t* d_rcap_out, uint32_t* d_rcup_out, bool bounds_only, QueryOut& qo, hipStream_t s);
 void run_plain(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values, QueryOut& qo,
                hipStream_t s);
+
+// Compact result of one query: rcap (V values, allocated by the caller) and,
+// after the tail, the unstable vertices and their relaxed rows in one
+// allocation (ulist first, rows of LG values from X).
+struct Compact {
+    uint32_t* rcap = nullptr;
+    uint32_t* ulist = nullptr;
+    uint32_t* X = nullptr;
+    uint32_t nU = 0, LG = 0;
+};
+
+// Whole query with a compact result (bound solves into c.rcap).
+void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Window& W, Compact& c, QueryOut& qo,
+                       hipStream_t s);
+// Steps after the bound solves, given both bounds: reduction and relaxation
+// into a compact result (c.rcap holds the intersection bound).
+void run_tail_compact(const Graph& g, uint32_t algo, uint32_t source, const Window& W, const uint32_t* rcup,
+                      Compact& c, QueryOut& qo, hipStream_t s);
+// values[v * L + i] from a compact result.
+void expand_compact(uint32_t V, uint32_t L, const uint32_t* rcap, const uint32_t* ulist, const uint32_t* X,
+                    uint32_t nU, uint32_t LG, uint32_t* d_values, hipStream_t s);
+uint32_t pick_lg(uint32_t L);
 
 }  // namespace evq
 

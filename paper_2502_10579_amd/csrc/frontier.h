@@ -228,6 +228,10 @@ class HostSlots {
     static HostSlots& get();  // one per host thread
     uint32_t* host() const { return h_; }
     uint32_t* dev() const { return d_; }
+    // Slot numbering runs on across loops, so that the iterations a finished
+    // loop issued past its end (still queued) never write a slot that the
+    // next loop has just reset.
+    uint64_t next = 0;
 
   private:
     HostSlots();
@@ -252,15 +256,24 @@ uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_it
     constexpr uint64_t kDepth = 3;
     HostSlots& hs = HostSlots::get();
     uint64_t issued = 0, consumed = 0;
+    const uint64_t base = hs.next;
+    struct Advance {
+        HostSlots& hs;
+        const uint64_t& end;
+        ~Advance() { hs.next = end; }
+    };
+    uint64_t end = base;
+    Advance adv{hs, end};
     for (;;) {
         while (issued < consumed + kDepth) {
-            const uint32_t k = (uint32_t)(issued % HostSlots::kSlots);
+            const uint32_t k = (uint32_t)((base + issued) % HostSlots::kSlots);
             __atomic_store_n(&hs.host()[k], HostSlots::kEmpty, __ATOMIC_RELEASE);
             issue(issued, f_parity, issued == 0, hs.dev() + k);
             f_parity ^= 1;
             ++issued;
+            end = base + issued;
         }
-        volatile uint32_t* slot = hs.host() + (consumed % HostSlots::kSlots);
+        volatile uint32_t* slot = hs.host() + ((base + consumed) % HostSlots::kSlots);
         wait_slot(slot, s, what);
         if (*slot == 0) break;
         if (items) *items += *slot;

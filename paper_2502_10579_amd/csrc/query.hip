@@ -528,7 +528,46 @@ __global__ void __launch_bounds__(kBlock) k_writeback1(uint32_t V, uint32_t L, u
     }
 }
 
+// dst[i] = src[i], i < n (4 values per thread where aligned).
+__global__ void k_copy4(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, uint32_t n) {
+    const uint64_t n4 = n / 4;
+    const bool al = ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0);
+    const uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, st = (uint64_t)gridDim.x * blockDim.x;
+    if (al) {
+        for (uint64_t i = i0; i < n4; i += st)
+            reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+        for (uint64_t i = n4 * 4 + i0; i < n; i += st) dst[i] = src[i];
+    } else {
+        for (uint64_t i = i0; i < n; i += st) dst[i] = src[i];
+    }
+}
+
+// Rows of a compact result into values[v * L + i]: four values per thread.
+__global__ void k_scatter_rows4(const uint32_t* __restrict__ ulist, uint32_t nU, const uint32_t* __restrict__ X,
+                                uint32_t LG, uint32_t L, uint32_t* __restrict__ out) {
+    const uint32_t Lq = L / 4;
+    const uint64_t n = (uint64_t)nU * Lq;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t c = k / Lq;
+        const uint32_t j = (uint32_t)(k - c * Lq);
+        reinterpret_cast<uint4*>(out)[(uint64_t)ulist[c] * Lq + j] =
+            reinterpret_cast<const uint4*>(X)[c * (LG / 4) + j];
+    }
+}
+
+__global__ void k_scatter_rows1(const uint32_t* __restrict__ ulist, uint32_t nU, const uint32_t* __restrict__ X,
+                                uint32_t LG, uint32_t L, uint32_t* __restrict__ out) {
+    const uint64_t n = (uint64_t)nU * L;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t c = k / L;
+        const uint32_t i = (uint32_t)(k - c * L);
+        out[(uint64_t)ulist[c] * L + i] = X[c * LG + i];
+    }
+}
+
 // ------------------------------------------------------------------ host side
+
+}  // namespace
 
 uint32_t pick_lg(uint32_t L) {
     if (L <= 8) return 8;
@@ -537,6 +576,8 @@ uint32_t pick_lg(uint32_t L) {
     if (L <= 64) return 64;
     return 128;
 }
+
+namespace {
 
 struct Timer {
     bool on;
@@ -734,22 +775,15 @@ uint64_t read_stat(const unsigned long long* d, int i, hipStream_t s) {
 
 }  // namespace
 
-void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values,
-               uint32_t* d_rcap_out, uint32_t* d_rcup_out, bool bounds_only, QueryOut& qo, hipStream_t s) {
-    auto t0 = std::chrono::steady_clock::now();
-    init_mempool(g.device);
-    Workspace& ws = Workspace::get(s);
-    Mailbox& mb = Mailbox::get();
+namespace {
+
+// Step 1: both bounds (the union solve starts from the intersection values).
+void bounds_impl(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* rcap, uint32_t* rcup,
+                 Frontier& f, QueryOut& qo, hipStream_t s, Timer& tm) {
     const bool st = qo.want_stats;
-    Timer tm(st, s);
-    tm.mark();
-    Frontier f = make_frontier(g, ws, s);
-    f.delta = choose_delta(algo);
-    uint32_t* rcap = d_rcap_out ? d_rcap_out : ws.buf<uint32_t>(Workspace::kRcap, g.V);
-    uint32_t* rcup = d_rcup_out ? d_rcup_out : ws.buf<uint32_t>(Workspace::kRcup, g.V);
     qo.st.iters_cap = solve_cap(g, algo, W, source, rcap, f, s, st);
     tm.mark();
-    EVQ_HIP(hipMemcpyAsync(rcup, rcap, (uint64_t)g.V * 4, hipMemcpyDeviceToDevice, s));
+    EVQ_LAUNCH("copy_bound", k_copy4, grid_for((g.V + 3) / 4, 256 * 4, 8192), 256, s, rcap, rcup, g.V);
     if (st) {
         qo.st.edges_cap = read_stat(f.stats, 0, s);
         qo.st.updates_cap = read_stat(f.stats, 4, s);
@@ -763,23 +797,71 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
         qo.st.updates_cup = read_stat(f.stats, 4, s) - qo.st.updates_cap;
         qo.st.seed_visits_cup = read_stat(f.stats, 5, s);
     }
-    if (bounds_only) {
-        EVQ_HIP(hipStreamSynchronize(s));
-        ws.in_use = false;
-        return;
-    }
+}
+
+// Steps 2-3 and Algorithm 2: reduction, then the multi-snapshot relaxation
+// into X (the workspace, or a compact result's rows), then the writeback of
+// values[V][L] when d_values is given.
+void tail_impl(const Graph& g, uint32_t algo, uint32_t source, const Window& W, const uint32_t* rcap,
+               const uint32_t* rcup, Frontier& f, Workspace& ws, uint32_t* d_values, Compact* c, QueryOut& qo,
+               hipStream_t s, Timer& tm) {
+    const bool st = qo.want_stats;
+    Mailbox& mb = Mailbox::get();
     const uint32_t LG = pick_lg(W.L);
     const uint32_t NLW = LG > 64 ? 2 : 1;
     Reduced red = reduce_graph(g, rcap, rcup, false, W, NLW, f, ws, mb, s);
     tm.mark();
     uint32_t* X = nullptr;
-    if (red.nU) {
+    if (c) {
+        c->nU = red.nU;
+        c->LG = LG;
+        c->ulist = c->X = nullptr;
+        if (red.nU) {
+            const uint64_t ub = ((uint64_t)red.nU * 4 + 255) & ~uint64_t(255);
+            char* p = static_cast<char*>(stream_alloc(ub + (uint64_t)red.nU * LG * 4, s));
+            c->ulist = reinterpret_cast<uint32_t*>(p);
+            c->X = reinterpret_cast<uint32_t*>(p + ub);
+            EVQ_LAUNCH("result_copy", k_copy4, grid_for((red.nU + 3) / 4, 256 * 4, 8192), 256, s, red.ulist,
+                       c->ulist, red.nU);
+            X = c->X;
+        }
+    } else if (red.nU) {
         X = ws.buf<uint32_t>(Workspace::kX, (uint64_t)red.nU * LG);
-        relax_algo(algo, LG, st, g, W, rcap, red, X, false, source, f, ws, s, qo);
     }
+    if (red.nU) relax_algo(algo, LG, st, g, W, rcap, red, X, false, source, f, ws, s, qo);
     tm.mark();
-    writeback(LG, g.V, W.L, red.cid_of, rcap, X, d_values, s);
+    if (d_values) writeback(LG, g.V, W.L, red.cid_of, rcap, X, d_values, s);
     tm.mark();
+    if (st) {
+        qo.st.n_unstable = red.nU;
+        qo.st.n_relax_edges = red.nU ? sum_u32(red.kc, red.nU, s) : 0;
+        qo.st.edge_visits_relax = read_stat(f.stats, 1, s);
+        qo.st.lane_relaxations = read_stat(f.stats, 2, s);
+        qo.st.n_seed_edges = read_stat(f.stats, 3, s);
+    }
+}
+
+}  // namespace
+
+void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values,
+               uint32_t* d_rcap_out, uint32_t* d_rcup_out, bool bounds_only, QueryOut& qo, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    init_mempool(g.device);
+    Workspace& ws = Workspace::get(s);
+    const bool st = qo.want_stats;
+    Timer tm(st, s);
+    tm.mark();
+    Frontier f = make_frontier(g, ws, s);
+    f.delta = choose_delta(algo);
+    uint32_t* rcap = d_rcap_out ? d_rcap_out : ws.buf<uint32_t>(Workspace::kRcap, g.V);
+    uint32_t* rcup = d_rcup_out ? d_rcup_out : ws.buf<uint32_t>(Workspace::kRcup, g.V);
+    bounds_impl(g, algo, source, W, rcap, rcup, f, qo, s, tm);
+    if (bounds_only) {
+        EVQ_HIP(hipStreamSynchronize(s));
+        ws.in_use = false;
+        return;
+    }
+    tail_impl(g, algo, source, W, rcap, rcup, f, ws, d_values, nullptr, qo, s, tm);
     ws.in_use = false;
     if (st) {
         qo.st.ms_cap = tm.ms(0, 1);
@@ -787,13 +869,64 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
         qo.st.ms_compact = tm.ms(2, 3);
         qo.st.ms_relax = tm.ms(3, 4);
         qo.st.ms_writeback = tm.ms(4, 5);
-        qo.st.n_unstable = red.nU;
-        qo.st.n_relax_edges = red.nU ? sum_u32(red.kc, red.nU, s) : 0;
-        qo.st.edge_visits_relax = read_stat(f.stats, 1, s);
-        qo.st.lane_relaxations = read_stat(f.stats, 2, s);
-        qo.st.n_seed_edges = read_stat(f.stats, 3, s);
         EVQ_HIP(hipStreamSynchronize(s));
         qo.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+}
+
+void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Window& W, Compact& c, QueryOut& qo,
+                       hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    init_mempool(g.device);
+    Workspace& ws = Workspace::get(s);
+    const bool st = qo.want_stats;
+    Timer tm(st, s);
+    tm.mark();
+    Frontier f = make_frontier(g, ws, s);
+    f.delta = choose_delta(algo);
+    uint32_t* rcup = ws.buf<uint32_t>(Workspace::kRcup, g.V);
+    bounds_impl(g, algo, source, W, c.rcap, rcup, f, qo, s, tm);
+    tail_impl(g, algo, source, W, c.rcap, rcup, f, ws, nullptr, &c, qo, s, tm);
+    ws.in_use = false;
+    if (st) {
+        qo.st.ms_cap = tm.ms(0, 1);
+        qo.st.ms_cup = tm.ms(1, 2);
+        qo.st.ms_compact = tm.ms(2, 3);
+        qo.st.ms_relax = tm.ms(3, 4);
+        EVQ_HIP(hipStreamSynchronize(s));
+        qo.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+}
+
+void run_tail_compact(const Graph& g, uint32_t algo, uint32_t source, const Window& W, const uint32_t* rcup,
+                      Compact& c, QueryOut& qo, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    init_mempool(g.device);
+    Workspace& ws = Workspace::get(s);
+    const bool st = qo.want_stats;
+    Timer tm(st, s);
+    tm.mark();
+    Frontier f = make_frontier(g, ws, s);
+    tail_impl(g, algo, source, W, c.rcap, rcup, f, ws, nullptr, &c, qo, s, tm);
+    ws.in_use = false;
+    if (st) {
+        qo.st.ms_compact = tm.ms(0, 1);
+        qo.st.ms_relax = tm.ms(1, 2);
+        EVQ_HIP(hipStreamSynchronize(s));
+        qo.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+}
+
+void expand_compact(uint32_t V, uint32_t L, const uint32_t* rcap, const uint32_t* ulist, const uint32_t* X,
+                    uint32_t nU, uint32_t LG, uint32_t* d_values, hipStream_t s) {
+    writeback(LG, V, L, nullptr, rcap, nullptr, d_values, s);
+    if (!nU) return;
+    if (L % 4 == 0 && (uintptr_t)d_values % 16 == 0) {
+        EVQ_LAUNCH("expand_rows", k_scatter_rows4, grid_for((uint64_t)nU * (L / 4), 256 * 4, 65535), 256, s, ulist,
+                   nU, X, LG, L, d_values);
+    } else {
+        EVQ_LAUNCH("expand_rows", k_scatter_rows1, grid_for((uint64_t)nU * L, 256 * 4, 65535), 256, s, ulist, nU, X,
+                   LG, L, d_values);
     }
 }
 

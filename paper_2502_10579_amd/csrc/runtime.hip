@@ -37,6 +37,21 @@ void dev_free(void* p) {
     if (p) (void)hipFree(p);
 }
 
+void* stream_alloc(uint64_t bytes, hipStream_t s) {
+    void* p = nullptr;
+    const uint64_t n = bytes ? (bytes + 255) & ~uint64_t(255) : 256;
+    hipError_t e = hipMallocAsync(&p, n, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(EVQ_ENOMEM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+
+void stream_free(void* p, hipStream_t s) {
+    if (p) EVQ_HIP(hipFreeAsync(p, s));
+}
+
 void init_mempool(int device) {
     static std::mutex mu;
     static std::vector<int> done;

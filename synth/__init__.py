@@ -118,6 +118,22 @@ def pick_sources(inst: Instance, count: int, seed: int = 1, stream: int = 1 << 3
     return [int(cand[draw(seed, stream, i) % cand.size]) for i in range(count)]
 
 
+def batch_queries(inst: Instance, n: int, seed: int = 1, start_max: int = 100, len_min: int = 25,
+                  len_max: int = 100, algos=(0, 1, 2, 3)) -> list:
+    """n query descriptors (algo, source, win_begin, win_len) for a batch: algorithm uniform over
+    `algos`, source uniform among base vertices of out-degree > 0, start uniform in [0, start_max]
+    (clamped to K - 1), length uniform in [len_min, len_max], clamped so the window ends by K."""
+    K = inst.K
+    srcs = pick_sources(inst, n, seed=seed, stream=(1 << 30) + 1)
+    out = []
+    for i in range(n):
+        a = algos[draw(seed, (1 << 30) + 2, i) % len(algos)]
+        b = min(draw(seed, (1 << 30) + 3, i) % (start_max + 1), K - 1)
+        L = len_min + draw(seed, (1 << 30) + 4, i) % (len_max - len_min + 1)
+        out.append((int(a), int(srcs[i]), int(b), int(max(1, min(L, K - b)))))
+    return out
+
+
 def random_instance(V: int, n_base: int, K: int, n_del: int, n_add: int, wmax: int, seed: int) -> Instance:
     """Small uniform multigraph instance (for exhaustive pin tests): base may hold
     exact duplicates; deletions draw from the current set; additions are uniform."""
