@@ -86,7 +86,8 @@ typedef struct {
     uint64_t num_edges;      /* distinct (src, dst, w) triples present in >= 1 snapshot */
     uint64_t num_partial;    /* of those, triples absent from >= 1 snapshot */
     uint64_t device_bytes;   /* device memory held by the handle */
-    double build_ms;         /* wall time of evq_build, host validation included */
+    double build_ms;         /* wall time of evq_build (or of the last evq_append), host validation included */
+    uint64_t first_snapshot; /* global id of the oldest snapshot held (0 until the first evq_append) */
 } evq_graph_info;
 
 /* Filled by evq_query when a non-NULL pointer is passed (the call then synchronises). */
@@ -140,7 +141,9 @@ evq_status evq_graph_export(const evq_graph* g, uint32_t* row_ptr, uint32_t* row
  * Answer a query over the window [win_begin, win_begin + win_len) of
  * snapshots (Algorithm 1 followed by Algorithm 2).
  *   algo: EVQ_SSSP / EVQ_BFS / EVQ_SSWP / EVQ_SSNP; source < V.
- *   1 <= win_len and win_begin + win_len <= K.
+ *   Snapshots are named by global id: the graph holds first .. first+K-1
+ *   (first = first_snapshot of evq_graph_info, 0 until an evq_append), so
+ *   first <= win_begin, 1 <= win_len and win_begin + win_len <= first + K.
  *   d_values: caller-owned DEVICE buffer of V * win_len uint32,
  *             d_values[v * win_len + i] = value of v in snapshot win_begin + i.
  *   stats: NULL, or a host struct filled after the call synchronises.
@@ -247,7 +250,22 @@ evq_status evq_result_free(evq_result* r, void* stream);
 evq_status evq_batch_config_get(evq_batch_config* c);
 evq_status evq_batch_config_set(const evq_batch_config* c);
 
-/* Release the handle and its device memory.  NULL is allowed. */
+/*
+ * Serving store: advance the window of held snapshots by one.  The new
+ * snapshot first+K is the newest held snapshot with batch `b` applied
+ * (deletions before additions, as in evq_build); it takes the mask bit of
+ * the oldest snapshot, `first`, which is dropped (a ring of K mask bits:
+ * snapshot t lives in bit t mod K).  Triples present in no held snapshot
+ * leave the graph.  The next version is built on the device beside the
+ * current one and then published: queries already running keep the version
+ * they started on, later calls see the new one.  Appends on one handle are
+ * serialised.  Synchronises `stream`.
+ * Errors: EVQ_EINVAL (NULL, id >= V, w == 0), EVQ_ERANGE, EVQ_ENOMEM,
+ * EVQ_EDEVICE; on failure the current version is unchanged.
+ */
+evq_status evq_append(evq_graph* g, const evq_batch* b, void* stream);
+
+/* Release the handle; each version's device memory is released once no call still uses it.  NULL is allowed. */
 void evq_free(evq_graph* g);
 
 /* Message of the last failing call on this thread ("" if none); valid until the next call. */

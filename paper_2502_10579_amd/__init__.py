@@ -38,7 +38,8 @@ class GraphInfo(ctypes.Structure):
     _fields_ = [("num_vertices", ctypes.c_uint32), ("num_snapshots", ctypes.c_uint32),
                 ("mask_words", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("num_edges", ctypes.c_uint64), ("num_partial", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_uint64), ("build_ms", ctypes.c_double)]
+                ("device_bytes", ctypes.c_uint64), ("build_ms", ctypes.c_double),
+                ("first_snapshot", ctypes.c_uint64)]
 
 
 class QueryStats(ctypes.Structure):
@@ -101,6 +102,8 @@ _lib.evq_batch_config_get.restype = ctypes.c_int32
 _lib.evq_batch_config_get.argtypes = [ctypes.POINTER(BatchConfig)]
 _lib.evq_batch_config_set.restype = ctypes.c_int32
 _lib.evq_batch_config_set.argtypes = [ctypes.POINTER(BatchConfig)]
+_lib.evq_append.restype = ctypes.c_int32
+_lib.evq_append.argtypes = [_P, ctypes.POINTER(Batch), _P]
 _lib.evq_free.restype = None
 _lib.evq_free.argtypes = [_P]
 _lib.evq_last_error.restype = ctypes.c_char_p
@@ -114,7 +117,7 @@ _lib.evq_timing_report.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int]
 
 EXPORTED = ["evq_build", "evq_graph_info_get", "evq_graph_export", "evq_query", "evq_query_bounds",
             "evq_query_plain", "evq_query_batch", "evq_result_expand", "evq_result_free",
-            "evq_batch_config_get", "evq_batch_config_set", "evq_free", "evq_last_error", "evq_timing_enable",
+            "evq_batch_config_get", "evq_batch_config_set", "evq_append", "evq_free", "evq_last_error", "evq_timing_enable",
             "evq_timing_reset", "evq_timing_report"]
 
 
@@ -172,6 +175,18 @@ class Graph:
         self.num_vertices = num_vertices
         self.K = len(dels)
 
+    def append(self, dels, adds, stream=None):
+        """Advance the held snapshots by one batch (evq_append)."""
+        d, dp = _edges(dels)
+        a, ap = _edges(adds)
+        b = Batch(dp, len(d), ap, len(a))
+        _check(_lib.evq_append(self._h, ctypes.byref(b), _stream(stream)))
+
+    @property
+    def first(self) -> int:
+        """Global id of the oldest snapshot held."""
+        return self.info["first_snapshot"]
+
     @classmethod
     def from_instance(cls, inst, stream=None):
         return cls(inst.num_vertices, inst.base, inst.dels, inst.adds, stream)
@@ -218,31 +233,39 @@ class Graph:
             raise ValueError("out must be a contiguous int32 CUDA tensor of V * L elements")
         return out
 
-    def query(self, algo, source, win_begin=0, win_len=None, out=None, stats=False, stream=None):
+    def _window(self, win_begin, win_len):
+        """Default window: from the oldest held snapshot (win_begin None) to the newest (win_len None)."""
+        if win_begin is None:
+            win_begin = self.first
+        if win_len is None:
+            win_len = self.first + self.K - win_begin
+        return win_begin, win_len
+
+    def query(self, algo, source, win_begin=None, win_len=None, out=None, stats=False, stream=None):
         """values (V, L) int32 tensor holding uint32 values (evq_query)."""
         algo = ALGOS.get(algo, algo)
-        L = self.K - win_begin if win_len is None else win_len
+        win_begin, L = self._window(win_begin, win_len)
         out = self._alloc(L, out)
         st = QueryStats() if stats else None
         _check(_lib.evq_query(self._h, algo, source, win_begin, L, _ptr(out),
                               ctypes.byref(st) if st is not None else None, _stream(stream)))
         return (out, st.as_dict()) if stats else out
 
-    def query_plain(self, algo, source, win_begin=0, win_len=None, out=None, stats=False, stream=None):
+    def query_plain(self, algo, source, win_begin=None, win_len=None, out=None, stats=False, stream=None):
         """Same output as query(), without the intersection-union analysis (evq_query_plain)."""
         algo = ALGOS.get(algo, algo)
-        L = self.K - win_begin if win_len is None else win_len
+        win_begin, L = self._window(win_begin, win_len)
         out = self._alloc(L, out)
         st = QueryStats() if stats else None
         _check(_lib.evq_query_plain(self._h, algo, source, win_begin, L, _ptr(out),
                                     ctypes.byref(st) if st is not None else None, _stream(stream)))
         return (out, st.as_dict()) if stats else out
 
-    def query_bounds(self, algo, source, win_begin=0, win_len=None, stream=None):
+    def query_bounds(self, algo, source, win_begin=None, win_len=None, stream=None):
         """(R_cap, R_cup) int32 tensors of V values (evq_query_bounds)."""
         import torch
         algo = ALGOS.get(algo, algo)
-        L = self.K - win_begin if win_len is None else win_len
+        win_begin, L = self._window(win_begin, win_len)
         rcap = torch.empty(self.num_vertices, dtype=torch.int32, device="cuda")
         rcup = torch.empty(self.num_vertices, dtype=torch.int32, device="cuda")
         _check(_lib.evq_query_bounds(self._h, algo, source, win_begin, L, _ptr(rcap), _ptr(rcup), _stream(stream)))

@@ -1,11 +1,23 @@
 // C ABI of the library: argument validation, error capture and dispatch.
 // Nothing throws across this boundary; every failure becomes an evq_status
 // with a thread-local message.
+#include <memory>
+#include <mutex>
+
 #include "batch.h"
 #include "evq_internal.h"
 
+// A graph handle holds its current version; queries take a reference to the
+// version they start on, so an append never waits for them and a version is
+// released (after the device drains) once its last query has returned.
 struct evq_graph {
-    evq::Graph* g;
+    mutable std::mutex mu;
+    std::shared_ptr<const evq::Graph> cur;
+    std::mutex append_mu;  // one append at a time
+    std::shared_ptr<const evq::Graph> get() const {
+        std::lock_guard<std::mutex> lk(mu);
+        return cur;
+    }
 };
 
 namespace {
@@ -35,18 +47,27 @@ evq_status bad(evq_status c, const char* msg) {
     return c;
 }
 
-// Validates a query and forms the window mask [b, b + L).
-evq_status make_window(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t b, uint32_t L, evq::Window& W) {
-    if (!h || !h->g) return bad(EVQ_EINVAL, "graph handle is NULL");
+void release_graph(evq::Graph* g) {
+    (void)hipDeviceSynchronize();  // no queued kernel may still read it
+    evq::free_graph(g);
+}
+
+// Validates a query and forms the mask of the window of snapshots
+// [b, b + L) (global ids; the graph holds first .. first + K - 1).
+evq_status make_window(const evq::Graph& g, uint32_t algo, uint32_t source, uint64_t b, uint32_t L,
+                       evq::Window& W) {
     if (algo > EVQ_SSNP) return bad(EVQ_EINVAL, "unknown algorithm");
-    const evq::Graph& g = *h->g;
     if (source >= g.V) return bad(EVQ_ERANGE, "source vertex out of range");
-    if (L == 0 || b >= g.K || L > g.K - b) return bad(EVQ_ERANGE, "window out of range");
-    W.b = b;
+    if (L == 0 || L > g.K || b < g.first || b - g.first > g.K - L) return bad(EVQ_ERANGE, "window out of range");
+    W.b = (uint32_t)(b % g.K);
     W.L = L;
+    W.K = g.K;
     W.w[0] = W.w[1] = 0;
-    for (uint32_t t = b; t < b + L; ++t) W.w[t >> 6] |= 1ull << (t & 63);
-    W.full = (b == 0 && L == g.K);
+    for (uint32_t i = 0; i < L; ++i) {
+        const uint32_t t = (W.b + i) % g.K;
+        W.w[t >> 6] |= 1ull << (t & 63);
+    }
+    W.full = L == g.K;
     return EVQ_OK;
 }
 
@@ -65,7 +86,15 @@ evq_status evq_build(uint32_t num_vertices, const evq_edge* base, uint64_t n_bas
     if (n_base && !base) return bad(EVQ_EINVAL, "base is NULL with n_base > 0");
     try {
         evq::Graph* g = evq::build_graph(num_vertices, base, n_base, batches, K, (hipStream_t)stream);
-        evq_graph* h = new evq_graph{g};
+        std::shared_ptr<const evq::Graph> sp;
+        try {
+            sp = std::shared_ptr<const evq::Graph>(g, release_graph);
+        } catch (...) {
+            evq::free_graph(g);
+            throw;
+        }
+        evq_graph* h = new evq_graph();
+        h->cur = std::move(sp);
         *out = h;
         return EVQ_OK;
     } catch (...) {
@@ -75,8 +104,9 @@ evq_status evq_build(uint32_t num_vertices, const evq_edge* base, uint64_t n_bas
 
 evq_status evq_graph_info_get(const evq_graph* h, evq_graph_info* info) {
     g_last_error.clear();
-    if (!h || !h->g || !info) return bad(EVQ_EINVAL, "NULL argument");
-    const evq::Graph& g = *h->g;
+    if (!h || !info) return bad(EVQ_EINVAL, "NULL argument");
+    auto gp = h->get();
+    const evq::Graph& g = *gp;
     std::memset(info, 0, sizeof(*info));
     info->num_vertices = g.V;
     info->num_snapshots = g.K;
@@ -85,15 +115,17 @@ evq_status evq_graph_info_get(const evq_graph* h, evq_graph_info* info) {
     info->num_partial = g.n_partial;
     info->device_bytes = g.bytes;
     info->build_ms = g.build_ms;
+    info->first_snapshot = g.first;
     return EVQ_OK;
 }
 
 evq_status evq_graph_export(const evq_graph* h, uint32_t* row_ptr, uint32_t* row_split, uint32_t* col, uint32_t* w,
                             uint64_t* mask, void* stream) {
     g_last_error.clear();
-    if (!h || !h->g) return bad(EVQ_EINVAL, "graph handle is NULL");
+    if (!h) return bad(EVQ_EINVAL, "graph handle is NULL");
     try {
-        const evq::Graph& g = *h->g;
+        auto gp = h->get();
+        const evq::Graph& g = *gp;
         hipStream_t s = (hipStream_t)stream;
         if (row_ptr) EVQ_HIP(hipMemcpyAsync(row_ptr, g.row_ptr, ((uint64_t)g.V + 1) * 4, hipMemcpyDeviceToHost, s));
         if (row_split) EVQ_HIP(hipMemcpyAsync(row_split, g.row_split, (uint64_t)g.V * 4, hipMemcpyDeviceToHost, s));
@@ -112,14 +144,16 @@ evq_status evq_graph_export(const evq_graph* h, uint32_t* row_ptr, uint32_t* row
 evq_status evq_query(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t win_begin, uint32_t win_len,
                      uint32_t* d_values, evq_query_stats* stats, void* stream) {
     g_last_error.clear();
+    if (!h) return bad(EVQ_EINVAL, "graph handle is NULL");
+    auto gp = h->get();
     evq::Window W;
-    evq_status rc = make_window(h, algo, source, win_begin, win_len, W);
+    evq_status rc = make_window(*gp, algo, source, win_begin, win_len, W);
     if (rc != EVQ_OK) return rc;
     if (!d_values) return bad(EVQ_EINVAL, "d_values is NULL");
     try {
         evq::QueryOut qo;
         qo.want_stats = stats != nullptr;
-        evq::run_query(*h->g, algo, source, W, d_values, nullptr, nullptr, false, qo, (hipStream_t)stream);
+        evq::run_query(*gp, algo, source, W, d_values, nullptr, nullptr, false, qo, (hipStream_t)stream);
         if (stats) *stats = qo.st;
         return EVQ_OK;
     } catch (...) {
@@ -130,12 +164,14 @@ evq_status evq_query(const evq_graph* h, uint32_t algo, uint32_t source, uint32_
 evq_status evq_query_bounds(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t win_begin, uint32_t win_len,
                             uint32_t* d_rcap, uint32_t* d_rcup, void* stream) {
     g_last_error.clear();
+    if (!h) return bad(EVQ_EINVAL, "graph handle is NULL");
+    auto gp = h->get();
     evq::Window W;
-    evq_status rc = make_window(h, algo, source, win_begin, win_len, W);
+    evq_status rc = make_window(*gp, algo, source, win_begin, win_len, W);
     if (rc != EVQ_OK) return rc;
     try {
         evq::QueryOut qo;
-        evq::run_query(*h->g, algo, source, W, nullptr, d_rcap, d_rcup, true, qo, (hipStream_t)stream);
+        evq::run_query(*gp, algo, source, W, nullptr, d_rcap, d_rcup, true, qo, (hipStream_t)stream);
         return EVQ_OK;
     } catch (...) {
         return guard_exc();
@@ -145,14 +181,16 @@ evq_status evq_query_bounds(const evq_graph* h, uint32_t algo, uint32_t source, 
 evq_status evq_query_plain(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t win_begin, uint32_t win_len,
                            uint32_t* d_values, evq_query_stats* stats, void* stream) {
     g_last_error.clear();
+    if (!h) return bad(EVQ_EINVAL, "graph handle is NULL");
+    auto gp = h->get();
     evq::Window W;
-    evq_status rc = make_window(h, algo, source, win_begin, win_len, W);
+    evq_status rc = make_window(*gp, algo, source, win_begin, win_len, W);
     if (rc != EVQ_OK) return rc;
     if (!d_values) return bad(EVQ_EINVAL, "d_values is NULL");
     try {
         evq::QueryOut qo;
         qo.want_stats = stats != nullptr;
-        evq::run_plain(*h->g, algo, source, W, d_values, qo, (hipStream_t)stream);
+        evq::run_plain(*gp, algo, source, W, d_values, qo, (hipStream_t)stream);
         if (stats) *stats = qo.st;
         return EVQ_OK;
     } catch (...) {
@@ -163,14 +201,15 @@ evq_status evq_query_plain(const evq_graph* h, uint32_t algo, uint32_t source, u
 evq_status evq_query_batch(const evq_graph* h, const evq_query_desc* q, uint32_t n, evq_result* results,
                            evq_query_stats* stats, void* stream) {
     g_last_error.clear();
-    if (!h || !h->g) return bad(EVQ_EINVAL, "graph handle is NULL");
+    if (!h) return bad(EVQ_EINVAL, "graph handle is NULL");
     if (!q || !results) return bad(EVQ_EINVAL, "NULL query or result array");
     if (n == 0 || n > 65536) return bad(EVQ_ERANGE, "a batch holds 1..65536 queries");
     std::memset(results, 0, sizeof(evq_result) * n);
     try {
+        auto gp = h->get();
         std::vector<evq::BatchQuery> bq(n);
         for (uint32_t i = 0; i < n; ++i) {
-            evq_status rc = make_window(h, q[i].algo, q[i].source, q[i].win_begin, q[i].win_len, bq[i].W);
+            evq_status rc = make_window(*gp, q[i].algo, q[i].source, q[i].win_begin, q[i].win_len, bq[i].W);
             if (rc != EVQ_OK) {
                 g_last_error = "query " + std::to_string(i) + ": " + g_last_error;
                 return rc;
@@ -179,14 +218,14 @@ evq_status evq_query_batch(const evq_graph* h, const evq_query_desc* q, uint32_t
             bq[i].source = q[i].source;
         }
         std::vector<evq::Compact> c(n);
-        evq::run_batch(*h->g, bq.data(), n, c.data(), stats, (hipStream_t)stream);
+        evq::run_batch(*gp, bq.data(), n, c.data(), stats, (hipStream_t)stream);
         for (uint32_t i = 0; i < n; ++i) {
             evq_result& r = results[i];
             r.algo = q[i].algo;
             r.source = q[i].source;
             r.win_begin = q[i].win_begin;
             r.win_len = q[i].win_len;
-            r.num_vertices = h->g->V;
+            r.num_vertices = gp->V;
             r.n_unstable = c[i].nU;
             r.row_stride = c[i].LG;
             r.d_rcap = c[i].rcap;
@@ -258,9 +297,36 @@ evq_status evq_batch_config_set(const evq_batch_config* c) {
     }
 }
 
+evq_status evq_append(evq_graph* h, const evq_batch* b, void* stream) {
+    g_last_error.clear();
+    if (!h || !b) return bad(EVQ_EINVAL, "NULL argument");
+    try {
+        std::lock_guard<std::mutex> lk(h->append_mu);
+        auto old = h->get();
+        evq::Graph* g = evq::append_graph(*old, *b, (hipStream_t)stream);
+        std::shared_ptr<const evq::Graph> sp;
+        try {
+            sp = std::shared_ptr<const evq::Graph>(g, release_graph);
+        } catch (...) {
+            evq::free_graph(g);
+            throw;
+        }
+        {
+            std::lock_guard<std::mutex> lk2(h->mu);
+            h->cur = std::move(sp);
+        }
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
 void evq_free(evq_graph* h) {
     if (!h) return;
-    evq::free_graph(h->g);
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        h->cur.reset();
+    }
     delete h;
 }
 

@@ -14,6 +14,7 @@
 //   4. prefix-sum compaction of the triples whose mask is non-zero;
 //   5. row offsets from the sorted sources, then a stable per-row partition
 //      (all-present edges first) and the list of partial edges.
+#include <algorithm>
 #include <chrono>
 
 #include "evq_internal.h"
@@ -35,7 +36,7 @@ __host__ __device__ inline int bits_for(uint64_t maxval) {
 }
 
 template <typename KT>
-__device__ __forceinline__ KT make_key(uint32_t s, uint32_t d, uint32_t w, uint32_t t, KeyLayout L) {
+__device__ __forceinline__ KT make_key(uint32_t s, uint32_t d, uint32_t w, uint64_t t, KeyLayout L) {
     KT k = (KT)s;
     k = (k << L.vb) | (KT)d;
     k = (k << L.wb) | (KT)w;
@@ -292,21 +293,13 @@ __global__ void k_row_split(const uint32_t* __restrict__ row_ptr, const uint32_t
     }
 }
 
+// Steps 4-5 from the sorted keys and, at the head of each run of equal
+// triples, its mask (mtmp) and whether it is kept (flag).  Releases its inputs.
 template <typename KT, int MW>
-void build_impl(Graph* g, const uint32_t* d_ev, uint64_t N, const uint64_t* d_seg, int nseg, KeyLayout L,
-                hipStream_t s, Arena& ar) {
+void finish_build(Graph* g, KT* sorted, uint64_t N, KeyLayout L, uint64_t* mtmp, uint32_t* flag, hipStream_t s,
+                  Arena& ar) {
     const uint32_t K = g->K;
-    KT* keys = ar.alloc<KT>(N);
-    KT* tmp = ar.alloc<KT>(N);
-    EVQ_LAUNCH("build_encode", k_encode<KT>, grid_for(N, 256), 256, s, d_ev, N, d_seg, nseg, L, keys);
-    KT* sorted = radix_sort<KT>(keys, tmp, N, L.total(), s, ar);
-    KT* other = sorted == keys ? tmp : keys;
-    ar.release(other);
-
-    uint64_t* mtmp = ar.alloc<uint64_t>(N * MW);
-    uint32_t* flag = ar.alloc<uint32_t>(N + 1);
     uint32_t* pos = ar.alloc<uint32_t>(N + 1);
-    EVQ_LAUNCH("build_seg_masks", (k_seg_masks<KT, MW>), grid_for(N, 256), 256, s, sorted, N, L, (int)K, mtmp, flag);
     scan_exclusive(flag, pos, N, pos + N, s, ar);
     Mailbox mb(1);
     EVQ_HIP(hipMemcpyAsync(mb.h, pos + N, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -317,9 +310,8 @@ void build_impl(Graph* g, const uint32_t* d_ev, uint64_t N, const uint64_t* d_se
     Mask<MW> all;
 #pragma unroll
     for (int q = 0; q < MW; ++q) {
-        int lo = 64 * q, hi = (int)K - 64 * q;
+        int hi = (int)K - 64 * q;
         all.w[q] = hi >= 64 ? ~0ull : (hi <= 0 ? 0ull : ((1ull << hi) - 1ull));
-        (void)lo;
     }
 
     uint32_t* c_src = ar.alloc<uint32_t>(E + 1);
@@ -356,6 +348,127 @@ void build_impl(Graph* g, const uint32_t* d_ev, uint64_t N, const uint64_t* d_se
                    E, g->row_ptr, g->col, g->wgt, g->mask, g->p_src, g->p_eid);
     EVQ_LAUNCH("build_row_split", k_row_split, grid_for(g->V, 256), 256, s, g->row_ptr, fb, g->V, g->row_split);
     EVQ_HIP(hipStreamSynchronize(s));
+}
+
+template <typename KT, int MW>
+void build_impl(Graph* g, const uint32_t* d_ev, uint64_t N, const uint64_t* d_seg, int nseg, KeyLayout L,
+                hipStream_t s, Arena& ar) {
+    KT* keys = ar.alloc<KT>(N);
+    KT* tmp = ar.alloc<KT>(N);
+    EVQ_LAUNCH("build_encode", k_encode<KT>, grid_for(N, 256), 256, s, d_ev, N, d_seg, nseg, L, keys);
+    KT* sorted = radix_sort<KT>(keys, tmp, N, L.total(), s, ar);
+    ar.release(sorted == keys ? tmp : keys);
+    uint64_t* mtmp = ar.alloc<uint64_t>(N * MW);
+    uint32_t* flag = ar.alloc<uint32_t>(N + 1);
+    EVQ_LAUNCH("build_seg_masks", (k_seg_masks<KT, MW>), grid_for(N, 256), 256, s, sorted, N, L, (int)g->K, mtmp,
+               flag);
+    finish_build<KT, MW>(g, sorted, N, L, mtmp, flag, s, ar);
+}
+
+// ------------------------------------------------------------------ ring append
+
+// A[x] = number of rows starting at edge x (x < E); then the source of edge
+// e is (rows starting at or before e) - 1.
+__global__ void k_row_starts(const uint32_t* __restrict__ row_ptr, uint32_t V, uint64_t E, uint32_t* __restrict__ A) {
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < V; u += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t x = row_ptr[u];
+        if (x < E) atomicAdd(&A[x], 1u);
+    }
+}
+
+// Keys of an append: every edge of the old version (tag 0, its edge index),
+// then the batch's deletions (tag 1) and additions (tag 2) with their index.
+// The time field of the key is (tag << ib) | index.
+template <typename KT>
+__global__ void k_encode_append(const uint32_t* __restrict__ A, const uint32_t* __restrict__ S,
+                                const uint32_t* __restrict__ col, const uint32_t* __restrict__ wgt, uint64_t E,
+                                const uint32_t* __restrict__ ev, uint64_t n_del, uint64_t n_ev, int ib, KeyLayout L,
+                                KT* __restrict__ keys) {
+    const uint64_t n = E + n_ev;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i < E) {
+            keys[i] = make_key<KT>(S[i] + A[i] - 1u, col[i], wgt[i], i, L);
+        } else {
+            const uint64_t j = i - E;
+            const uint64_t tag = j < n_del ? 1u : 2u;
+            keys[i] = make_key<KT>(ev[3 * j], ev[3 * j + 1], ev[3 * j + 2], (tag << ib) | j, L);
+        }
+    }
+}
+
+// Per run of equal triples: the old mask (from its tag-0 entry, if any) with
+// bit s_new replaced by presence in the new snapshot: present in the old
+// newest snapshot (bit s_prev) unless the batch deletes it, or added by the
+// batch (deletions act before additions).
+template <typename KT, int MW>
+__global__ void k_append_masks(const KT* __restrict__ keys, uint64_t n, KeyLayout L, int ib,
+                               const uint64_t* __restrict__ old_mask, uint32_t s_prev, uint32_t s_new,
+                               uint64_t* __restrict__ mtmp, uint32_t* __restrict__ flag) {
+    const KT tmask = ((KT)1 << L.tb) - 1;
+    const uint64_t imask = (1ull << ib) - 1ull;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const KT trip = keys[i] >> L.tb;
+        const bool head = (i == 0) || ((keys[i - 1] >> L.tb) != trip);
+        uint32_t f = 0;
+        if (head) {
+            uint64_t m[MW];
+#pragma unroll
+            for (int q = 0; q < MW; ++q) m[q] = 0;
+            bool del = false, add = false;
+            for (uint64_t j = i; j < n; ++j) {
+                const KT k = keys[j];
+                if ((k >> L.tb) != trip) break;
+                const uint64_t t = (uint64_t)(k & tmask);
+                const uint64_t tag = t >> ib, idx = t & imask;
+                if (tag == 0) {
+#pragma unroll
+                    for (int q = 0; q < MW; ++q) m[q] = old_mask[(uint64_t)idx * MW + q];
+                } else if (tag == 1) {
+                    del = true;
+                } else {
+                    add = true;
+                }
+            }
+            const bool prev = (m[s_prev >> 6] >> (s_prev & 63)) & 1ull;
+            const bool now = add || (prev && !del);
+            m[s_new >> 6] &= ~(1ull << (s_new & 63));
+            if (now) m[s_new >> 6] |= 1ull << (s_new & 63);
+#pragma unroll
+            for (int q = 0; q < MW; ++q) {
+                mtmp[i * MW + q] = m[q];
+                f |= m[q] != 0;
+            }
+        }
+        flag[i] = f;
+    }
+}
+
+template <typename KT, int MW>
+void append_impl(const Graph& old, Graph* g, const uint32_t* d_ev, uint64_t n_del, uint64_t n_ev, KeyLayout L, int ib,
+                 hipStream_t s, Arena& ar) {
+    const uint64_t E = old.E, N = E + n_ev;
+    uint32_t* A = ar.alloc<uint32_t>(E + 1);
+    uint32_t* S = ar.alloc<uint32_t>(E + 1);
+    if (E) {
+        fill_u32(A, E + 1, 0u, s);
+        EVQ_LAUNCH("append_rows", k_row_starts, grid_for(old.V, 256), 256, s, old.row_ptr, old.V, E, A);
+        scan_exclusive(A, S, E, nullptr, s, ar);
+    }
+    KT* keys = ar.alloc<KT>(N);
+    KT* tmp = ar.alloc<KT>(N);
+    EVQ_LAUNCH("append_encode", k_encode_append<KT>, grid_for(N, 256), 256, s, A, S, old.col, old.wgt, E, d_ev, n_del,
+               n_ev, ib, L, keys);
+    ar.release(A);
+    ar.release(S);
+    KT* sorted = radix_sort<KT>(keys, tmp, N, L.total(), s, ar);
+    ar.release(sorted == keys ? tmp : keys);
+    uint64_t* mtmp = ar.alloc<uint64_t>(N * MW);
+    uint32_t* flag = ar.alloc<uint32_t>(N + 1);
+    const uint32_t s_new = (uint32_t)(old.first % old.K);
+    const uint32_t s_prev = (uint32_t)((old.first + old.K - 1) % old.K);
+    EVQ_LAUNCH("append_masks", (k_append_masks<KT, MW>), grid_for(N, 256), 256, s, sorted, N, L, ib, old.mask, s_prev,
+               s_new, mtmp, flag);
+    finish_build<KT, MW>(g, sorted, N, L, mtmp, flag, s, ar);
 }
 
 }  // namespace
@@ -402,6 +515,7 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
     g->V = V;
     g->K = K;
     g->MW = K > 64 ? 2 : 1;
+    g->maxw = (uint32_t)maxw;
     g->device = dev;
     try {
         Arena ar(s);
@@ -450,6 +564,75 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
         } else {
             if (g->MW == 1) build_impl<u128, 1>(g, d_ev, N, d_seg, nseg - 1, L, s, ar);
             else build_impl<u128, 2>(g, d_ev, N, d_seg, nseg - 1, L, s, ar);
+        }
+        if (g->E >= 0xFFFFFFFEull) fail(EVQ_ERANGE, "more than 2^32 - 2 union edges");
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        free_graph(g);
+        throw;
+    }
+    EVQ_HIP(hipStreamSynchronize(s));
+    g->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return g;
+}
+
+Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    const uint32_t V = old.V;
+    uint64_t maxw = old.maxw;
+    auto check = [&](const evq_edge* e, uint64_t n, const char* what) {
+        if (n && !e) fail(EVQ_EINVAL, std::string(what) + " is NULL with a non-zero count");
+        for (uint64_t i = 0; i < n; ++i) {
+            if (e[i].src >= V || e[i].dst >= V)
+                fail(EVQ_EINVAL, std::string(what) + ": vertex id out of range at index " + std::to_string(i));
+            if (e[i].w == 0) fail(EVQ_EINVAL, std::string(what) + ": zero weight at index " + std::to_string(i));
+            if (e[i].w > maxw) maxw = e[i].w;
+        }
+    };
+    check(b.del, b.n_del, "batch deletions");
+    check(b.add, b.n_add, "batch additions");
+    const uint64_t n_ev = b.n_del + b.n_add;
+    if (old.E + n_ev >= 0xFFFFFFFEull) fail(EVQ_ERANGE, "more than 2^32 - 2 edges and events");
+
+    Graph* g = new Graph();
+    g->V = V;
+    g->K = old.K;
+    g->MW = old.MW;
+    g->first = old.first + 1;
+    g->maxw = (uint32_t)maxw;
+    g->device = old.device;
+    try {
+        Arena ar(s);
+        uint32_t* d_ev = ar.alloc<uint32_t>(3 * (n_ev + 1));
+        if (b.n_del) EVQ_HIP(hipMemcpyAsync(d_ev, b.del, b.n_del * sizeof(evq_edge), hipMemcpyHostToDevice, s));
+        if (b.n_add)
+            EVQ_HIP(hipMemcpyAsync(d_ev + 3 * b.n_del, b.add, b.n_add * sizeof(evq_edge), hipMemcpyHostToDevice, s));
+        KeyLayout L;
+        const int ib = bits_for(std::max<uint64_t>(old.E, n_ev));
+        L.vb = bits_for(V - 1);
+        L.wb = bits_for(maxw);
+        L.tb = 2 + ib;
+        if (old.E + n_ev == 0) {
+            g->E = 0;
+            g->n_partial = 0;
+            g->row_ptr = (uint32_t*)dev_alloc(((uint64_t)V + 1) * 4);
+            g->row_split = (uint32_t*)dev_alloc((uint64_t)V * 4);
+            fill_u32(g->row_ptr, (uint64_t)V + 1, 0u, s);
+            fill_u32(g->row_split, V, 0u, s);
+            g->col = (uint32_t*)dev_alloc(4);
+            g->wgt = (uint32_t*)dev_alloc(4);
+            g->mask = (uint64_t*)dev_alloc(16);
+            g->p_src = (uint32_t*)dev_alloc(4);
+            g->p_eid = (uint32_t*)dev_alloc(4);
+            g->bytes = ((uint64_t)V + 1) * 8;
+        } else if (L.total() <= 64) {
+            if (g->MW == 1) append_impl<uint64_t, 1>(old, g, d_ev, b.n_del, n_ev, L, ib, s, ar);
+            else append_impl<uint64_t, 2>(old, g, d_ev, b.n_del, n_ev, L, ib, s, ar);
+        } else if (L.total() <= 128) {
+            if (g->MW == 1) append_impl<u128, 1>(old, g, d_ev, b.n_del, n_ev, L, ib, s, ar);
+            else append_impl<u128, 2>(old, g, d_ev, b.n_del, n_ev, L, ib, s, ar);
+        } else {
+            fail(EVQ_ERANGE, "append key does not fit 128 bits");
         }
         if (g->E >= 0xFFFFFFFEull) fail(EVQ_ERANGE, "more than 2^32 - 2 union edges");
     } catch (...) {

@@ -30,8 +30,12 @@ constexpr uint32_t kSat = 0xFFFFFFFEu;
 
 // ------------------------------------------------------------------ graph
 
+// Snapshot t (a global id, counted from the first snapshot ever built) is
+// held in mask bit (t mod K); the graph holds snapshots first .. first+K-1.
 struct Graph {
     uint32_t V = 0, K = 0, MW = 1;
+    uint64_t first = 0;             // global id of the oldest snapshot held
+    uint32_t maxw = 1;              // largest weight ever seen (key layout of appends)
     uint64_t E = 0, n_partial = 0;
     uint32_t* row_ptr = nullptr;    // V + 1
     uint32_t* row_split = nullptr;  // V: end of the edges present in all K snapshots
@@ -143,11 +147,16 @@ void fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 
 Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_batch* batches, uint32_t K,
                    hipStream_t s);
+// The next version of a graph: snapshot first+K (old newest with batch b
+// applied) replaces snapshot `first` in its mask bit.  `old` is not changed.
+Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s);
 void free_graph(Graph* g);
 
+// A window of L consecutive snapshots; lane i is snapshot (first of the
+// window) + i, held in mask bit (b + i) mod K.
 struct Window {
-    uint32_t b = 0, L = 0;
-    uint64_t w[2] = {0, 0};  // bits [b, b+L)
+    uint32_t b = 0, L = 0, K = 0;
+    uint64_t w[2] = {0, 0};  // the window's mask bits
     bool full = false;       // the window is all K snapshots
 };
 

@@ -46,22 +46,26 @@ struct Lanes {
 
 __device__ __forceinline__ uint64_t low_mask(uint32_t n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
 
-// Window lane bits of edge e (bit i = present in snapshot b + i).
+// Window lane bits of edge e: bit i = present in the window's snapshot i,
+// held in mask bit (b + i) mod K.  The K-bit mask is rotated right by b
+// (bits moved past K are cleared by the L-bit lane mask, L <= K).
 template <int MW, int NLW>
 __device__ __forceinline__ void edge_lanes(const uint64_t* __restrict__ mask, uint32_t e, bool full_edge, uint32_t b,
-                                           uint32_t L, uint64_t (&out)[NLW]) {
+                                           uint32_t L, uint32_t K, uint64_t (&out)[NLW]) {
     if (full_edge) {
         out[0] = low_mask(L);
         if (NLW == 2) out[NLW - 1] = L > 64 ? low_mask(L - 64) : 0ull;
         return;
     }
     if (MW == 1) {
-        out[0] = (mask[e] >> b) & low_mask(L);
+        uint64_t m = mask[e];
+        if (b) m = (m >> b) | (m << (K - b));
+        out[0] = m & low_mask(L);
         if (NLW == 2) out[NLW - 1] = 0ull;
         return;
     }
     unsigned __int128 m = ((unsigned __int128)mask[2ull * e + 1] << 64) | mask[2ull * e];
-    m >>= b;
+    if (b) m = (m >> b) | (m << (K - b));
     out[0] = (uint64_t)m & low_mask(L);
     if (NLW == 2) out[NLW - 1] = L > 64 ? ((uint64_t)(m >> 64) & low_mask(L - 64)) : 0ull;
 }
@@ -191,7 +195,7 @@ struct ReduceArgs {
     const uint32_t* cid_of;
     uint32_t* kc;  // kept edges per compact id (must start at zero)
     void* recs;
-    uint32_t nR, TU, b, L;
+    uint32_t nR, TU, b, L, K;
 };
 
 // The reduced subgraph, built from U's rows (Section 6.2): every edge of a U
@@ -242,7 +246,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(ReduceArgs a) {
         if (t < end) {
             cd = a.cid_of[a.col[e]];
             if (cd != kNone) {
-                edge_lanes<MW, NLW>(a.mask, e, e < split, a.b, a.L, lanes);
+                edge_lanes<MW, NLW>(a.mask, e, e < split, a.b, a.L, a.K, lanes);
                 bool any = false;
 #pragma unroll
                 for (int j = 0; j < NLW; ++j) any |= lanes[j] != 0;
@@ -336,7 +340,8 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
                                                        const uint32_t* __restrict__ wgt,
                                                        const uint64_t* __restrict__ mask,
                                                        const uint32_t* __restrict__ cid_of,
-                                                       const uint32_t* __restrict__ rcap, uint32_t b, uint32_t L) {
+                                                       const uint32_t* __restrict__ rcap, uint32_t b, uint32_t L,
+                                                       uint32_t K) {
     using T = Lanes<LG>;
     const uint32_t lane = lane_id();
     const int g = LG >= 64 ? 0 : (int)lane / LG;
@@ -355,7 +360,7 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
             cv = cid_of[col[e]];
             act = cv != kNone;
             if (act) {
-                edge_lanes<MW, T::NLW>(mask, e, false, b, L, lanes);
+                edge_lanes<MW, T::NLW>(mask, e, false, b, L, K, lanes);
                 act = lanes_partial<T::NLW>(lanes, L);
                 if (act) cand = Alg<A>::extend(rcap[p_src[q]], wgt[e]);
             }
@@ -656,6 +661,7 @@ Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup,
         a.TU = (uint32_t)r.TU;
         a.b = W.b;
         a.L = W.L;
+        a.K = g.K;
         const uint32_t blocks = grid_for((r.TU + 63) / 64, kBlock / 64, 2048);
         if (g.MW == 1) EVQ_LAUNCH("compact_reduce", (k_reduce<1, 1>), blocks, kBlock, s, a);
         else if (NLW == 1) EVQ_LAUNCH("compact_reduce", (k_reduce<2, 1>), blocks, kBlock, s, a);
@@ -698,7 +704,7 @@ void relax_phase(const Graph& g, const Window& W, const uint32_t* rcap, const Re
             const uint32_t waves = (uint32_t)((g.n_partial + 63) / 64);
 #define EVQ_SEED(MW_)                                                                                             \
     EVQ_LAUNCH("relax_seed", (k_relax_seed<A, MW_, LG, ST>), grid_for(waves, kBlock / 64, 8192), kBlock, s, ra,   \
-               g.p_src, g.p_eid, (uint32_t)g.n_partial, g.col, g.wgt, g.mask, red.cid_of, rcap, W.b, W.L)
+               g.p_src, g.p_eid, (uint32_t)g.n_partial, g.col, g.wgt, g.mask, red.cid_of, rcap, W.b, W.L, g.K)
             if (g.MW == 1) EVQ_SEED(1);
             else EVQ_SEED(2);
 #undef EVQ_SEED
