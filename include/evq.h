@@ -54,6 +54,7 @@ typedef int32_t evq_status;
 #define EVQ_ENOMEM (-3)    /* device or host allocation failed */
 #define EVQ_EDEVICE (-4)   /* a HIP runtime call failed */
 #define EVQ_ENOCONV (-5)   /* a frontier loop exceeded its iteration cap */
+#define EVQ_ECANCELED (-6) /* a served query was dropped when its server shut down */
 
 #define EVQ_SSSP 0
 #define EVQ_BFS 1
@@ -264,6 +265,63 @@ evq_status evq_batch_config_set(const evq_batch_config* c);
  * EVQ_EDEVICE; on failure the current version is unchanged.
  */
 evq_status evq_append(evq_graph* g, const evq_batch* b, void* stream);
+
+/*
+ * Query server (a systems layer: the paper evaluates a fixed snapshot set
+ * known up front).  Queries name (algorithm, source, window length); at
+ * admission the window becomes the newest `len` snapshots the graph holds
+ * (len clamped to K), recorded in the result's win_begin / win_len.
+ *   mode 0, continuous batching: a dispatcher admits queued queries while
+ *     the estimated device footprint of all queries in flight stays within
+ *     mem_budget (one query is always admitted when nothing is in flight),
+ *     and forms groups of up to max_batch queued queries of the algorithm of
+ *     the oldest waiting query; a group's bound solves run together (one
+ *     query per lane), then each query's reduction and relaxation complete
+ *     independently on the worker pool.  At most max_groups group solves run
+ *     at once, so under load later groups fill up.
+ *   mode 1, plain: one query at a time in arrival order (the per-query path
+ *     of evq_query), as a baseline.
+ * Appends (evq_append on the same handle) may run at any time: queries
+ * admitted later see the new snapshots.  The handle must outlive the server.
+ */
+typedef struct evq_server evq_server;
+
+typedef struct {
+    uint32_t mode;           /* 0: continuous batching, 1: plain */
+    uint32_t max_batch;      /* queries per group, 1..64 (0: 64) */
+    uint32_t max_inflight;   /* admitted and not completed (0: 256) */
+    uint32_t max_groups;     /* group bound solves running at once (0: 2) */
+    uint64_t mem_budget;     /* device bytes, by estimate (0: a quarter of the free memory at creation) */
+} evq_server_config;
+
+typedef struct {
+    uint64_t ticket;
+    evq_status status;       /* EVQ_OK, or why the query failed (its result is then empty) */
+    uint32_t reserved;
+    double t_arrival_ms;     /* submission, ms since the server was created */
+    double t_admit_ms;       /* admission (window fixed) */
+    double t_done_ms;        /* compact result complete on the device */
+    uint64_t n_unstable;
+    uint64_t iters_relax;
+    evq_result result;       /* the caller's once returned: release with evq_result_free */
+} evq_completion;
+
+/* Start a server on graph g.  c may be NULL (defaults).  EVQ_EINVAL on bad fields. */
+evq_status evq_server_create(evq_graph* g, const evq_server_config* c, evq_server** out);
+
+/* Queue a query; *ticket identifies its completion.  EVQ_EINVAL / EVQ_ERANGE
+ * on a bad algorithm, source >= V or win_len == 0. */
+evq_status evq_server_submit(evq_server* s, uint32_t algo, uint32_t source, uint32_t win_len, uint64_t* ticket);
+
+/* Move up to cap completions to out (waiting up to wait_ms for the first); returns their number. */
+int evq_server_poll(evq_server* s, evq_completion* out, int cap, int wait_ms);
+
+/* Queries waiting for admission and queries admitted but not complete. */
+evq_status evq_server_pending(evq_server* s, uint32_t* queued, uint32_t* inflight);
+
+/* Stop: queries not yet admitted are dropped, running ones finish; results
+ * never collected are released.  NULL is allowed. */
+evq_status evq_server_destroy(evq_server* s);
 
 /* Release the handle; each version's device memory is released once no call still uses it.  NULL is allowed. */
 void evq_free(evq_graph* g);

@@ -71,6 +71,17 @@ class BatchConfig(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
+                ("max_groups", ctypes.c_uint32), ("mem_budget", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("reserved", ctypes.c_uint32),
+                ("t_arrival_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+                ("n_unstable", ctypes.c_uint64), ("iters_relax", ctypes.c_uint64), ("result", ResultC)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
@@ -104,6 +115,17 @@ _lib.evq_batch_config_set.restype = ctypes.c_int32
 _lib.evq_batch_config_set.argtypes = [ctypes.POINTER(BatchConfig)]
 _lib.evq_append.restype = ctypes.c_int32
 _lib.evq_append.argtypes = [_P, ctypes.POINTER(Batch), _P]
+_lib.evq_server_create.restype = ctypes.c_int32
+_lib.evq_server_create.argtypes = [_P, ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]
+_lib.evq_server_submit.restype = ctypes.c_int32
+_lib.evq_server_submit.argtypes = [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                   ctypes.POINTER(ctypes.c_uint64)]
+_lib.evq_server_poll.restype = ctypes.c_int
+_lib.evq_server_poll.argtypes = [_P, ctypes.POINTER(Completion), ctypes.c_int, ctypes.c_int]
+_lib.evq_server_pending.restype = ctypes.c_int32
+_lib.evq_server_pending.argtypes = [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]
+_lib.evq_server_destroy.restype = ctypes.c_int32
+_lib.evq_server_destroy.argtypes = [_P]
 _lib.evq_free.restype = None
 _lib.evq_free.argtypes = [_P]
 _lib.evq_last_error.restype = ctypes.c_char_p
@@ -117,7 +139,8 @@ _lib.evq_timing_report.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int]
 
 EXPORTED = ["evq_build", "evq_graph_info_get", "evq_graph_export", "evq_query", "evq_query_bounds",
             "evq_query_plain", "evq_query_batch", "evq_result_expand", "evq_result_free",
-            "evq_batch_config_get", "evq_batch_config_set", "evq_append", "evq_free", "evq_last_error", "evq_timing_enable",
+            "evq_batch_config_get", "evq_batch_config_set", "evq_append", "evq_server_create",
+            "evq_server_submit", "evq_server_poll", "evq_server_pending", "evq_server_destroy", "evq_free", "evq_last_error", "evq_timing_enable",
             "evq_timing_reset", "evq_timing_report"]
 
 
@@ -318,6 +341,59 @@ class Result:
             self.free()
         except Exception:
             pass
+
+
+class Server:
+    """Query server over a graph (evq_server_*): mode "batch" (continuous batching) or "plain" (one at a time)."""
+
+    def __init__(self, graph, mode="batch", max_batch=0, max_inflight=0, max_groups=0, mem_budget=0):
+        cfg = ServerConfig({"batch": 0, "plain": 1}[mode], max_batch, max_inflight, max_groups, mem_budget)
+        h = ctypes.c_void_p()
+        _check(_lib.evq_server_create(graph._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.graph = graph  # the handle must outlive the server
+
+    def submit(self, algo, source, win_len) -> int:
+        t = ctypes.c_uint64()
+        _check(_lib.evq_server_submit(self._h, ALGOS.get(algo, algo), source, win_len, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, cap=256, wait_ms=0) -> list:
+        """Completed queries: dicts with ticket, status, times (ms), window and a Result (None on failure)."""
+        arr = (Completion * cap)()
+        n = _lib.evq_server_poll(self._h, arr, cap, wait_ms)
+        out = []
+        for i in range(n):
+            c = arr[i]
+            r = c.result
+            out.append({"ticket": c.ticket, "status": c.status, "t_arrival_ms": c.t_arrival_ms,
+                        "t_admit_ms": c.t_admit_ms, "t_done_ms": c.t_done_ms, "n_unstable": c.n_unstable,
+                        "iters_relax": c.iters_relax, "algo": r.algo, "source": r.source,
+                        "win_begin": r.win_begin, "win_len": r.win_len,
+                        "result": Result(r) if c.status == EVQ_OK and r.d_rcap else None})
+        return out
+
+    def pending(self):
+        q, f = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(_lib.evq_server_pending(self._h, ctypes.byref(q), ctypes.byref(f)))
+        return q.value, f.value
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.evq_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def batch_config() -> dict:

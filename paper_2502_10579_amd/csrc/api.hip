@@ -6,23 +6,15 @@
 
 #include "batch.h"
 #include "evq_internal.h"
+#include "handle.h"
 
-// A graph handle holds its current version; queries take a reference to the
-// version they start on, so an append never waits for them and a version is
-// released (after the device drains) once its last query has returned.
-struct evq_graph {
-    mutable std::mutex mu;
-    std::shared_ptr<const evq::Graph> cur;
-    std::mutex append_mu;  // one append at a time
-    std::shared_ptr<const evq::Graph> get() const {
-        std::lock_guard<std::mutex> lk(mu);
-        return cur;
-    }
-};
+namespace evq {
+thread_local std::string g_last_error;
+}  // namespace evq
+
+using evq::g_last_error;
 
 namespace {
-
-thread_local std::string g_last_error;
 
 evq_status guard_exc() {
     try {
@@ -45,11 +37,6 @@ evq_status guard_exc() {
 evq_status bad(evq_status c, const char* msg) {
     g_last_error = msg;
     return c;
-}
-
-void release_graph(evq::Graph* g) {
-    (void)hipDeviceSynchronize();  // no queued kernel may still read it
-    evq::free_graph(g);
 }
 
 // Validates a query and forms the mask of the window of snapshots
@@ -88,7 +75,7 @@ evq_status evq_build(uint32_t num_vertices, const evq_edge* base, uint64_t n_bas
         evq::Graph* g = evq::build_graph(num_vertices, base, n_base, batches, K, (hipStream_t)stream);
         std::shared_ptr<const evq::Graph> sp;
         try {
-            sp = std::shared_ptr<const evq::Graph>(g, release_graph);
+            sp = std::shared_ptr<const evq::Graph>(g, evq::release_graph);
         } catch (...) {
             evq::free_graph(g);
             throw;
@@ -306,7 +293,7 @@ evq_status evq_append(evq_graph* h, const evq_batch* b, void* stream) {
         evq::Graph* g = evq::append_graph(*old, *b, (hipStream_t)stream);
         std::shared_ptr<const evq::Graph> sp;
         try {
-            sp = std::shared_ptr<const evq::Graph>(g, release_graph);
+            sp = std::shared_ptr<const evq::Graph>(g, evq::release_graph);
         } catch (...) {
             evq::free_graph(g);
             throw;

@@ -2,6 +2,11 @@
 // pool that runs every query's reduction and relaxation concurrently.
 #pragma once
 
+#include <condition_variable>
+#include <deque>
+#include <functional>
+#include <mutex>
+
 #include "bounds.h"
 
 namespace evq {
@@ -24,6 +29,27 @@ void set_batch_tuning(const BatchTuning& t);
 void batch_bounds(const Graph& g, uint32_t algo, const Window* wins, const uint32_t* sources, uint32_t nq,
                   uint32_t* const* rcap_cols, uint32_t* const* rcup_cols, const BatchTuning& tu, hipStream_t s,
                   BatchTimes& bt);
+
+// Host threads, each driving its own non-blocking stream (default priority)
+// on one device; EVQ_BATCH_WORKERS of them (default 4).  Jobs may submit
+// further jobs.  The pool lives as long as the process; each worker keeps its
+// own query workspace and host slots.
+class Pool {
+  public:
+    using Job = std::function<void(hipStream_t)>;
+    static Pool& get(int device);
+    void submit(Job j);
+    const std::vector<hipStream_t>& streams() const { return st_; }
+
+  private:
+    Pool(int device, uint32_t n);
+    void loop(uint32_t i);
+    int device_;
+    std::vector<hipStream_t> st_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::deque<Job> q_;
+};
 
 struct BatchQuery {
     uint32_t algo, source;

@@ -352,65 +352,6 @@ void set_batch_tuning(const BatchTuning& t) {
 
 namespace {
 
-// Host threads, each driving its own non-blocking stream (default priority)
-// on one device.  Jobs may submit further jobs.  The pool lives as long as
-// the process; each worker keeps its own query workspace and host slots.
-class Pool {
-  public:
-    using Job = std::function<void(hipStream_t)>;
-
-    static Pool& get(int device) {
-        static std::mutex mu;
-        static std::vector<std::pair<int, Pool*>> all;
-        std::lock_guard<std::mutex> lk(mu);
-        for (auto& kv : all)
-            if (kv.first == device) return *kv.second;
-        Pool* p = new Pool(device, std::max(1u, std::min(16u, env_u32("EVQ_BATCH_WORKERS", 4))));
-        all.push_back({device, p});
-        return *p;
-    }
-
-    void submit(Job j) {
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            q_.push_back(std::move(j));
-        }
-        cv_.notify_one();
-    }
-
-    const std::vector<hipStream_t>& streams() const { return st_; }
-
-  private:
-    Pool(int device, uint32_t n) : device_(device), st_(n, nullptr) {
-        int prev = 0;
-        EVQ_HIP(hipGetDevice(&prev));
-        EVQ_HIP(hipSetDevice(device));
-        for (uint32_t i = 0; i < n; ++i) EVQ_HIP(hipStreamCreateWithFlags(&st_[i], hipStreamNonBlocking));
-        EVQ_HIP(hipSetDevice(prev));
-        for (uint32_t i = 0; i < n; ++i) std::thread([this, i] { loop(i); }).detach();
-    }
-
-    void loop(uint32_t i) {
-        (void)hipSetDevice(device_);
-        for (;;) {
-            Job j;
-            {
-                std::unique_lock<std::mutex> lk(mu_);
-                cv_.wait(lk, [this] { return !q_.empty(); });
-                j = std::move(q_.front());
-                q_.pop_front();
-            }
-            j(st_[i]);
-        }
-    }
-
-    int device_;
-    std::vector<hipStream_t> st_;
-    std::mutex mu_;
-    std::condition_variable cv_;
-    std::deque<Job> q_;
-};
-
 // Completion count and first error of one batch.
 struct BatchState {
     std::mutex mu;
@@ -462,6 +403,50 @@ hipEvent_t new_event() {
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ worker pool
+
+Pool& Pool::get(int device) {
+    static std::mutex mu;
+    static std::vector<std::pair<int, Pool*>> all;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& kv : all)
+        if (kv.first == device) return *kv.second;
+    Pool* p = new Pool(device, std::max(1u, std::min(16u, env_u32("EVQ_BATCH_WORKERS", 4))));
+    all.push_back({device, p});
+    return *p;
+}
+
+Pool::Pool(int device, uint32_t n) : device_(device), st_(n, nullptr) {
+    int prev = 0;
+    EVQ_HIP(hipGetDevice(&prev));
+    EVQ_HIP(hipSetDevice(device));
+    for (uint32_t i = 0; i < n; ++i) EVQ_HIP(hipStreamCreateWithFlags(&st_[i], hipStreamNonBlocking));
+    EVQ_HIP(hipSetDevice(prev));
+    for (uint32_t i = 0; i < n; ++i) std::thread([this, i] { loop(i); }).detach();
+}
+
+void Pool::submit(Job j) {
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        q_.push_back(std::move(j));
+    }
+    cv_.notify_one();
+}
+
+void Pool::loop(uint32_t i) {
+    (void)hipSetDevice(device_);
+    for (;;) {
+        Job j;
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_.wait(lk, [this] { return !q_.empty(); });
+            j = std::move(q_.front());
+            q_.pop_front();
+        }
+        j(st_[i]);
+    }
+}
 
 // ------------------------------------------------------------------ batch executor
 

@@ -20,6 +20,7 @@ struct Error {
 };
 
 [[noreturn]] void fail(evq_status code, const std::string& msg);
+extern thread_local std::string g_last_error;  // message of the last failing C ABI call on this thread
 void hip_check(hipError_t e, const char* what);
 
 #define EVQ_HIP(expr) ::evq::hip_check((expr), #expr)
@@ -180,6 +181,9 @@ struct Compact {
     uint32_t nU = 0, LG = 0;
 };
 
+// Both bounds of one query into device arrays of V values.
+void run_bounds(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* rcap, uint32_t* rcup,
+                QueryOut& qo, hipStream_t s);
 // Whole query with a compact result (bound solves into c.rcap).
 void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Window& W, Compact& c, QueryOut& qo,
                        hipStream_t s);

@@ -880,6 +880,17 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     }
 }
 
+void run_bounds(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* rcap, uint32_t* rcup,
+                QueryOut& qo, hipStream_t s) {
+    init_mempool(g.device);
+    Workspace& ws = Workspace::get(s);
+    Timer tm(false, s);
+    Frontier f = make_frontier(g, ws, s);
+    f.delta = choose_delta(algo);
+    bounds_impl(g, algo, source, W, rcap, rcup, f, qo, s, tm);
+    ws.in_use = false;
+}
+
 void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Window& W, Compact& c, QueryOut& qo,
                        hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
