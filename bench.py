@@ -67,6 +67,203 @@ def algorithmic_bytes(kernel, st, L, V):
     return None
 
 
+def percentiles(x):
+    x = np.asarray(x, dtype=np.float64)
+    return {"p50": float(np.percentile(x, 50)), "p90": float(np.percentile(x, 90)),
+            "p99": float(np.percentile(x, 99)), "max": float(x.max()), "mean": float(x.mean())}
+
+
+def bench_served(args):
+    """Serving: R-MAT scale 24 ring of 128 snapshots, one append of 100k + 100k updates per second, Poisson
+    arrivals at each rate of --qps for --duration seconds; every query takes the newest len snapshots, len uniform
+    in [16, 128], algorithm uniform over the four, source random with base out-degree > 0.  The same arrival trace
+    and the same appends are replayed against the continuous-batching server and the plain one-at-a-time server,
+    each on a freshly built graph.  Latency = arrival to compact result complete on the device."""
+    import threading
+
+    import torch
+
+    import paper_2502_10579_amd as evq
+    import synth
+
+    torch.cuda.set_device(0)
+    K = 128
+    qps_list = [float(x) for x in args.qps.split(",")]
+    T = args.duration
+    n_app = int(T) + 1
+    t0 = time.time()
+    inst = synth.rmat_instance(seed=args.seed, **dict(synth.CONFIGS["served"], K=K + n_app))
+    log(f"[served] generated: base {len(inst.base)} edges, {K + n_app} batches ({time.time() - t0:.1f}s)")
+    V = inst.num_vertices
+    src_pool = synth.pick_sources(inst, 4096, seed=args.seed)
+    levels = []
+    for qps in qps_list:
+        rng = np.random.default_rng(int(qps * 1000) + args.seed)
+        arr = np.cumsum(rng.exponential(1.0 / qps, size=int(qps * T * 2) + 16))
+        arr = arr[arr < T]
+        qs = [(int(rng.integers(0, 4)), int(src_pool[int(rng.integers(0, len(src_pool)))]), int(rng.integers(16, 129)))
+              for _ in range(len(arr))]
+        lev = {"qps": qps, "queries": len(qs)}
+        for mode in ("batch", "plain"):
+            g = evq.Graph(V, inst.base, inst.dels[:K], inst.adds[:K])
+            with evq.Server(g, mode=mode) as srv:
+                # warm-up: the worker pool's buffers and the kernels' first launches
+                for i in range(16):
+                    srv.submit(i % 4, int(src_pool[i]), 128)
+                got = 0
+                while got < 16:
+                    for c in srv.poll(64, 1000):
+                        got += 1
+                        if c["result"] is not None:
+                            c["result"].free()
+                torch.cuda.synchronize()
+                app_ms = []
+                start = time.perf_counter()
+
+                def appender():
+                    for k in range(n_app - 1):
+                        dt = start + (k + 1) * 1.0 - time.perf_counter()
+                        if dt > 0:
+                            time.sleep(dt)
+                        ta = time.perf_counter()
+                        g.append(inst.dels[K + k], inst.adds[K + k])
+                        app_ms.append((time.perf_counter() - ta) * 1000.0)
+
+                def submitter():
+                    for t_arr, (a, s_, L) in zip(arr, qs):
+                        dt = start + t_arr - time.perf_counter()
+                        if dt > 0:
+                            time.sleep(dt)
+                        srv.submit(a, s_, L)
+
+                th = [threading.Thread(target=appender), threading.Thread(target=submitter)]
+                for t in th:
+                    t.start()
+                comps = []
+                while len(comps) < len(qs):
+                    for c in srv.poll(256, 50):
+                        comps.append({k: c[k] for k in ("t_arrival_ms", "t_admit_ms", "t_bounds_ms", "t_done_ms",
+                                                        "status", "group_size")})
+                        if c["result"] is not None:
+                            c["result"].free()
+                for t in th:
+                    t.join()
+                torch.cuda.synchronize()
+            g.close()
+            lat = [c["t_done_ms"] - c["t_arrival_ms"] for c in comps]
+            wait = [c["t_admit_ms"] - c["t_arrival_ms"] for c in comps]
+            span = (max(c["t_done_ms"] for c in comps) - min(c["t_arrival_ms"] for c in comps)) / 1000.0
+            bnd = [c["t_bounds_ms"] - c["t_admit_ms"] for c in comps]
+            tail = [c["t_done_ms"] - c["t_bounds_ms"] for c in comps]
+            lev[mode] = {"latency_ms": percentiles(lat), "admission_wait_ms": percentiles(wait),
+                         "bounds_ms": percentiles(bnd), "after_bounds_ms": percentiles(tail),
+                         "mean_group_size": float(np.mean([c["group_size"] for c in comps])),
+                         "completed_per_s": len(comps) / span, "failed": sum(1 for c in comps if c["status"]),
+                         "append_ms": percentiles(app_ms) if app_ms else None}
+            log(f"[served] qps {qps:g} {mode}: {len(comps)} queries, p50 {lev[mode]['latency_ms']['p50']:.1f} ms, "
+                f"p99 {lev[mode]['latency_ms']['p99']:.1f} ms, {lev[mode]['completed_per_s']:.1f}/s, "
+                f"wait p50 {lev[mode]['admission_wait_ms']['p50']:.1f}, bounds p50 {lev[mode]['bounds_ms']['p50']:.1f}, "
+                f"after p50 {lev[mode]['after_bounds_ms']['p50']:.1f} ms, group {lev[mode]['mean_group_size']:.1f}, "
+                f"appends {lev[mode]['append_ms']['p50'] if app_ms else 0:.0f} ms")
+        levels.append(lev)
+    top = levels[-1]
+    res = {
+        "metric": "served query latency p99 (ms)",
+        "value": top["batch"]["latency_ms"]["p99"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": sum(l["queries"] for l in levels),
+        "warmup": 16,
+        "ms_per_step": top["batch"]["latency_ms"]["mean"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"served: R-MAT scale 24 ({V} vertices, {inst.meta['n_samples']} samples, "
+                               f"w in [1,100]), ring of {K} snapshots of 100k+100k updates, 1 append/s, "
+                               f"Poisson arrivals {args.qps} q/s for {T:g} s, newest len in [16,128], "
+                               f"algorithm uniform over 4"},
+        "levels": levels,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def bench_batched(args):
+    """Batching: R-MAT scale 22, K = 128 snapshots of 20k + 20k updates, 256 queries (algorithm uniform over the
+    four, source random with base out-degree > 0, start uniform in [0, 100], length uniform in [25, 100] clamped
+    to the last snapshot) answered by one evq_query_batch call, against the same queries one at a time."""
+    import torch
+
+    import paper_2502_10579_amd as evq
+    import synth
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    inst = synth.config_instance("batched", seed=args.seed)
+    qs = synth.batch_queries(inst, 256, seed=args.seed)
+    log(f"[batched] generated ({time.time() - t0:.1f}s)")
+    g = evq.Graph.from_instance(inst)
+    ex = g.export()
+    counts = snapshot_edge_counts(ex, inst.K)
+    del ex
+    snap_edges = int(sum(counts[b:b + L].sum() for (_, _, b, L) in qs))
+    V = inst.num_vertices
+    out = torch.empty(V * 128, dtype=torch.int32, device="cuda")
+    for (a, s_, b, L) in qs[:8]:
+        g.query(a, s_, b, L, out=out[:V * L].view(V, L))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for (a, s_, b, L) in qs:
+        g.query(a, s_, b, L, out=out[:V * L].view(V, L))
+    torch.cuda.synchronize()
+    one_ms = (time.perf_counter() - t) * 1000.0
+    log(f"[batched] one at a time: {one_ms:.1f} ms for {len(qs)} queries")
+    rows = {}
+    for lanes in (1, 2):
+        evq.set_batch_config(lanes=lanes)
+        for r in g.query_batch(qs):
+            r.free()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(max(1, args.steps)):
+            t = time.perf_counter()
+            res = g.query_batch(qs)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1000.0
+            best = ms if best is None else min(best, ms)
+            for r in res:
+                r.free()
+        rows[lanes] = best
+        log(f"[batched] batch lanes={lanes}: {best:.1f} ms for {len(qs)} queries")
+    evq.set_batch_config(lanes=1)
+    ms = rows[1]
+    res = {
+        "metric": "snapshot-edge relaxations/s",
+        "value": snap_edges / (ms / 1000.0),
+        "unit": "snapshot-edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "batched: R-MAT scale 22 (4194304 vertices, 67108864 samples, w in [1,100]), "
+                               "K=128 snapshots of 20k+20k updates, 256 queries (algorithm uniform, start in "
+                               "[0,100], length in [25,100] clamped), compact results"},
+        "queries_per_s": len(qs) / (ms / 1000.0),
+        "batch_ms": ms,
+        "batch_one_solve_per_query_ms": rows[2],
+        "one_at_a_time_ms": one_ms,
+        "speedup_vs_one_at_a_time": one_ms / ms,
+    }
+    g.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,11 +275,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--qps", default="4,16,64", help="served: arrival rates")
+    ap.add_argument("--duration", type=float, default=6.0, help="served: seconds of arrivals per rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this build has no "
               f"multi-GPU path)", file=sys.stderr)
         sys.exit(2)
+    if args.config == "served":
+        return bench_served(args)
+    if args.config == "batched":
+        return bench_batched(args)
 
     import torch
 

@@ -297,9 +297,10 @@ typedef struct {
 typedef struct {
     uint64_t ticket;
     evq_status status;       /* EVQ_OK, or why the query failed (its result is then empty) */
-    uint32_t reserved;
+    uint32_t group_size;     /* queries whose bound solves ran together with this one's */
     double t_arrival_ms;     /* submission, ms since the server was created */
     double t_admit_ms;       /* admission (window fixed) */
+    double t_bounds_ms;      /* its bound solves issued and drained on the host */
     double t_done_ms;        /* compact result complete on the device */
     uint64_t n_unstable;
     uint64_t iters_relax;

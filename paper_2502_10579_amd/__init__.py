@@ -77,8 +77,9 @@ class ServerConfig(ctypes.Structure):
 
 
 class Completion(ctypes.Structure):
-    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("reserved", ctypes.c_uint32),
-                ("t_arrival_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("group_size", ctypes.c_uint32),
+                ("t_arrival_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double), ("t_bounds_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double),
                 ("n_unstable", ctypes.c_uint64), ("iters_relax", ctypes.c_uint64), ("result", ResultC)]
 
 
@@ -366,8 +367,9 @@ class Server:
         for i in range(n):
             c = arr[i]
             r = c.result
-            out.append({"ticket": c.ticket, "status": c.status, "t_arrival_ms": c.t_arrival_ms,
-                        "t_admit_ms": c.t_admit_ms, "t_done_ms": c.t_done_ms, "n_unstable": c.n_unstable,
+            out.append({"ticket": c.ticket, "status": c.status, "group_size": c.group_size,
+                        "t_arrival_ms": c.t_arrival_ms, "t_admit_ms": c.t_admit_ms, "t_bounds_ms": c.t_bounds_ms,
+                        "t_done_ms": c.t_done_ms, "n_unstable": c.n_unstable,
                         "iters_relax": c.iters_relax, "algo": r.algo, "source": r.source,
                         "win_begin": r.win_begin, "win_len": r.win_len,
                         "result": Result(r) if c.status == EVQ_OK and r.d_rcap else None})

@@ -1,12 +1,14 @@
-// Batched queries.  Queries of one algorithm are solved 64 at a time with one
-// query per lane: the intersection and union bound solves of all of them run
-// as one multi-lane relaxation over the shared versioned graph, lane q testing
-// the edge's presence mask against query q's own window, with the values laid
-// out [vertex][64] so that a wave reads and updates one destination row as a
-// single 256-byte span.  The frontier is the union of the queries' frontiers
-// (query-oblivious, as the snapshot-oblivious frontier of Section 4.2).  The
-// bounds are then transposed into one column per query, and each query's
-// reduction and multi-snapshot relaxation run on worker streams, concurrently,
+// Batched queries.  Queries of one algorithm are solved up to 64 at a time
+// with one query per lane: the intersection and union bound solves of all of
+// them run as one multi-lane relaxation over the shared versioned graph, lane
+// q testing the edge's presence mask against query q's own window.  Values
+// are laid out [vertex][LQ], LQ = the group size rounded up to a power of
+// two, so that a lane group of LQ lanes reads and updates one destination row
+// as one contiguous span; a wave holds 64 / LQ such groups, each on its own
+// task.  The frontier is the union of the queries' frontiers (query-
+// oblivious, as the snapshot-oblivious frontier of Section 4.2).  The bounds
+// are then transposed into one column per query, and each query's reduction
+// and multi-snapshot relaxation run on worker streams, concurrently,
 // producing a compact result (R_cap, compact ids, relaxed rows) that is
 // expanded to values[V][L] on demand.
 #include <algorithm>
@@ -25,7 +27,7 @@ namespace evq {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kLanes = 64;
+constexpr int kMaxLanes = 64;
 
 struct BatchArgs {
     const uint32_t* row_ptr;
@@ -33,13 +35,28 @@ struct BatchArgs {
     const uint32_t* col;
     const uint32_t* wgt;
     const uint64_t* mask;
-    uint32_t* X;          // [V][64] values of this solve
-    const uint64_t* win;  // [64][2] window bits per lane (0 for an unused lane)
+    uint32_t* X;          // [V][LQ] values of this solve
+    const uint64_t* win;  // [LQ][2] window bits per lane (0 for an unused lane)
     uint8_t* flags;
     uint64_t* tasks;      // (chunk << 32 | vertex)
     FrontierCounters* cnt;
     uint32_t V;
     uint32_t chunk;       // edges per task
+    uint32_t LQ;          // lanes per row: 1, 2, 4, ..., 64
+};
+
+// Lane layout of a wave: 64 / LQ groups of LQ lanes.
+struct LaneGroup {
+    uint32_t q, g, G;
+    uint64_t gmask;  // this group's lanes in a ballot
+    __device__ explicit LaneGroup(uint32_t LQ) {
+        const uint32_t l = lane_id();
+        q = l & (LQ - 1);
+        g = l / LQ;
+        G = 64 / LQ;
+        gmask = (LQ >= 64 ? ~0ull : ((1ull << LQ) - 1ull)) << (g * LQ);
+    }
+    __device__ bool any(bool x) const { return (__ballot(x) & gmask) != 0; }
 };
 
 // Frontier vertices -> tasks of `chunk` edges of their union rows.
@@ -71,15 +88,17 @@ __device__ __forceinline__ bool lane_has(const uint64_t* __restrict__ mask, uint
     return cup ? any : all;
 }
 
-// One iteration of the batched bound solve: each wave takes one task (up to
-// CH edges of one vertex); lane q relaxes query q over the edges present in
-// its window's intersection (CUP = false) or union (CUP = true).
+// One iteration of the batched bound solve: each lane group takes one task
+// (up to CH edges of one vertex); lane q relaxes query q over the edges
+// present in its window's intersection (CUP = false) or union (CUP = true).
 template <int A, bool CUP, int MW, int CH>
 __global__ void __launch_bounds__(kBlock) k_bexpand(BatchArgs a, int p, uint32_t* slot) {
     const unsigned long long cx = expand_prologue(a.cnt, p, slot);
     const uint32_t n = items_of(cx);
     if (n == 0) return;
-    const uint32_t q = lane_id();
+    const uint32_t LQ = a.LQ;
+    const LaneGroup lg(LQ);
+    const uint32_t q = lg.q;
     uint64_t w[MW];
     bool used = false;
 #pragma unroll
@@ -89,13 +108,19 @@ __global__ void __launch_bounds__(kBlock) k_bexpand(BatchArgs a, int p, uint32_t
     }
     const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint32_t nw = gridDim.x * (kBlock / 64);
-    for (uint32_t t = gw; t < n; t += nw) {
-        const uint64_t tk = a.tasks[t];
-        const uint32_t u = uniform((uint32_t)tk), ch = uniform((uint32_t)(tk >> 32));
-        const uint32_t rb = a.row_ptr[u], re = a.row_ptr[u + 1], split = a.row_split[u];
-        const uint32_t e0 = rb + ch * CH;
-        const uint32_t ne = re - e0 < (uint32_t)CH ? re - e0 : (uint32_t)CH;
-        const uint32_t xu = a.X[(uint64_t)u * kLanes + q];
+    for (uint32_t tb = gw * lg.G; tb < n; tb += nw * lg.G) {
+        const uint32_t t = tb + lg.g;
+        uint32_t u = 0, ne = 0, e0 = 0, split = 0;
+        if (t < n) {
+            const uint64_t tk = a.tasks[t];
+            u = (uint32_t)tk;
+            const uint32_t ch = (uint32_t)(tk >> 32);
+            const uint32_t rb = a.row_ptr[u], re = a.row_ptr[u + 1];
+            split = a.row_split[u];
+            e0 = rb + ch * CH;
+            ne = re - e0 < (uint32_t)CH ? re - e0 : (uint32_t)CH;
+        }
+        const uint32_t xu = ne ? a.X[(uint64_t)u * LQ + q] : 0u;
         uint32_t dst[CH], wt[CH], cur[CH];
         bool in[CH];
 #pragma unroll
@@ -111,18 +136,18 @@ __global__ void __launch_bounds__(kBlock) k_bexpand(BatchArgs a, int p, uint32_t
             }
         }
 #pragma unroll
-        for (int k = 0; k < CH; ++k) cur[k] = in[k] ? a.X[(uint64_t)dst[k] * kLanes + q] : 0u;
+        for (int k = 0; k < CH; ++k) cur[k] = in[k] ? a.X[(uint64_t)dst[k] * LQ + q] : 0u;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
             bool imp = false;
             if (in[k]) {
                 const uint32_t cand = Alg<A>::extend(xu, wt[k]);
                 if (Alg<A>::better(cand, cur[k])) {
-                    Alg<A>::improve_nr(&a.X[(uint64_t)dst[k] * kLanes + q], cand);
+                    Alg<A>::improve_nr(&a.X[(uint64_t)dst[k] * LQ + q], cand);
                     imp = true;
                 }
             }
-            if (__ballot(imp) && q == 0) mark(a.flags, dst[k]);
+            if (lg.any(imp) && q == 0) mark(a.flags, dst[k]);
         }
     }
 }
@@ -133,21 +158,23 @@ __global__ void k_binit(uint32_t* X, uint64_t n, uint32_t unreached) {
         X[i] = unreached;
 }
 
-__global__ void k_bsources(uint32_t* X, uint8_t* flags, const uint32_t* __restrict__ src, uint32_t nq,
+__global__ void k_bsources(uint32_t* X, uint8_t* flags, const uint32_t* __restrict__ src, uint32_t nq, uint32_t LQ,
                            uint32_t at_source) {
     const uint32_t q = threadIdx.x;
     if (q < nq) {
-        X[(uint64_t)src[q] * kLanes + q] = at_source;
+        X[(uint64_t)src[q] * LQ + q] = at_source;
         flags[src[q]] = 1;
     }
 }
 
 // Union solve, first step: every edge partial in some lane's window relaxes
-// that lane from the intersection values.
+// that lane from the intersection values (one partial edge per lane group).
 template <int A, int MW>
 __global__ void __launch_bounds__(kBlock) k_bseed(BatchArgs a, const uint32_t* __restrict__ p_src,
                                                   const uint32_t* __restrict__ p_eid, uint32_t n_partial) {
-    const uint32_t q = lane_id();
+    const uint32_t LQ = a.LQ;
+    const LaneGroup lg(LQ);
+    const uint32_t q = lg.q;
     uint64_t w[MW];
     bool used = false;
 #pragma unroll
@@ -157,48 +184,54 @@ __global__ void __launch_bounds__(kBlock) k_bseed(BatchArgs a, const uint32_t* _
     }
     const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint32_t nw = gridDim.x * (kBlock / 64);
-    for (uint32_t i = gw; i < n_partial; i += nw) {
-        const uint32_t e = uniform(p_eid[i]);
-        const uint32_t u = uniform(p_src[i]);
-        bool any = false, all = true;
+    for (uint32_t ib = gw * lg.G; ib < n_partial; ib += nw * lg.G) {
+        const uint32_t i = ib + lg.g;
+        bool act = false;
+        uint32_t u = 0, e = 0;
+        if (i < n_partial) {
+            e = p_eid[i];
+            u = p_src[i];
+            bool any = false, all = true;
 #pragma unroll
-        for (int j = 0; j < MW; ++j) {
-            const uint64_t m = a.mask[(uint64_t)e * MW + j] & w[j];
-            any |= m != 0;
-            all &= m == w[j];
+            for (int j = 0; j < MW; ++j) {
+                const uint64_t m = a.mask[(uint64_t)e * MW + j] & w[j];
+                any |= m != 0;
+                all &= m == w[j];
+            }
+            act = used && any && !all;
         }
-        const bool act = used && any && !all;
         if (!__ballot(act)) continue;
-        const uint32_t v = a.col[e];
         bool imp = false;
+        uint32_t v = 0;
         if (act) {
-            const uint32_t cand = Alg<A>::extend(a.X[(uint64_t)u * kLanes + q], a.wgt[e]);
-            uint32_t* px = &a.X[(uint64_t)v * kLanes + q];
+            v = a.col[e];
+            const uint32_t cand = Alg<A>::extend(a.X[(uint64_t)u * LQ + q], a.wgt[e]);
+            uint32_t* px = &a.X[(uint64_t)v * LQ + q];
             if (Alg<A>::better(cand, *px)) {
                 Alg<A>::improve_nr(px, cand);
                 imp = true;
             }
         }
-        if (__ballot(imp) && q == 0) mark(a.flags, v);
+        // the group's lanes share e and so v; any improving lane marks it
+        const uint64_t bal = __ballot(imp) & lg.gmask;
+        if (bal && lane_id() == (uint32_t)__ffsll((unsigned long long)bal) - 1) mark(a.flags, v);
     }
 }
 
-// [V][64] -> column q of each used lane (cols[q][v]), through a 64 x 64 LDS tile.
-__global__ void __launch_bounds__(256) k_transpose(const uint32_t* __restrict__ X, uint32_t V,
+// [V][LQ] -> column q of each used lane (cols[q][v]), through a 64-vertex LDS tile.
+__global__ void __launch_bounds__(256) k_transpose(const uint32_t* __restrict__ X, uint32_t V, uint32_t LQ,
                                                    uint32_t* const* __restrict__ cols, uint32_t nq) {
     __shared__ uint32_t tile[64][65];
-    const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (uint64_t v0 = (uint64_t)blockIdx.x * 64; v0 < V; v0 += (uint64_t)gridDim.x * 64) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const uint32_t r = ty + 4 * k;
-            tile[r][tx] = v0 + r < V ? X[(v0 + r) * kLanes + tx] : 0u;
+        const uint32_t nv = V - v0 < 64 ? (uint32_t)(V - v0) : 64u;
+        for (uint32_t k = threadIdx.x; k < 64 * LQ; k += 256) {
+            const uint32_t r = k / LQ, c = k - r * LQ;
+            tile[r][c] = r < nv ? X[(v0 + r) * LQ + c] : 0u;
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const uint32_t q = ty + 4 * k;
-            if (q < nq && v0 + tx < V) cols[q][v0 + tx] = tile[tx][q];
+        for (uint32_t k = threadIdx.x; k < 64 * nq; k += 256) {
+            const uint32_t q = k / 64, r = k - q * 64;
+            if (r < nv) cols[q][v0 + r] = tile[r][q];
         }
         __syncthreads();
     }
@@ -228,17 +261,17 @@ void batch_loop(BatchArgs a, uint32_t chunk, uint32_t blocks, Frontier& f, hipSt
 template <int A, int MW>
 void batch_bounds_t(const Graph& g, BatchArgs a, uint32_t* Xcap, uint32_t* Xcup, const uint32_t* d_src, uint32_t nq,
                     const BatchTuning& tu, Frontier& f, hipStream_t s, BatchTimes& bt) {
-    const uint64_t n = (uint64_t)g.V * kLanes;
+    const uint64_t n = (uint64_t)g.V * a.LQ;
     EVQ_LAUNCH("batch_init", k_binit, grid_for(n, 256 * 8, 16384), 256, s, Xcap, n, Alg<A>::unreached);
-    EVQ_LAUNCH("batch_init", k_bsources, 1, 64, s, Xcap, f.flags, d_src, nq, Alg<A>::at_source);
+    EVQ_LAUNCH("batch_init", k_bsources, 1, 64, s, Xcap, f.flags, d_src, nq, a.LQ, Alg<A>::at_source);
     a.X = Xcap;
     batch_loop<A, false, MW>(a, tu.chunk, tu.blocks, f, s, (uint64_t)g.V + 2, &bt.iters_cap);
-    EVQ_LAUNCH("batch_copy", k_copy_u32x4, grid_for(n / 4, 256 * 4, 16384), 256, s,
-               reinterpret_cast<const uint4*>(Xcap), reinterpret_cast<uint4*>(Xcup), n / 4);
+    EVQ_LAUNCH("batch_copy", k_copy_u32x4, grid_for((n + 3) / 4, 256 * 4, 16384), 256, s,
+               reinterpret_cast<const uint4*>(Xcap), reinterpret_cast<uint4*>(Xcup), (n + 3) / 4);
     a.X = Xcup;
     if (g.n_partial)
-        EVQ_LAUNCH("batch_seed", (k_bseed<A, MW>), grid_for(g.n_partial, kBlock / 64, 16384), kBlock, s, a, g.p_src,
-                   g.p_eid, (uint32_t)g.n_partial);
+        EVQ_LAUNCH("batch_seed", (k_bseed<A, MW>), grid_for((g.n_partial + 63) / 64 * a.LQ, kBlock / 64, 16384), kBlock,
+                   s, a, g.p_src, g.p_eid, (uint32_t)g.n_partial);
     batch_loop<A, true, MW>(a, tu.chunk, tu.blocks, f, s, (uint64_t)g.V + 2, &bt.iters_cup);
 }
 
@@ -261,22 +294,24 @@ void batch_bounds_mw(uint32_t algo, const Graph& g, BatchArgs a, uint32_t* Xcap,
 void batch_bounds(const Graph& g, uint32_t algo, const Window* wins, const uint32_t* sources, uint32_t nq,
                   uint32_t* const* rcap_cols, uint32_t* const* rcup_cols, const BatchTuning& tu, hipStream_t s,
                   BatchTimes& bt) {
-    if (nq == 0 || nq > (uint32_t)kLanes) fail(EVQ_EINVAL, "a batch holds 1..64 queries");
+    if (nq == 0 || nq > (uint32_t)kMaxLanes) fail(EVQ_EINVAL, "a batch holds 1..64 queries");
+    uint32_t LQ = 1;
+    while (LQ < nq) LQ <<= 1;
     Workspace& ws = Workspace::get(s);
     Frontier f = make_frontier(g, ws, s);
-    const uint64_t n = (uint64_t)g.V * kLanes;
-    uint32_t* Xcap = ws.buf<uint32_t>(Workspace::kBatchCap, n);
-    uint32_t* Xcup = ws.buf<uint32_t>(Workspace::kBatchCup, n);
+    const uint64_t n = (uint64_t)g.V * LQ;
+    uint32_t* Xcap = ws.buf<uint32_t>(Workspace::kBatchCap, n + 4);
+    uint32_t* Xcup = ws.buf<uint32_t>(Workspace::kBatchCup, n + 4);
     // per-lane table: windows (2 words), sources, column pointers
-    std::vector<uint64_t> hwin(kLanes * 2, 0ull);
-    std::vector<uint32_t> hsrc(kLanes, 0u);
-    std::vector<uint32_t*> hcols(2 * kLanes, nullptr);
+    std::vector<uint64_t> hwin(kMaxLanes * 2, 0ull);
+    std::vector<uint32_t> hsrc(kMaxLanes, 0u);
+    std::vector<uint32_t*> hcols(2 * kMaxLanes, nullptr);
     for (uint32_t i = 0; i < nq; ++i) {
         hwin[2 * i] = wins[i].w[0];
         hwin[2 * i + 1] = wins[i].w[1];
         hsrc[i] = sources[i];
         hcols[i] = rcap_cols[i];
-        hcols[kLanes + i] = rcup_cols[i];
+        hcols[kMaxLanes + i] = rcup_cols[i];
     }
     char* tab = ws.buf<char>(Workspace::kBatchTable, 4096);
     uint64_t* d_win = reinterpret_cast<uint64_t*>(tab);
@@ -298,11 +333,12 @@ void batch_bounds(const Graph& g, uint32_t algo, const Window* wins, const uint3
     a.cnt = f.cnt;
     a.V = g.V;
     a.chunk = tu.chunk;
+    a.LQ = LQ;
     if (g.MW == 1) batch_bounds_mw<1>(algo, g, a, Xcap, Xcup, d_src, nq, tu, f, s, bt);
     else batch_bounds_mw<2>(algo, g, a, Xcap, Xcup, d_src, nq, tu, f, s, bt);
     const uint32_t tb = grid_for(g.V, 64, 16384);
-    EVQ_LAUNCH("batch_transpose", k_transpose, tb, 256, s, Xcap, g.V, d_cols, nq);
-    EVQ_LAUNCH("batch_transpose", k_transpose, tb, 256, s, Xcup, g.V, d_cols + kLanes, nq);
+    EVQ_LAUNCH("batch_transpose", k_transpose, tb, 256, s, Xcap, g.V, LQ, d_cols, nq);
+    EVQ_LAUNCH("batch_transpose", k_transpose, tb, 256, s, Xcup, g.V, LQ, d_cols + kMaxLanes, nq);
     ws.in_use = false;
 }
 

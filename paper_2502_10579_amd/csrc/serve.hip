@@ -27,7 +27,8 @@ namespace {
 struct SQuery {
     uint64_t ticket = 0;
     uint32_t algo = 0, source = 0, len = 0;
-    double t_arrival = 0, t_admit = 0, t_done = 0;
+    double t_arrival = 0, t_admit = 0, t_bounds = 0, t_done = 0;
+    uint32_t group = 1;
     uint64_t win_begin = 0;
     uint32_t win_len = 0, V = 0;
     uint64_t footprint = 0;
@@ -70,7 +71,6 @@ struct evq_server {
     double est_unstable[4] = {0, 0, 0, 0};  // running estimate of |U| / V per algorithm
     bool stop = false;
     std::thread dispatcher;
-    hipStream_t plain_stream = nullptr;
 
     double now() const {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -154,6 +154,7 @@ void launch_group(evq_server* sv, std::shared_ptr<const Graph> gp, std::vector<S
                 q->c.rcap = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
                 q->rcup = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
                 run_bounds(g, q->algo, q->source, W, q->c.rcap, q->rcup, q->qo, ws);
+                q->t_bounds = sv->now();
             } catch (...) {
                 ok = false;
                 fail_query(q, current_error(), ws);
@@ -201,9 +202,12 @@ void launch_group(evq_server* sv, std::shared_ptr<const Graph> gp, std::vector<S
             batch_bounds(g, grp[0]->algo, wins.data(), srcs.data(), nq, rcap.data(), rcup.data(), tu, ws, bt);
             EVQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
             EVQ_HIP(hipEventRecord(ev, ws));
+            const double tb = sv->now();
             for (SQuery* q : grp) {
                 q->qo.st.iters_cap = bt.iters_cap;
                 q->qo.st.iters_cup = bt.iters_cup;
+                q->t_bounds = tb;
+                q->group = nq;
             }
         } catch (...) {
             ok = false;
@@ -259,21 +263,26 @@ void dispatch_loop(evq_server* sv) {
         std::shared_ptr<const Graph> gp = sv->h->get();
         const Graph& g = *gp;
         if (sv->cfg.mode == 1) {
-            // plain: one query at a time, in arrival order, on this thread
+            // plain: one query at a time, in arrival order, on one worker
             SQuery* q = sv->queue.front();
             sv->queue.pop_front();
             admit(sv, q, g);
             q->footprint = 0;
             sv->inflight += 1;
             lk.unlock();
-            try {
-                q->c.rcap = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, sv->plain_stream));
-                run_query_compact(g, q->algo, q->source, window_of(g, q), q->c, q->qo, sv->plain_stream);
-            } catch (...) {
-                fail_query(q, current_error(), sv->plain_stream);
-            }
-            complete(sv, q, g, sv->plain_stream);
+            Pool::get(sv->device).submit([sv, gp, q](hipStream_t ws) {
+                const Graph& g = *gp;
+                try {
+                    q->c.rcap = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
+                    run_query_compact(g, q->algo, q->source, window_of(g, q), q->c, q->qo, ws);
+                } catch (...) {
+                    fail_query(q, current_error(), ws);
+                }
+                q->t_bounds = sv->now();
+                complete(sv, q, g, ws);
+            });
             lk.lock();
+            sv->cv.wait(lk, [sv] { return sv->inflight == 0; });
             continue;
         }
         // continuous batching: the oldest query picks the algorithm; others of
@@ -346,7 +355,6 @@ evq_status evq_server_create(evq_graph* h, const evq_server_config* c, evq_serve
         sv->cfg = cfg;
         sv->device = gp->device;
         sv->t0 = std::chrono::steady_clock::now();
-        if (cfg.mode == 1) EVQ_HIP(hipStreamCreateWithFlags(&sv->plain_stream, hipStreamNonBlocking));
         sv->dispatcher = std::thread([sv] { evq::dispatch_loop(sv); });
         *out = sv;
         return EVQ_OK;
@@ -400,7 +408,9 @@ int evq_server_poll(evq_server* sv, evq_completion* out, int cap, int wait_ms) {
         c.status = q->status;
         c.t_arrival_ms = q->t_arrival;
         c.t_admit_ms = q->t_admit;
+        c.t_bounds_ms = q->t_bounds;
         c.t_done_ms = q->t_done;
+        c.group_size = q->group;
         evq_result& r = c.result;
         r.algo = q->algo;
         r.source = q->source;
@@ -456,7 +466,6 @@ evq_status evq_server_destroy(evq_server* sv) {
         delete q;
     }
     (void)hipDeviceSynchronize();
-    if (sv->plain_stream) (void)hipStreamDestroy(sv->plain_stream);
     delete sv;
     return EVQ_OK;
 }
