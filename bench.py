@@ -43,6 +43,28 @@ def snapshot_edge_counts(ex, K):
     return counts
 
 
+def counter_traffic(kernel):
+    """HBM traffic per dispatch of `kernel` from the committed rocprofv3 counter summary, or (None, reason)
+    when there is none or the kernel's sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+    for path in glob.glob(os.path.join(ROOT, "profiles", "counters_*.md")):
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+        if not m:
+            continue
+        blk = json.loads(m.group(1))
+        if blk.get("timing_name") != kernel:
+            continue
+        h = hashlib.sha256()
+        for f in blk["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != blk["sources_sha256"]:
+            return None, f"{os.path.basename(path)}: kernel sources changed since the counters were taken"
+        return blk["traffic_bytes_per_dispatch"], os.path.basename(path)
+    return None, "no counter summary for this kernel"
+
+
 def algorithmic_bytes(kernel, st, L, V):
     """Bytes a kernel's work must move at minimum, from the query's counters.
 
@@ -219,9 +241,14 @@ def bench_batched(args):
     torch.cuda.synchronize()
     one_ms = (time.perf_counter() - t) * 1000.0
     log(f"[batched] one at a time: {one_ms:.1f} ms for {len(qs)} queries")
+    if args.no_autotune:
+        cfg, tune_ms = evq.batch_config(), None
+    else:
+        cfg, tune_ms = g.autotune_batch(qs)
+    log(f"[batched] execution choices: {cfg} (autotune best {tune_ms} ms)")
     rows = {}
     for lanes in (1, 2):
-        evq.set_batch_config(lanes=lanes)
+        evq.set_batch_config(lanes=lanes, chunk=cfg["chunk"], blocks=cfg["blocks"])
         for r in g.query_batch(qs):
             r.free()
         torch.cuda.synchronize()
@@ -236,8 +263,8 @@ def bench_batched(args):
                 r.free()
         rows[lanes] = best
         log(f"[batched] batch lanes={lanes}: {best:.1f} ms for {len(qs)} queries")
-    evq.set_batch_config(lanes=1)
-    ms = rows[1]
+    evq.set_batch_config(**cfg)
+    ms = min(rows[1], rows[2])
     res = {
         "metric": "snapshot-edge relaxations/s",
         "value": snap_edges / (ms / 1000.0),
@@ -255,7 +282,9 @@ def bench_batched(args):
                                "K=128 snapshots of 20k+20k updates, 256 queries (algorithm uniform, start in "
                                "[0,100], length in [25,100] clamped), compact results"},
         "queries_per_s": len(qs) / (ms / 1000.0),
+        "batch_config": cfg,
         "batch_ms": ms,
+        "batch_shared_solves_ms": rows[1],
         "batch_one_solve_per_query_ms": rows[2],
         "one_at_a_time_ms": one_ms,
         "speedup_vs_one_at_a_time": one_ms / ms,
@@ -275,6 +304,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="batched: keep the current execution choices")
     ap.add_argument("--qps", default="4,16,64", help="served: arrival rates")
     ap.add_argument("--duration", type=float, default=6.0, help="served: seconds of arrivals per rate")
     args = ap.parse_args()
@@ -357,10 +387,16 @@ def main():
         byts = algorithmic_bytes(dom, st, L, inst.num_vertices)
         if byts is not None:
             ach = byts * reps / (tot_ms / 1000.0) / 1e9
+            avg_us = tot_ms * 1000.0 / launches
+            traffic, tsrc = counter_traffic(dom)
             roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-                    "avg_launch_us": round(tot_ms * 1000.0 / launches, 3), "launches_per_query": launches // reps,
-                    "algorithmic_bytes_per_query": int(byts)}
+                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
+                    "avg_launch_us": round(avg_us, 3), "launches_per_query": launches // reps,
+                    "algorithmic_bytes_per_query": int(byts),
+                    "algorithmic_bytes_per_launch": int(byts * reps / launches), "traffic_source": tsrc}
+            if traffic:
+                roof["traffic_GBps"] = round(traffic / (avg_us * 1e-6) / 1e9, 2)
+                roof["traffic_frac"] = round(traffic / (avg_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
         relax_b = algorithmic_bytes("relax", st, L, inst.num_vertices)
         if "relax" in kernels and relax_b:
             rl, rt = kernels["relax"]

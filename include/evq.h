@@ -252,6 +252,17 @@ evq_status evq_batch_config_get(evq_batch_config* c);
 evq_status evq_batch_config_set(const evq_batch_config* c);
 
 /*
+ * Autotune: run evq_query_batch on the caller's n queries once to warm up,
+ * then once under each candidate choice (shared solves with chunk 4/8/16 and
+ * 256-thread workgroups 1024/2048/4096 per expansion, and one solve per
+ * query), discard the results, and install the fastest for this process.
+ * chosen / best_ms (host, nullable) receive it and its wall time.
+ * Synchronises `stream`.  Errors as evq_query_batch.
+ */
+evq_status evq_batch_autotune(const evq_graph* g, const evq_query_desc* q, uint32_t n, evq_batch_config* chosen,
+                              double* best_ms, void* stream);
+
+/*
  * Serving store: advance the window of held snapshots by one.  The new
  * snapshot first+K is the newest held snapshot with batch `b` applied
  * (deletions before additions, as in evq_build); it takes the mask bit of

@@ -127,6 +127,9 @@ _lib.evq_server_pending.restype = ctypes.c_int32
 _lib.evq_server_pending.argtypes = [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]
 _lib.evq_server_destroy.restype = ctypes.c_int32
 _lib.evq_server_destroy.argtypes = [_P]
+_lib.evq_batch_autotune.restype = ctypes.c_int32
+_lib.evq_batch_autotune.argtypes = [_P, ctypes.POINTER(QueryDesc), ctypes.c_uint32, ctypes.POINTER(BatchConfig),
+                                    ctypes.POINTER(ctypes.c_double), _P]
 _lib.evq_free.restype = None
 _lib.evq_free.argtypes = [_P]
 _lib.evq_last_error.restype = ctypes.c_char_p
@@ -140,7 +143,7 @@ _lib.evq_timing_report.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int]
 
 EXPORTED = ["evq_build", "evq_graph_info_get", "evq_graph_export", "evq_query", "evq_query_bounds",
             "evq_query_plain", "evq_query_batch", "evq_result_expand", "evq_result_free",
-            "evq_batch_config_get", "evq_batch_config_set", "evq_append", "evq_server_create",
+            "evq_batch_config_get", "evq_batch_config_set", "evq_batch_autotune", "evq_append", "evq_server_create",
             "evq_server_submit", "evq_server_poll", "evq_server_pending", "evq_server_destroy", "evq_free", "evq_last_error", "evq_timing_enable",
             "evq_timing_reset", "evq_timing_report"]
 
@@ -308,6 +311,19 @@ class Graph:
         _check(_lib.evq_query_batch(self._h, descs, n, res, st, _stream(stream)))
         out = [Result(res[i]) for i in range(n)]
         return (out, [st[i].as_dict() for i in range(n)]) if stats else out
+
+
+    def autotune_batch(self, queries, stream=None):
+        """Time query_batch's execution choices on these queries and install the fastest (evq_batch_autotune).
+        Returns (config dict, best milliseconds)."""
+        qs = list(queries)
+        descs = (QueryDesc * max(len(qs), 1))()
+        for i, (a, src, b, L) in enumerate(qs):
+            descs[i] = QueryDesc(ALGOS.get(a, a), src, b, L)
+        c = BatchConfig()
+        ms = ctypes.c_double()
+        _check(_lib.evq_batch_autotune(self._h, descs, len(qs), ctypes.byref(c), ctypes.byref(ms), _stream(stream)))
+        return {"lanes": c.lanes, "chunk": c.chunk, "blocks": c.blocks}, ms.value
 
 
 class Result:

@@ -308,6 +308,36 @@ evq_status evq_append(evq_graph* h, const evq_batch* b, void* stream) {
     }
 }
 
+evq_status evq_batch_autotune(const evq_graph* h, const evq_query_desc* q, uint32_t n, evq_batch_config* chosen,
+                              double* best_ms, void* stream) {
+    g_last_error.clear();
+    if (!h || !q) return bad(EVQ_EINVAL, "NULL argument");
+    if (n == 0 || n > 65536) return bad(EVQ_ERANGE, "a batch holds 1..65536 queries");
+    try {
+        auto gp = h->get();
+        std::vector<evq::BatchQuery> bq(n);
+        for (uint32_t i = 0; i < n; ++i) {
+            evq_status rc = make_window(*gp, q[i].algo, q[i].source, q[i].win_begin, q[i].win_len, bq[i].W);
+            if (rc != EVQ_OK) {
+                g_last_error = "query " + std::to_string(i) + ": " + g_last_error;
+                return rc;
+            }
+            bq[i].algo = q[i].algo;
+            bq[i].source = q[i].source;
+        }
+        const evq::BatchTuning t = evq::autotune_batch(*gp, bq.data(), n, (hipStream_t)stream, best_ms);
+        if (chosen) {
+            std::memset(chosen, 0, sizeof(*chosen));
+            chosen->lanes = t.lanes;
+            chosen->chunk = t.chunk;
+            chosen->blocks = t.blocks;
+        }
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
 void evq_free(evq_graph* h) {
     if (!h) return;
     {

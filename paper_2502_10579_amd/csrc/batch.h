@@ -62,4 +62,7 @@ struct BatchQuery {
 void run_batch(const Graph& g, const BatchQuery* q, uint32_t n, Compact* out, evq_query_stats* stats,
                hipStream_t s);
 
+// Tries the execution choices on the given queries and installs the fastest.
+BatchTuning autotune_batch(const Graph& g, const BatchQuery* q, uint32_t n, hipStream_t s, double* best_ms);
+
 }  // namespace evq

@@ -635,4 +635,55 @@ void run_batch(const Graph& g, const BatchQuery* q, uint32_t n, Compact* out, ev
     }
 }
 
+// Times run_batch on the caller's queries under each candidate (lanes,
+// chunk, blocks), after one warm-up run, and installs the fastest.
+BatchTuning autotune_batch(const Graph& g, const BatchQuery* q, uint32_t n, hipStream_t s, double* best_ms) {
+    std::vector<BatchTuning> cand;
+    for (uint32_t chunk : {4u, 8u, 16u})
+        for (uint32_t blocks : {1024u, 2048u, 4096u}) {
+            BatchTuning t;
+            t.lanes = 1;
+            t.chunk = chunk;
+            t.blocks = blocks;
+            cand.push_back(t);
+        }
+    BatchTuning one;
+    one.lanes = 2;
+    cand.push_back(one);
+    const BatchTuning before = batch_tuning();
+    std::vector<Compact> out(n);
+    auto run = [&]() {
+        run_batch(g, q, n, out.data(), nullptr, s);
+        EVQ_HIP(hipStreamSynchronize(s));
+        for (Compact& c : out) {
+            stream_free(c.rcap, s);
+            stream_free(c.ulist, s);
+            c = Compact{};
+        }
+        EVQ_HIP(hipStreamSynchronize(s));
+    };
+    BatchTuning best = before;
+    double best_t = 1e300;
+    try {
+        set_batch_tuning(before);
+        run();  // warm-up: workspaces, first launches
+        for (const BatchTuning& t : cand) {
+            set_batch_tuning(t);
+            const auto t0 = std::chrono::steady_clock::now();
+            run();
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (ms < best_t) {
+                best_t = ms;
+                best = t;
+            }
+        }
+    } catch (...) {
+        set_batch_tuning(before);
+        throw;
+    }
+    set_batch_tuning(best);
+    if (best_ms) *best_ms = best_t;
+    return best;
+}
+
 }  // namespace evq

@@ -131,3 +131,21 @@ def test_batch_result_free_and_reuse(evq):
         for r, (a, s, b, L) in list(zip(r1, qs))[1:]:
             want = oracle.window_values(inst, a, s, b, L, replayed=rep)
             assert_equal_values(evq.to_u32(r.expand()).reshape(inst.num_vertices, L), want, str((a, s, b, L)))
+
+
+def test_batch_autotune_installs_a_valid_choice(evq):
+    import torch
+    inst = synth.config_instance("small", seed=8)
+    qs = synth.batch_queries(inst, 48, seed=8, start_max=7, len_min=1, len_max=8)
+    rep = oracle.replay(inst)
+    with evq.Graph.from_instance(inst) as g:
+        cfg, ms = g.autotune_batch(qs)
+        assert cfg == evq.batch_config()
+        assert cfg["lanes"] in (1, 2) and cfg["chunk"] in (4, 8, 16) and 64 <= cfg["blocks"] <= 16384 and ms > 0
+        res = g.query_batch(qs)
+        torch.cuda.synchronize()
+        for r, (a, s, b, L) in zip(res, qs):
+            want = oracle.window_values(inst, a, s, b, L, replayed=rep)
+            assert_equal_values(evq.to_u32(r.expand()).reshape(inst.num_vertices, L), want, str((a, s, b, L)))
+            r.free()
+    evq.set_batch_config(lanes=1, chunk=8, blocks=2048)
