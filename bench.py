@@ -128,7 +128,7 @@ def bench_served(args):
         lev = {"qps": qps, "queries": len(qs)}
         for mode in ("batch", "plain"):
             g = evq.Graph(V, inst.base, inst.dels[:K], inst.adds[:K])
-            with evq.Server(g, mode=mode) as srv:
+            with evq.Server(g, mode=mode, max_groups=args.max_groups, max_batch=args.max_batch) as srv:
                 # warm-up: the worker pool's buffers and the kernels' first launches
                 for i in range(16):
                     srv.submit(i % 4, int(src_pool[i]), 128)
@@ -143,7 +143,7 @@ def bench_served(args):
                 start = time.perf_counter()
 
                 def appender():
-                    for k in range(n_app - 1):
+                    for k in range(0 if args.no_appends else n_app - 1):
                         dt = start + (k + 1) * 1.0 - time.perf_counter()
                         if dt > 0:
                             time.sleep(dt)
@@ -307,6 +307,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="batched: keep the current execution choices")
     ap.add_argument("--qps", default="4,16,64", help="served: arrival rates")
     ap.add_argument("--duration", type=float, default=6.0, help="served: seconds of arrivals per rate")
+    ap.add_argument("--max-groups", type=int, default=0, help="served: group solves at once (0: server default)")
+    ap.add_argument("--max-batch", type=int, default=0, help="served: queries per group (0: server default)")
+    ap.add_argument("--no-appends", action="store_true", help="served: no appends during the run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this build has no "
@@ -367,6 +370,34 @@ def main():
         plain_ms = (time.perf_counter() - t) * 1000.0 / n_plain
         same = bool(torch.equal(out, outp))
         log(f"[bench] plain concurrent evaluation: {plain_ms:.3f} ms/query, identical={same}")
+
+    # batching leg on the same graph: 64 mixed queries of the batched recipe (algorithm uniform, random
+    # source, start in [0, K - 25], length in [25, K] clamped), one call against one at a time
+    batch_leg = None
+    if not args.no_plain:
+        bq = synth.batch_queries(inst, 64, seed=args.seed, start_max=K - 25, len_min=25, len_max=K)
+        V = inst.num_vertices
+        buf = torch.empty(V * K, dtype=torch.int32, device="cuda")
+        for (a, s_, b_, L_) in bq[:4]:
+            g.query(a, s_, b_, L_, out=buf[:V * L_].view(V, L_))
+        for r in g.query_batch(bq):
+            r.free()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for (a, s_, b_, L_) in bq:
+            g.query(a, s_, b_, L_, out=buf[:V * L_].view(V, L_))
+        torch.cuda.synchronize()
+        one_ms = (time.perf_counter() - t) * 1000.0
+        t = time.perf_counter()
+        res_b = g.query_batch(bq)
+        torch.cuda.synchronize()
+        bat_ms = (time.perf_counter() - t) * 1000.0
+        for r in res_b:
+            r.free()
+        del buf
+        batch_leg = {"queries": len(bq), "batch_ms": round(bat_ms, 3), "one_at_a_time_ms": round(one_ms, 3),
+                     "speedup": round(one_ms / bat_ms, 3), "config": evq.batch_config()}
+        log(f"[bench] batch of {len(bq)} mixed queries: {bat_ms:.1f} ms vs one at a time {one_ms:.1f} ms")
 
     roof = None
     kernels = None
@@ -448,6 +479,7 @@ def main():
         "plain_ms_per_query": plain_ms,
         "speedup_vs_plain": (plain_ms / ms) if plain_ms else None,
         "build_ms": info["build_ms"],
+        "batch_leg": batch_leg,
         "query_stats": st,
         "roofline": roof,
         "cpu_baseline": cpu,

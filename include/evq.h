@@ -212,7 +212,7 @@ typedef struct {
     uint32_t lanes;      /* 1: shared bound solves, one query per lane; 2: one bound solve per query */
     uint32_t chunk;      /* edges per wave task of the shared bound solves: 4, 8 or 16 */
     uint32_t blocks;     /* workgroups of 256 threads per expansion launch, 64 .. 16384 */
-    uint32_t reserved;
+    uint32_t group;      /* queries per shared solve, 1 .. 64 (a larger set of one algorithm is split evenly) */
 } evq_batch_config;
 
 /*
@@ -253,9 +253,9 @@ evq_status evq_batch_config_set(const evq_batch_config* c);
 
 /*
  * Autotune: run evq_query_batch on the caller's n queries once to warm up,
- * then once under each candidate choice (shared solves with chunk 4/8/16 and
- * 256-thread workgroups 1024/2048/4096 per expansion, and one solve per
- * query), discard the results, and install the fastest for this process.
+ * then once under each candidate choice (shared solves of 16/32/64 queries
+ * with chunk 4/8/16, and one solve per query), discard the results, and
+ * install the fastest for this process.
  * chosen / best_ms (host, nullable) receive it and its wall time.
  * Synchronises `stream`.  Errors as evq_query_batch.
  */
@@ -299,7 +299,7 @@ typedef struct evq_server evq_server;
 
 typedef struct {
     uint32_t mode;           /* 0: continuous batching, 1: plain */
-    uint32_t max_batch;      /* queries per group, 1..64 (0: 64) */
+    uint32_t max_batch;      /* queries per group, 1..64 (0: 16) */
     uint32_t max_inflight;   /* admitted and not completed (0: 256) */
     uint32_t max_groups;     /* group bound solves running at once (0: 2) */
     uint64_t mem_budget;     /* device bytes, by estimate (0: a quarter of the free memory at creation) */

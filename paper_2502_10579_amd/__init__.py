@@ -68,7 +68,7 @@ class ResultC(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("lanes", ctypes.c_uint32), ("chunk", ctypes.c_uint32), ("blocks", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("group", ctypes.c_uint32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -323,7 +323,7 @@ class Graph:
         c = BatchConfig()
         ms = ctypes.c_double()
         _check(_lib.evq_batch_autotune(self._h, descs, len(qs), ctypes.byref(c), ctypes.byref(ms), _stream(stream)))
-        return {"lanes": c.lanes, "chunk": c.chunk, "blocks": c.blocks}, ms.value
+        return {"lanes": c.lanes, "chunk": c.chunk, "blocks": c.blocks, "group": c.group}, ms.value
 
 
 class Result:
@@ -417,12 +417,12 @@ class Server:
 def batch_config() -> dict:
     c = BatchConfig()
     _check(_lib.evq_batch_config_get(ctypes.byref(c)))
-    return {"lanes": c.lanes, "chunk": c.chunk, "blocks": c.blocks}
+    return {"lanes": c.lanes, "chunk": c.chunk, "blocks": c.blocks, "group": c.group}
 
 
-def set_batch_config(lanes=0, chunk=0, blocks=0):
+def set_batch_config(lanes=0, chunk=0, blocks=0, group=0):
     """Execution choices of query_batch (0 keeps the current value)."""
-    _check(_lib.evq_batch_config_set(ctypes.byref(BatchConfig(lanes, chunk, blocks, 0))))
+    _check(_lib.evq_batch_config_set(ctypes.byref(BatchConfig(lanes, chunk, blocks, group))))
 
 
 def to_u32(t) -> np.ndarray:

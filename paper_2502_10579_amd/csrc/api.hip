@@ -77,7 +77,7 @@ evq_status evq_build(uint32_t num_vertices, const evq_edge* base, uint64_t n_bas
         try {
             sp = std::shared_ptr<const evq::Graph>(g, evq::release_graph);
         } catch (...) {
-            evq::free_graph(g);
+            evq::free_graph(g, (hipStream_t)stream);
             throw;
         }
         evq_graph* h = new evq_graph();
@@ -114,6 +114,7 @@ evq_status evq_graph_export(const evq_graph* h, uint32_t* row_ptr, uint32_t* row
         auto gp = h->get();
         const evq::Graph& g = *gp;
         hipStream_t s = (hipStream_t)stream;
+        evq::UseGuard ug{g, s};
         if (row_ptr) EVQ_HIP(hipMemcpyAsync(row_ptr, g.row_ptr, ((uint64_t)g.V + 1) * 4, hipMemcpyDeviceToHost, s));
         if (row_split) EVQ_HIP(hipMemcpyAsync(row_split, g.row_split, (uint64_t)g.V * 4, hipMemcpyDeviceToHost, s));
         if (g.E) {
@@ -140,6 +141,7 @@ evq_status evq_query(const evq_graph* h, uint32_t algo, uint32_t source, uint32_
     try {
         evq::QueryOut qo;
         qo.want_stats = stats != nullptr;
+        evq::UseGuard ug{*gp, (hipStream_t)stream};
         evq::run_query(*gp, algo, source, W, d_values, nullptr, nullptr, false, qo, (hipStream_t)stream);
         if (stats) *stats = qo.st;
         return EVQ_OK;
@@ -158,6 +160,7 @@ evq_status evq_query_bounds(const evq_graph* h, uint32_t algo, uint32_t source, 
     if (rc != EVQ_OK) return rc;
     try {
         evq::QueryOut qo;
+        evq::UseGuard ug{*gp, (hipStream_t)stream};
         evq::run_query(*gp, algo, source, W, nullptr, d_rcap, d_rcup, true, qo, (hipStream_t)stream);
         return EVQ_OK;
     } catch (...) {
@@ -177,6 +180,7 @@ evq_status evq_query_plain(const evq_graph* h, uint32_t algo, uint32_t source, u
     try {
         evq::QueryOut qo;
         qo.want_stats = stats != nullptr;
+        evq::UseGuard ug{*gp, (hipStream_t)stream};
         evq::run_plain(*gp, algo, source, W, d_values, qo, (hipStream_t)stream);
         if (stats) *stats = qo.st;
         return EVQ_OK;
@@ -205,6 +209,7 @@ evq_status evq_query_batch(const evq_graph* h, const evq_query_desc* q, uint32_t
             bq[i].source = q[i].source;
         }
         std::vector<evq::Compact> c(n);
+        evq::UseGuard ug{*gp, (hipStream_t)stream};  // the stream waits for every worker stream
         evq::run_batch(*gp, bq.data(), n, c.data(), stats, (hipStream_t)stream);
         for (uint32_t i = 0; i < n; ++i) {
             evq_result& r = results[i];
@@ -263,6 +268,7 @@ evq_status evq_batch_config_get(evq_batch_config* c) {
         c->lanes = t.lanes;
         c->chunk = t.chunk;
         c->blocks = t.blocks;
+        c->group = t.group;
         return EVQ_OK;
     } catch (...) {
         return guard_exc();
@@ -277,6 +283,7 @@ evq_status evq_batch_config_set(const evq_batch_config* c) {
         if (c->lanes) t.lanes = c->lanes;
         if (c->chunk) t.chunk = c->chunk;
         if (c->blocks) t.blocks = c->blocks;
+        if (c->group) t.group = c->group;
         evq::set_batch_tuning(t);
         return EVQ_OK;
     } catch (...) {
@@ -290,12 +297,16 @@ evq_status evq_append(evq_graph* h, const evq_batch* b, void* stream) {
     try {
         std::lock_guard<std::mutex> lk(h->append_mu);
         auto old = h->get();
-        evq::Graph* g = evq::append_graph(*old, *b, (hipStream_t)stream);
+        evq::Graph* g = nullptr;
+        {
+            evq::UseGuard ug{*old, (hipStream_t)stream};
+            g = evq::append_graph(*old, *b, (hipStream_t)stream);
+        }
         std::shared_ptr<const evq::Graph> sp;
         try {
             sp = std::shared_ptr<const evq::Graph>(g, evq::release_graph);
         } catch (...) {
-            evq::free_graph(g);
+            evq::free_graph(g, (hipStream_t)stream);
             throw;
         }
         {
@@ -325,12 +336,14 @@ evq_status evq_batch_autotune(const evq_graph* h, const evq_query_desc* q, uint3
             bq[i].algo = q[i].algo;
             bq[i].source = q[i].source;
         }
+        evq::UseGuard ug{*gp, (hipStream_t)stream};
         const evq::BatchTuning t = evq::autotune_batch(*gp, bq.data(), n, (hipStream_t)stream, best_ms);
         if (chosen) {
             std::memset(chosen, 0, sizeof(*chosen));
             chosen->lanes = t.lanes;
             chosen->chunk = t.chunk;
             chosen->blocks = t.blocks;
+            chosen->group = t.group;
         }
         return EVQ_OK;
     } catch (...) {

@@ -15,6 +15,7 @@ struct BatchTuning {
     uint32_t lanes = 1;     // 1: shared bound solves; 2: one bound solve per query
     uint32_t chunk = 8;     // edges per wave task of the shared solves
     uint32_t blocks = 2048; // workgroups per expansion launch
+    uint32_t group = 64;    // queries per shared solve
 };
 
 struct BatchTimes {

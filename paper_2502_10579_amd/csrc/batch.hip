@@ -359,6 +359,7 @@ BatchTuning checked(BatchTuning t) {
     if (t.lanes != 1 && t.lanes != 2) fail(EVQ_EINVAL, "batch config: lanes must be 1 or 2");
     if (t.chunk != 4 && t.chunk != 8 && t.chunk != 16) fail(EVQ_EINVAL, "batch config: chunk must be 4, 8 or 16");
     if (t.blocks < 64 || t.blocks > 16384) fail(EVQ_EINVAL, "batch config: blocks must be in [64, 16384]");
+    if (t.group < 1 || t.group > 64) fail(EVQ_EINVAL, "batch config: group must be in [1, 64]");
     return t;
 }
 
@@ -371,6 +372,7 @@ BatchTuning batch_tuning() {
         t.lanes = env_u32("EVQ_BATCH_LANES", t.lanes);
         t.chunk = env_u32("EVQ_BATCH_CHUNK", t.chunk);
         t.blocks = env_u32("EVQ_BATCH_BLOCKS", t.blocks);
+        t.group = env_u32("EVQ_BATCH_GROUP", t.group);
         g_tune = checked(t);
         g_tune_init = true;
     }
@@ -510,8 +512,10 @@ void run_batch(const Graph& g, const BatchQuery* q, uint32_t n, Compact* out, ev
             std::vector<uint32_t> ids;
             for (uint32_t i = 0; i < n; ++i)
                 if (q[i].algo == a) ids.push_back(i);
-            for (size_t k = 0; k < ids.size(); k += 64)
-                groups.emplace_back(ids.begin() + k, ids.begin() + std::min(ids.size(), k + 64));
+            // equal groups of at most tu.group queries
+            const size_t ng = (ids.size() + tu.group - 1) / tu.group;
+            for (size_t k = 0; k < ng; ++k)
+                groups.emplace_back(ids.begin() + ids.size() * k / ng, ids.begin() + ids.size() * (k + 1) / ng);
         }
     }
     std::vector<BatchTimes> times(groups.size());
@@ -639,12 +643,13 @@ void run_batch(const Graph& g, const BatchQuery* q, uint32_t n, Compact* out, ev
 // chunk, blocks), after one warm-up run, and installs the fastest.
 BatchTuning autotune_batch(const Graph& g, const BatchQuery* q, uint32_t n, hipStream_t s, double* best_ms) {
     std::vector<BatchTuning> cand;
-    for (uint32_t chunk : {4u, 8u, 16u})
-        for (uint32_t blocks : {1024u, 2048u, 4096u}) {
+    for (uint32_t group : {16u, 32u, 64u})
+        for (uint32_t chunk : {4u, 8u, 16u}) {
             BatchTuning t;
             t.lanes = 1;
             t.chunk = chunk;
-            t.blocks = blocks;
+            t.blocks = 2048;
+            t.group = group;
             cand.push_back(t);
         }
     BatchTuning one;

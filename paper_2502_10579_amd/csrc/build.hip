@@ -327,11 +327,11 @@ void finish_build(Graph* g, KT* sorted, uint64_t N, KeyLayout L, uint64_t* mtmp,
     ar.release(pos);
     ar.release(sorted);
 
-    g->row_ptr = (uint32_t*)dev_alloc(((uint64_t)g->V + 1) * 4);
-    g->row_split = (uint32_t*)dev_alloc((uint64_t)g->V * 4);
-    g->col = (uint32_t*)dev_alloc(E * 4);
-    g->wgt = (uint32_t*)dev_alloc(E * 4);
-    g->mask = (uint64_t*)dev_alloc(E * 8 * MW);
+    g->row_ptr = (uint32_t*)stream_alloc(((uint64_t)g->V + 1) * 4, s);
+    g->row_split = (uint32_t*)stream_alloc((uint64_t)g->V * 4, s);
+    g->col = (uint32_t*)stream_alloc(E * 4, s);
+    g->wgt = (uint32_t*)stream_alloc(E * 4, s);
+    g->mask = (uint64_t*)stream_alloc(E * 8 * MW, s);
     g->bytes = ((uint64_t)g->V + 1) * 4 + (uint64_t)g->V * 4 + E * (8 + 8 * MW);
 
     EVQ_LAUNCH("build_row_ptr", k_row_ptr, grid_for(E + 1, 256), 256, s, c_src, E, g->V, g->row_ptr);
@@ -340,8 +340,8 @@ void finish_build(Graph* g, KT* sorted, uint64_t N, KeyLayout L, uint64_t* mtmp,
     EVQ_HIP(hipStreamSynchronize(s));
     const uint64_t n_full = mb.h[0];
     g->n_partial = E - n_full;
-    g->p_src = (uint32_t*)dev_alloc(g->n_partial * 4);
-    g->p_eid = (uint32_t*)dev_alloc(g->n_partial * 4);
+    g->p_src = (uint32_t*)stream_alloc(g->n_partial * 4, s);
+    g->p_eid = (uint32_t*)stream_alloc(g->n_partial * 4, s);
     g->bytes += g->n_partial * 8;
     if (E > 0)
         EVQ_LAUNCH("build_partition", k_partition<MW>, grid_for(E, 256), 256, s, c_src, c_dst, c_w, c_mask, c_full, fb,
@@ -473,15 +473,12 @@ void append_impl(const Graph& old, Graph* g, const uint32_t* d_ev, uint64_t n_de
 
 }  // namespace
 
-void free_graph(Graph* g) {
+void free_graph(Graph* g, hipStream_t s) {
     if (!g) return;
-    dev_free(g->row_ptr);
-    dev_free(g->row_split);
-    dev_free(g->col);
-    dev_free(g->wgt);
-    dev_free(g->mask);
-    dev_free(g->p_src);
-    dev_free(g->p_eid);
+    void* arrays[7] = {g->row_ptr, g->row_split, g->col, g->wgt, g->mask, g->p_src, g->p_eid};
+    for (void* p : arrays)
+        if (p) (void)hipFreeAsync(p, s);
+    for (hipEvent_t e : g->uses) (void)hipEventDestroy(e);
     delete g;
 }
 
@@ -547,15 +544,15 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
         if (N == 0) {
             g->E = 0;
             g->n_partial = 0;
-            g->row_ptr = (uint32_t*)dev_alloc(((uint64_t)V + 1) * 4);
-            g->row_split = (uint32_t*)dev_alloc((uint64_t)V * 4);
+            g->row_ptr = (uint32_t*)stream_alloc(((uint64_t)V + 1) * 4, s);
+            g->row_split = (uint32_t*)stream_alloc((uint64_t)V * 4, s);
             fill_u32(g->row_ptr, (uint64_t)V + 1, 0u, s);
             fill_u32(g->row_split, V, 0u, s);
-            g->col = (uint32_t*)dev_alloc(4);
-            g->wgt = (uint32_t*)dev_alloc(4);
-            g->mask = (uint64_t*)dev_alloc(16);
-            g->p_src = (uint32_t*)dev_alloc(4);
-            g->p_eid = (uint32_t*)dev_alloc(4);
+            g->col = (uint32_t*)stream_alloc(4, s);
+            g->wgt = (uint32_t*)stream_alloc(4, s);
+            g->mask = (uint64_t*)stream_alloc(16, s);
+            g->p_src = (uint32_t*)stream_alloc(4, s);
+            g->p_eid = (uint32_t*)stream_alloc(4, s);
             g->bytes = ((uint64_t)V + 1) * 8;
             EVQ_HIP(hipStreamSynchronize(s));
         } else if (L.total() <= 64) {
@@ -568,7 +565,7 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
         if (g->E >= 0xFFFFFFFEull) fail(EVQ_ERANGE, "more than 2^32 - 2 union edges");
     } catch (...) {
         (void)hipStreamSynchronize(s);
-        free_graph(g);
+        free_graph(g, s);
         throw;
     }
     EVQ_HIP(hipStreamSynchronize(s));
@@ -615,15 +612,15 @@ Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
         if (old.E + n_ev == 0) {
             g->E = 0;
             g->n_partial = 0;
-            g->row_ptr = (uint32_t*)dev_alloc(((uint64_t)V + 1) * 4);
-            g->row_split = (uint32_t*)dev_alloc((uint64_t)V * 4);
+            g->row_ptr = (uint32_t*)stream_alloc(((uint64_t)V + 1) * 4, s);
+            g->row_split = (uint32_t*)stream_alloc((uint64_t)V * 4, s);
             fill_u32(g->row_ptr, (uint64_t)V + 1, 0u, s);
             fill_u32(g->row_split, V, 0u, s);
-            g->col = (uint32_t*)dev_alloc(4);
-            g->wgt = (uint32_t*)dev_alloc(4);
-            g->mask = (uint64_t*)dev_alloc(16);
-            g->p_src = (uint32_t*)dev_alloc(4);
-            g->p_eid = (uint32_t*)dev_alloc(4);
+            g->col = (uint32_t*)stream_alloc(4, s);
+            g->wgt = (uint32_t*)stream_alloc(4, s);
+            g->mask = (uint64_t*)stream_alloc(16, s);
+            g->p_src = (uint32_t*)stream_alloc(4, s);
+            g->p_eid = (uint32_t*)stream_alloc(4, s);
             g->bytes = ((uint64_t)V + 1) * 8;
         } else if (L.total() <= 64) {
             if (g->MW == 1) append_impl<uint64_t, 1>(old, g, d_ev, b.n_del, n_ev, L, ib, s, ar);
@@ -637,7 +634,7 @@ Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
         if (g->E >= 0xFFFFFFFEull) fail(EVQ_ERANGE, "more than 2^32 - 2 union edges");
     } catch (...) {
         (void)hipStreamSynchronize(s);
-        free_graph(g);
+        free_graph(g, s);
         throw;
     }
     EVQ_HIP(hipStreamSynchronize(s));

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -48,6 +49,23 @@ struct Graph {
     int device = 0;
     uint64_t bytes = 0;
     double build_ms = 0.0;
+    // Events recorded on the streams of calls that read this version; its
+    // arrays are released (stream-ordered, after all of them) when it retires.
+    mutable std::mutex use_mu;
+    mutable std::vector<hipEvent_t> uses;
+};
+
+// Records that work reading g was queued on s (call after the last launch).
+void note_use(const Graph& g, hipStream_t s);
+struct UseGuard {
+    const Graph& g;
+    hipStream_t s;
+    ~UseGuard() {
+        try {
+            note_use(g, s);
+        } catch (...) {
+        }
+    }
 };
 
 // ------------------------------------------------------------------ memory
@@ -98,8 +116,6 @@ class Workspace {
     uint64_t cap_[kSlots] = {};
 };
 
-void* dev_alloc(uint64_t bytes);  // hipMalloc; throws EVQ_ENOMEM
-void dev_free(void* p);
 void* stream_alloc(uint64_t bytes, hipStream_t s);  // hipMallocAsync from the device pool; throws EVQ_ENOMEM
 void stream_free(void* p, hipStream_t s);          // hipFreeAsync (NULL allowed)
 void init_mempool(int device);
@@ -151,7 +167,11 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
 // The next version of a graph: snapshot first+K (old newest with batch b
 // applied) replaces snapshot `first` in its mask bit.  `old` is not changed.
 Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s);
-void free_graph(Graph* g);
+// Releases g's device arrays, ordered on s, and deletes g.
+void free_graph(Graph* g, hipStream_t s);
+// A retired version: its arrays are released on a private stream once every
+// recorded use has completed; no device-wide synchronisation.
+void retire_graph(Graph* g);
 
 // A window of L consecutive snapshots; lane i is snapshot (first of the
 // window) + i, held in mask bit (b + i) mod K.

@@ -1,7 +1,7 @@
 // The graph handle behind the C ABI.  It holds the current version of the
 // versioned graph; every call takes a reference to the version it starts on,
-// so an append never waits for running queries, and a version is released
-// (after the device drains) once its last user has returned.
+// so an append never waits for running queries; a version is released once
+// its last user has returned, ordered after the work its users queued.
 #pragma once
 
 #include <memory>
@@ -11,10 +11,7 @@
 
 namespace evq {
 
-inline void release_graph(Graph* g) {
-    (void)hipDeviceSynchronize();  // no queued kernel may still read it
-    free_graph(g);
-}
+inline void release_graph(Graph* g) { retire_graph(g); }
 
 }  // namespace evq
 

@@ -23,18 +23,65 @@ void hip_check(hipError_t e, const char* what) {
 
 // ------------------------------------------------------------------ memory
 
-void* dev_alloc(uint64_t bytes) {
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(EVQ_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+void note_use(const Graph& g, hipStream_t s) {
+    hipEvent_t e = nullptr;
+    EVQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipError_t r = hipEventRecord(e, s);
+    if (r != hipSuccess) {
+        (void)hipEventDestroy(e);
+        hip_check(r, "hipEventRecord");
     }
-    return p;
+    std::lock_guard<std::mutex> lk(g.use_mu);
+    if (g.uses.size() >= 64) {  // drop the uses that have completed
+        std::vector<hipEvent_t> keep;
+        for (hipEvent_t x : g.uses) {
+            if (hipEventQuery(x) == hipSuccess) (void)hipEventDestroy(x);
+            else keep.push_back(x);
+        }
+        g.uses.swap(keep);
+    }
+    g.uses.push_back(e);
 }
 
-void dev_free(void* p) {
-    if (p) (void)hipFree(p);
+void retire_graph(Graph* g) {
+    static std::mutex mu;
+    static std::vector<std::pair<int, hipStream_t>> reapers;
+    hipStream_t r = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& kv : reapers)
+            if (kv.first == g->device) r = kv.second;
+        if (!r) {
+            int prev = 0;
+            (void)hipGetDevice(&prev);
+            (void)hipSetDevice(g->device);
+            if (hipStreamCreateWithFlags(&r, hipStreamNonBlocking) != hipSuccess) r = nullptr;
+            (void)hipSetDevice(prev);
+            if (r) reapers.push_back({g->device, r});
+        }
+    }
+    std::vector<hipEvent_t> uses;
+    {
+        std::lock_guard<std::mutex> lk(g->use_mu);
+        uses.swap(g->uses);
+    }
+    if (!r) {  // no stream for ordered release: wait for everything instead
+        (void)hipDeviceSynchronize();
+        for (hipEvent_t e : uses) (void)hipEventDestroy(e);
+        try {
+            free_graph(g, nullptr);
+        } catch (...) {
+        }
+        return;
+    }
+    for (hipEvent_t e : uses) {
+        (void)hipStreamWaitEvent(r, e, 0);
+        (void)hipEventDestroy(e);
+    }
+    try {
+        free_graph(g, r);
+    } catch (...) {
+    }
 }
 
 void* stream_alloc(uint64_t bytes, hipStream_t s) {
@@ -76,17 +123,19 @@ Workspace& Workspace::get(hipStream_t s) {
     return *all.back().second;
 }
 
+// Buffers come from the device's stream-ordered pool on the workspace's own
+// stream (every use is on that stream), so growing one needs no
+// synchronisation.
 void* Workspace::raw(Slot slot, uint64_t bytes) {
     if (bytes == 0) bytes = 16;
     if (cap_[slot] >= bytes) return p_[slot];
     if (p_[slot]) {
-        EVQ_HIP(hipStreamSynchronize(s_));
-        dev_free(p_[slot]);
+        stream_free(p_[slot], s_);
         p_[slot] = nullptr;
         cap_[slot] = 0;
     }
     const uint64_t want = ((bytes + bytes / 4) + 4095) & ~uint64_t(4095);
-    p_[slot] = dev_alloc(want);
+    p_[slot] = stream_alloc(want, s_);
     cap_[slot] = want;
     if (slot == kFlags) fresh_flags = true;
     return p_[slot];

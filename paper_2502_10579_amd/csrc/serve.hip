@@ -148,6 +148,7 @@ void launch_group(evq_server* sv, std::shared_ptr<const Graph> gp, std::vector<S
         SQuery* q = grp[0];
         pool.submit([sv, gp, q](hipStream_t ws) {
             const Graph& g = *gp;
+            UseGuard ug{g, ws};
             const Window W = window_of(g, q);
             bool ok = true;
             try {
@@ -182,6 +183,7 @@ void launch_group(evq_server* sv, std::shared_ptr<const Graph> gp, std::vector<S
     }
     pool.submit([sv, gp, grp](hipStream_t ws) {
         const Graph& g = *gp;
+        UseGuard ug{g, ws};
         Pool& pool = Pool::get(sv->device);
         const uint32_t nq = (uint32_t)grp.size();
         const BatchTuning tu = batch_tuning();
@@ -234,6 +236,7 @@ void launch_group(evq_server* sv, std::shared_ptr<const Graph> gp, std::vector<S
         for (SQuery* q : grp) {
             pool.submit([sv, gp, q, evp](hipStream_t ts) {
                 const Graph& g = *gp;
+                UseGuard ug{g, ts};
                 try {
                     EVQ_HIP(hipStreamWaitEvent(ts, (hipEvent_t)evp.get(), 0));
                     run_tail_compact(g, q->algo, q->source, window_of(g, q), q->rcup, q->c, q->qo, ts);
@@ -272,6 +275,7 @@ void dispatch_loop(evq_server* sv) {
             lk.unlock();
             Pool::get(sv->device).submit([sv, gp, q](hipStream_t ws) {
                 const Graph& g = *gp;
+            UseGuard ug{g, ws};
                 try {
                     q->c.rcap = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
                     run_query_compact(g, q->algo, q->source, window_of(g, q), q->c, q->qo, ws);
@@ -341,7 +345,7 @@ evq_status evq_server_create(evq_graph* h, const evq_server_config* c, evq_serve
         evq_server_config cfg{};
         if (c) cfg = *c;
         if (cfg.mode > 1) return sbad(EVQ_EINVAL, "mode must be 0 (continuous batching) or 1 (plain)");
-        if (cfg.max_batch == 0) cfg.max_batch = 64;
+        if (cfg.max_batch == 0) cfg.max_batch = 16;  // measured best per-query cost at scale 24
         if (cfg.max_batch > 64) return sbad(EVQ_EINVAL, "max_batch must be <= 64");
         if (cfg.max_inflight == 0) cfg.max_inflight = 256;
         if (cfg.max_groups == 0) cfg.max_groups = 2;

@@ -25,14 +25,15 @@ def evq():
         pytest.skip("no GPU")
     import paper_2502_10579_amd as m
     yield m
-    m.set_batch_config(lanes=1, chunk=8, blocks=2048)
+    m.set_batch_config(lanes=1, chunk=8, blocks=2048, group=64)
 
 
-def _check_batch(evq, inst, queries, lanes, chunk=8, blocks=2048, rep=None, vs_single=True, vs_oracle=True):
+def _check_batch(evq, inst, queries, lanes, chunk=8, blocks=2048, group=64, rep=None, vs_single=True,
+                 vs_oracle=True):
     import torch
     V = inst.num_vertices
-    evq.set_batch_config(lanes=lanes, chunk=chunk, blocks=blocks)
-    print(f"batch: {len(queries)} queries, lanes={lanes} chunk={chunk} blocks={blocks}", flush=True)
+    evq.set_batch_config(lanes=lanes, chunk=chunk, blocks=blocks, group=group)
+    print(f"batch: {len(queries)} queries, lanes={lanes} chunk={chunk} blocks={blocks} group={group}", flush=True)
     rep = rep if rep is not None else oracle.replay(inst)
     with evq.Graph.from_instance(inst) as g:
         res = g.query_batch(queries)
@@ -61,22 +62,22 @@ def test_batch_small_mixed(evq, lanes, seed):
     _check_batch(evq, inst, qs, lanes)
 
 
-@pytest.mark.parametrize("chunk", [4, 8, 16])
-def test_batch_chunks_and_grids(evq, chunk):
+@pytest.mark.parametrize("chunk,group", [(4, 64), (8, 16), (16, 5), (8, 1)])
+def test_batch_chunks_grids_groups(evq, chunk, group):
     inst = synth.config_instance("small", seed=4)
     qs = synth.batch_queries(inst, 40, seed=9, start_max=7, len_min=1, len_max=8)
-    _check_batch(evq, inst, qs, 1, chunk=chunk, blocks=64 if chunk == 4 else 2048)
+    _check_batch(evq, inst, qs, 1, chunk=chunk, blocks=64 if chunk == 4 else 2048, group=group)
 
 
 def test_batch_more_than_64_per_algorithm(evq):
-    # 150 SSSP queries: groups of 64, 64 and 22 lanes; 10 BFS for a second algorithm
+    # 150 SSSP queries: three groups of 50 (64 lanes each); 10 BFS for a second algorithm
     inst = synth.config_instance("small", seed=5)
     qs = synth.batch_queries(inst, 150, seed=5, start_max=7, len_min=1, len_max=8, algos=(0,))
     qs += synth.batch_queries(inst, 10, seed=6, start_max=7, len_min=1, len_max=8, algos=(1,))
     rep = oracle.replay(inst)
     _check_batch(evq, inst, qs, 1, rep=rep, vs_oracle=False)
-    # oracle on a sample spanning all three groups
-    _check_batch(evq, inst, [qs[i] for i in (0, 63, 64, 127, 128, 149, 150, 159)], 1, rep=rep)
+    # oracle on a sample spanning the groups
+    _check_batch(evq, inst, [qs[i] for i in (0, 49, 50, 99, 100, 149, 150, 159)], 1, rep=rep)
 
 
 @pytest.mark.parametrize("lanes", [1, 2])
@@ -118,7 +119,7 @@ def test_batch_result_free_and_reuse(evq):
     inst = synth.config_instance("small", seed=7)
     qs = synth.batch_queries(inst, 12, seed=7, start_max=7, len_min=1, len_max=8)
     rep = oracle.replay(inst)
-    evq.set_batch_config(lanes=1, chunk=8, blocks=2048)
+    evq.set_batch_config(lanes=1, chunk=8, blocks=2048, group=64)
     with evq.Graph.from_instance(inst) as g:
         r1 = g.query_batch(qs)
         r2 = g.query_batch(qs[::-1])
@@ -148,4 +149,4 @@ def test_batch_autotune_installs_a_valid_choice(evq):
             want = oracle.window_values(inst, a, s, b, L, replayed=rep)
             assert_equal_values(evq.to_u32(r.expand()).reshape(inst.num_vertices, L), want, str((a, s, b, L)))
             r.free()
-    evq.set_batch_config(lanes=1, chunk=8, blocks=2048)
+    evq.set_batch_config(lanes=1, chunk=8, blocks=2048, group=64)

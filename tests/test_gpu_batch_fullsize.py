@@ -45,7 +45,7 @@ def batched(evq):
 def batch_results(evq, batched):
     import torch
     inst, qs, g = batched
-    evq.set_batch_config(lanes=1, chunk=8, blocks=2048)
+    evq.set_batch_config(lanes=1, chunk=8, blocks=2048, group=64)
     print(f"batched: {len(qs)} queries on V={inst.num_vertices}", flush=True)
     res, st = g.query_batch(qs, stats=True)
     torch.cuda.synchronize()

@@ -1,0 +1,123 @@
+"""Concurrent use of one graph through the C ABI.
+
+* Single queries from several host threads, each on its own stream, equal
+  the oracle (frontier loops on different threads and streams share nothing;
+  iterations issued past the end of one loop never end the next one early).
+* Appends while other threads run single and batched queries: every result
+  equals the oracle for the window it was answered on (a query keeps the
+  graph version it started on).
+Values are uint32: tolerance zero.
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_equal_values
+
+pytestmark = pytest.mark.gpu
+
+ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP]
+
+
+@pytest.fixture(scope="module")
+def evq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2502_10579_amd as m
+    return m
+
+
+def test_threads_on_streams(evq):
+    import torch
+    inst = synth.config_instance("small", seed=2)
+    qs = synth.batch_queries(inst, 24, seed=2, start_max=7, len_min=1, len_max=8)
+    rep = oracle.replay(inst)
+    V = inst.num_vertices
+    want = [oracle.window_values(inst, a, s, b, L, replayed=rep) for (a, s, b, L) in qs]
+    bad = []
+    with evq.Graph.from_instance(inst) as g:
+        def worker(tid):
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for _ in range(5):
+                    for k in range(tid, len(qs), 4):
+                        a, s, b, L = qs[k]
+                        out = g.query(a, s, b, L, stream=st.cuda_stream)
+                        st.synchronize()
+                        if not np.array_equal(evq.to_u32(out).reshape(V, L), want[k]):
+                            bad.append((tid, k))
+        th = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+    assert not bad, f"wrong results on (thread, query): {bad[:5]}"
+
+
+def test_appends_while_querying(evq):
+    import torch
+    K, A = 16, 12
+    inst = synth.random_instance(120, 1500, K + A, 8, 8, 9, 61)
+    rep = oracle.replay(inst)  # global snapshot ids
+    V = inst.num_vertices
+    src = synth.pick_sources(inst, 8, seed=6)
+    results = []  # (algo, source, b, L, host values)
+    errors = []
+    with evq.Graph.from_instance(synth.Instance(V, inst.base, inst.dels[:K], inst.adds[:K])) as g:
+        done = threading.Event()
+
+        def single(tid):
+            st = torch.cuda.Stream()
+            i = 0
+            with torch.cuda.stream(st):
+                while not done.is_set() or i < 3:
+                    a = ALGOS[(tid + i) % 4]
+                    s = src[(tid + i) % len(src)]
+                    L = 1 + (i * 5 + tid) % K
+                    try:
+                        first = g.first
+                        b = first + K - L
+                        out = g.query(a, s, b, L, stream=st.cuda_stream)
+                        st.synchronize()
+                        results.append((a, s, b, L, evq.to_u32(out).reshape(V, L)))
+                    except evq.EvqError as e:
+                        # an append between reading first and querying retires the oldest snapshot
+                        if e.status != evq.EVQ_ERANGE:
+                            errors.append(str(e))
+                    i += 1
+
+        def batched():
+            st = torch.cuda.Stream()
+            i = 0
+            with torch.cuda.stream(st):
+                while not done.is_set() or i < 2:
+                    first = g.first
+                    qs = [(ALGOS[k % 4], src[k], first + K - 1 - k, 1 + k) for k in range(6)]
+                    try:
+                        res = g.query_batch(qs, stream=st.cuda_stream)
+                        st.synchronize()
+                        for r, (a, s, b, L) in zip(res, qs):
+                            results.append((a, s, b, L, evq.to_u32(r.expand(stream=st.cuda_stream)).reshape(V, L)))
+                            r.free(stream=st.cuda_stream)
+                    except evq.EvqError as e:
+                        if e.status != evq.EVQ_ERANGE:
+                            errors.append(str(e))
+                    i += 1
+
+        th = [threading.Thread(target=single, args=(t,)) for t in range(2)] + [threading.Thread(target=batched)]
+        for t in th:
+            t.start()
+        for a in range(A):
+            g.append(inst.dels[K + a], inst.adds[K + a])
+        done.set()
+        for t in th:
+            t.join()
+        torch.cuda.synchronize()
+    assert not errors, errors[:3]
+    assert len(results) > 20
+    for (a, s, b, L, got) in results:
+        assert_equal_values(got, oracle.window_values(inst, a, s, b, L, replayed=rep), f"{(a, s, b, L)}")

@@ -34,7 +34,7 @@ def evq():
         pytest.skip("no GPU")
     import paper_2502_10579_amd as m
     yield m
-    m.set_batch_config(lanes=1, chunk=8, blocks=2048)
+    m.set_batch_config(lanes=1, chunk=8, blocks=2048, group=64)
 
 
 def head(inst, K):
