@@ -358,6 +358,7 @@ def main():
     log(f"[bench] stats: {json.dumps({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()})}")
 
     plain_ms = None
+    seq_ms = None
     if not args.no_plain:
         outp = torch.empty_like(out)
         g.query_plain(algo, source, b, L, out=outp)
@@ -370,6 +371,15 @@ def main():
         plain_ms = (time.perf_counter() - t) * 1000.0 / n_plain
         same = bool(torch.equal(out, outp))
         log(f"[bench] plain concurrent evaluation: {plain_ms:.3f} ms/query, identical={same}")
+        g.query_sequential(algo, source, b, L, out=outp)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n_plain):
+            g.query_sequential(algo, source, b, L, out=outp)
+        torch.cuda.synchronize()
+        seq_ms = (time.perf_counter() - t) * 1000.0 / n_plain
+        same_seq = bool(torch.equal(out, outp))
+        log(f"[bench] sequential per-snapshot evaluation: {seq_ms:.3f} ms/query, identical={same_seq}")
 
     # batching leg on the same graph: 64 mixed queries of the batched recipe (algorithm uniform, random
     # source, start in [0, K - 25], length in [25, K] clamped), one call against one at a time
@@ -400,6 +410,7 @@ def main():
         log(f"[bench] batch of {len(bq)} mixed queries: {bat_ms:.1f} ms vs one at a time {one_ms:.1f} ms")
 
     roof = None
+    relax_roof = None
     kernels = None
     if not args.no_roofline:
         evq.timing_reset()
@@ -432,6 +443,9 @@ def main():
         if "relax" in kernels and relax_b:
             rl, rt = kernels["relax"]
             roof_relax = relax_b * reps / (rt / 1000.0) / 1e9
+            relax_roof = {"kernel": "relax", "achieved": round(roof_relax, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": round(roof_relax / PEAK_HBM_GBS, 4), "launches_per_query": rl // reps,
+                          "avg_launch_us": round(rt * 1000.0 / rl, 3), "algorithmic_bytes_per_query": int(relax_b)}
             log(f"[bench] relaxer: {roof_relax:.1f} GB/s algorithmic over {rl // reps} launches/query")
 
     cpu = None
@@ -445,6 +459,10 @@ def main():
         t = time.perf_counter()
         want = oracle.query(inst.num_vertices, trip, bits, algo, source, sample, nthreads)
         cpu_s = time.perf_counter() - t
+        # per-core rate: two snapshots on one thread
+        t = time.perf_counter()
+        oracle.query(inst.num_vertices, trip, bits, algo, source, sample[:2], 1)
+        one_s = time.perf_counter() - t
         got = evq.to_u32(out).reshape(inst.num_vertices, L)[:, :len(sample)]
         ok = bool(np.array_equal(got, want))
         cpu = {"value": float(counts[sample].sum() / cpu_s), "unit": "snapshot-edges/s", "cores": nthreads,
@@ -452,7 +470,9 @@ def main():
                "sample": f"snapshots {sample[0]}..{sample[-1]} of the window ({len(sample)} of {L}), per-snapshot "
                          f"materialisation + Dijkstra, {cpu_s:.2f}s; replay of the batches ({replay_s:.1f}s) not "
                          f"included",
-               "matches_gpu": ok}
+               "matches_gpu": ok,
+               "one_core": {"value": float(counts[sample[:2]].sum() / one_s), "unit": "snapshot-edges/s",
+                            "sample": f"snapshots {sample[0]}..{sample[1]} on 1 thread, {one_s:.2f}s"}}
         log(f"[bench] oracle sample: {cpu_s:.2f}s for {len(sample)} snapshots on {nthreads} threads, "
             f"matches GPU: {ok}")
 
@@ -478,10 +498,14 @@ def main():
         "ms_per_query": ms,
         "plain_ms_per_query": plain_ms,
         "speedup_vs_plain": (plain_ms / ms) if plain_ms else None,
+        "sequential_ms_per_query": seq_ms,
+        "speedup_vs_sequential": (seq_ms / ms) if seq_ms else None,
         "build_ms": info["build_ms"],
         "batch_leg": batch_leg,
         "query_stats": st,
+        "executed_relaxations_per_s": (st["edges_cap"] + st["edges_cup"] + st["lane_relaxations"]) / (ms / 1000.0),
         "roofline": roof,
+        "relax_roofline": relax_roof,
         "cpu_baseline": cpu,
     }
     if kernels:

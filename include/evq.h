@@ -176,6 +176,16 @@ evq_status evq_query_plain(const evq_graph* g, uint32_t algo, uint32_t source, u
                            uint32_t win_len, uint32_t* d_values, evq_query_stats* stats, void* stream);
 
 /*
+ * Ablation: the same bounds and reduced subgraph as evq_query, but the
+ * window's snapshots are relaxed one after another (Algorithm 1's
+ * per-snapshot evaluation of the reduced subgraph), each as its own
+ * one-lane relaxation, instead of concurrently (Algorithm 2).  Same
+ * arguments, output layout and errors as evq_query.
+ */
+evq_status evq_query_sequential(const evq_graph* g, uint32_t algo, uint32_t source, uint32_t win_begin,
+                                uint32_t win_len, uint32_t* d_values, evq_query_stats* stats, void* stream);
+
+/*
  * Batched queries (a systems layer over Algorithm 1 and Algorithm 2; the
  * paper answers one query at a time).  Queries of one algorithm share their
  * bound solves: up to 64 of them are solved together, one query per lane of

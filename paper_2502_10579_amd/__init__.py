@@ -96,7 +96,7 @@ _lib.evq_graph_info_get.restype = ctypes.c_int32
 _lib.evq_graph_info_get.argtypes = [_P, ctypes.POINTER(GraphInfo)]
 _lib.evq_graph_export.restype = ctypes.c_int32
 _lib.evq_graph_export.argtypes = [_P, _P, _P, _P, _P, _P, _P]
-for _name in ("evq_query", "evq_query_plain"):
+for _name in ("evq_query", "evq_query_plain", "evq_query_sequential"):
     getattr(_lib, _name).restype = ctypes.c_int32
     getattr(_lib, _name).argtypes = [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _P,
                                      ctypes.POINTER(QueryStats), _P]
@@ -142,7 +142,7 @@ _lib.evq_timing_report.restype = ctypes.c_int
 _lib.evq_timing_report.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int]
 
 EXPORTED = ["evq_build", "evq_graph_info_get", "evq_graph_export", "evq_query", "evq_query_bounds",
-            "evq_query_plain", "evq_query_batch", "evq_result_expand", "evq_result_free",
+            "evq_query_plain", "evq_query_sequential", "evq_query_batch", "evq_result_expand", "evq_result_free",
             "evq_batch_config_get", "evq_batch_config_set", "evq_batch_autotune", "evq_append", "evq_server_create",
             "evq_server_submit", "evq_server_poll", "evq_server_pending", "evq_server_destroy", "evq_free", "evq_last_error", "evq_timing_enable",
             "evq_timing_reset", "evq_timing_report"]
@@ -286,6 +286,16 @@ class Graph:
         st = QueryStats() if stats else None
         _check(_lib.evq_query_plain(self._h, algo, source, win_begin, L, _ptr(out),
                                     ctypes.byref(st) if st is not None else None, _stream(stream)))
+        return (out, st.as_dict()) if stats else out
+
+    def query_sequential(self, algo, source, win_begin=None, win_len=None, out=None, stats=False, stream=None):
+        """Same output as query(), relaxing the window's snapshots one after another (evq_query_sequential)."""
+        algo = ALGOS.get(algo, algo)
+        win_begin, L = self._window(win_begin, win_len)
+        out = self._alloc(L, out)
+        st = QueryStats() if stats else None
+        _check(_lib.evq_query_sequential(self._h, algo, source, win_begin, L, _ptr(out),
+                                         ctypes.byref(st) if st is not None else None, _stream(stream)))
         return (out, st.as_dict()) if stats else out
 
     def query_bounds(self, algo, source, win_begin=None, win_len=None, stream=None):

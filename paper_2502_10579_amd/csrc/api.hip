@@ -189,6 +189,27 @@ evq_status evq_query_plain(const evq_graph* h, uint32_t algo, uint32_t source, u
     }
 }
 
+evq_status evq_query_sequential(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t win_begin,
+                                uint32_t win_len, uint32_t* d_values, evq_query_stats* stats, void* stream) {
+    g_last_error.clear();
+    if (!h) return bad(EVQ_EINVAL, "graph handle is NULL");
+    auto gp = h->get();
+    evq::Window W;
+    evq_status rc = make_window(*gp, algo, source, win_begin, win_len, W);
+    if (rc != EVQ_OK) return rc;
+    if (!d_values) return bad(EVQ_EINVAL, "d_values is NULL");
+    try {
+        evq::QueryOut qo;
+        qo.want_stats = stats != nullptr;
+        evq::UseGuard ug{*gp, (hipStream_t)stream};
+        evq::run_sequential(*gp, algo, source, W, d_values, qo, (hipStream_t)stream);
+        if (stats) *stats = qo.st;
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
 evq_status evq_query_batch(const evq_graph* h, const evq_query_desc* q, uint32_t n, evq_result* results,
                            evq_query_stats* stats, void* stream) {
     g_last_error.clear();

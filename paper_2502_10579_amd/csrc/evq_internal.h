@@ -190,6 +190,8 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
                uint32_t* d_rcap_out, uint32_t* d_rcup_out, bool bounds_only, QueryOut& qo, hipStream_t s);
 void run_plain(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values, QueryOut& qo,
                hipStream_t s);
+void run_sequential(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values,
+                    QueryOut& qo, hipStream_t s);
 
 // Compact result of one query: rcap (V values, allocated by the caller) and,
 // after the tail, the unstable vertices and their relaxed rows in one

@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
                                                        const uint64_t* __restrict__ mask,
                                                        const uint32_t* __restrict__ cid_of,
                                                        const uint32_t* __restrict__ rcap, uint32_t b, uint32_t L,
-                                                       uint32_t K) {
+                                                       uint32_t K, uint32_t pb, uint32_t pL) {
     using T = Lanes<LG>;
     const uint32_t lane = lane_id();
     const int g = LG >= 64 ? 0 : (int)lane / LG;
@@ -360,8 +360,15 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
             cv = cid_of[col[e]];
             act = cv != kNone;
             if (act) {
+                // seeded lanes: the relaxed window (b, L); the edge must be
+                // partial in the bound window (pb, pL), which contains it
+                uint64_t pl[2];
+                edge_lanes<MW, 2>(mask, e, false, pb, pL, K, pl);
                 edge_lanes<MW, T::NLW>(mask, e, false, b, L, K, lanes);
-                act = lanes_partial<T::NLW>(lanes, L);
+                bool any = false;
+#pragma unroll
+                for (int j = 0; j < T::NLW; ++j) any |= lanes[j] != 0;
+                act = any && lanes_partial<2>(pl, pL);
                 if (act) cand = Alg<A>::extend(rcap[p_src[q]], wgt[e]);
             }
         }
@@ -491,6 +498,10 @@ __global__ void k_xinit_plain(const uint32_t* __restrict__ ulist, uint32_t nU, u
         X[k] = ulist[k / LG] == source ? at_source : unreached;
 }
 
+__global__ void k_init_frontier_stats(unsigned long long* st) {
+    if (threadIdx.x >= 1 && threadIdx.x < 4) st[threadIdx.x] = 0ull;
+}
+
 __global__ void k_mark_source(uint8_t* flags, const uint32_t* __restrict__ cid_of, uint32_t source) {
     if (threadIdx.x == 0) flags[cid_of[source]] = 1;
 }
@@ -570,6 +581,38 @@ __global__ void k_scatter_rows1(const uint32_t* __restrict__ ulist, uint32_t nU,
     }
 }
 
+// Column of one snapshot: col[v] = R_cap[v] for stable v, else its relaxed value.
+__global__ void k_column(uint32_t V, const uint32_t* __restrict__ cid_of, const uint32_t* __restrict__ rcap,
+                         const uint32_t* __restrict__ X, uint32_t* __restrict__ col) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = cid_of ? cid_of[v] : kNone;
+        col[v] = c == kNone ? rcap[v] : X[c];
+    }
+}
+
+// T[i][v] (L columns of V values) -> out[v * L + i], through a 64 x 64 LDS tile.
+__global__ void __launch_bounds__(256) k_columns_to_rows(const uint32_t* __restrict__ T, uint32_t L, uint32_t V,
+                                                         uint32_t* __restrict__ out) {
+    __shared__ uint32_t tile[64][65];
+    const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const uint64_t vt = (V + 63) / 64, it = (L + 63) / 64;
+    for (uint64_t t = blockIdx.x; t < vt * it; t += gridDim.x) {
+        const uint64_t v0 = (t % vt) * 64, i0 = (t / vt) * 64;
+#pragma unroll 4
+        for (uint32_t k = ty; k < 64; k += 4) {  // rows i0 + k of T, columns v0 + tx
+            const uint64_t i = i0 + k, v = v0 + tx;
+            tile[k][tx] = (i < L && v < V) ? T[i * V + v] : 0u;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (uint32_t k = ty; k < 64; k += 4) {  // out rows v0 + k, columns i0 + tx
+            const uint64_t v = v0 + k, i = i0 + tx;
+            if (v < V && i < L) out[v * L + i] = tile[tx][k];
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ host side
 
 }  // namespace
@@ -614,9 +657,14 @@ struct Reduced {
     uint32_t* cid_of = nullptr;
     uint32_t* ulist = nullptr;
     uint32_t* cuo = nullptr;
+    uint32_t* rv = nullptr;   // U rows: vertex, compact id, start in the record buffer
+    uint32_t* rc = nullptr;
+    uint32_t* ruo = nullptr;
     uint32_t* kc = nullptr;
     void* recs = nullptr;
 };
+
+void reduce_edges(const Graph& g, Reduced& r, const Window& W, uint32_t NLW, Workspace& ws, hipStream_t s);
 
 // Builds U's compact ids and the reduced subgraph.  all_vertices: U = V.
 // One host read-back (|U|, rows, edges) sizes the subgraph buffer.
@@ -627,9 +675,9 @@ Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup,
     r.cid_of = ws.buf<uint32_t>(Workspace::kCidOf, V);
     r.ulist = ws.buf<uint32_t>(Workspace::kUlist, V);
     r.cuo = ws.buf<uint32_t>(Workspace::kCuo, V);
-    uint32_t* rv = ws.buf<uint32_t>(Workspace::kRv, V);
-    uint32_t* rc = ws.buf<uint32_t>(Workspace::kRc, V);
-    uint32_t* ruo = ws.buf<uint32_t>(Workspace::kRuo, V);
+    uint32_t* rv = r.rv = ws.buf<uint32_t>(Workspace::kRv, V);
+    uint32_t* rc = r.rc = ws.buf<uint32_t>(Workspace::kRc, V);
+    uint32_t* ruo = r.ruo = ws.buf<uint32_t>(Workspace::kRuo, V);
     UCounters* uc = reinterpret_cast<UCounters*>(f.aux);
     fill_u32(reinterpret_cast<uint32_t*>(uc), sizeof(UCounters) / 4, 0u, s);
     EVQ_LAUNCH("compact_unstable", k_unstable, grid_for(V, kUPerBlock, 65535), kUBlock, s,
@@ -641,6 +689,13 @@ Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup,
     r.nR = (uint32_t)(hc[1] >> 32);
     r.TU = (uint32_t)hc[1];
     if (r.nU == 0) return r;
+    reduce_edges(g, r, W, NLW, ws, s);
+    return r;
+}
+
+// The reduced subgraph's records for window W over the unstable set of r
+// (rebuilt in place: kc and the records).
+void reduce_edges(const Graph& g, Reduced& r, const Window& W, uint32_t NLW, Workspace& ws, hipStream_t s) {
     r.kc = ws.buf<uint32_t>(Workspace::kKc, r.nU);
     fill_u32(r.kc, r.nU, 0u, s);
     r.recs = ws.raw(Workspace::kRecs, (r.TU + 1) * (NLW == 1 ? sizeof(Rec<1>) : sizeof(Rec<2>)));
@@ -651,9 +706,9 @@ Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup,
         a.col = g.col;
         a.wgt = g.wgt;
         a.mask = g.mask;
-        a.rv = rv;
-        a.rc = rc;
-        a.ruo = ruo;
+        a.rv = r.rv;
+        a.rc = r.rc;
+        a.ruo = r.ruo;
         a.cid_of = r.cid_of;
         a.kc = r.kc;
         a.recs = r.recs;
@@ -667,7 +722,6 @@ Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup,
         else if (NLW == 1) EVQ_LAUNCH("compact_reduce", (k_reduce<2, 1>), blocks, kBlock, s, a);
         else EVQ_LAUNCH("compact_reduce", (k_reduce<2, 2>), blocks, kBlock, s, a);
     }
-    return r;
 }
 
 uint64_t sum_u32(const uint32_t* d, uint32_t n, hipStream_t s) {
@@ -680,8 +734,8 @@ uint64_t sum_u32(const uint32_t* d, uint32_t n, hipStream_t s) {
 }
 
 template <int A, int LG, bool ST>
-void relax_phase(const Graph& g, const Window& W, const uint32_t* rcap, const Reduced& red, uint32_t* X, bool plain,
-                 uint32_t source, Frontier& f, Workspace& ws, hipStream_t s, QueryOut& qo) {
+void relax_phase(const Graph& g, const Window& W, const Window& PW, const uint32_t* rcap, const Reduced& red,
+                 uint32_t* X, bool plain, uint32_t source, Frontier& f, Workspace& ws, hipStream_t s, QueryOut& qo) {
     using T = Lanes<LG>;
     RelaxArgs ra;
     ra.cuo = red.cuo;
@@ -704,7 +758,7 @@ void relax_phase(const Graph& g, const Window& W, const uint32_t* rcap, const Re
             const uint32_t waves = (uint32_t)((g.n_partial + 63) / 64);
 #define EVQ_SEED(MW_)                                                                                             \
     EVQ_LAUNCH("relax_seed", (k_relax_seed<A, MW_, LG, ST>), grid_for(waves, kBlock / 64, 8192), kBlock, s, ra,   \
-               g.p_src, g.p_eid, (uint32_t)g.n_partial, g.col, g.wgt, g.mask, red.cid_of, rcap, W.b, W.L, g.K)
+               g.p_src, g.p_eid, (uint32_t)g.n_partial, g.col, g.wgt, g.mask, red.cid_of, rcap, W.b, W.L, g.K, PW.b, PW.L)
             if (g.MW == 1) EVQ_SEED(1);
             else EVQ_SEED(2);
 #undef EVQ_SEED
@@ -720,14 +774,16 @@ void relax_phase(const Graph& g, const Window& W, const uint32_t* rcap, const Re
 }
 
 template <int A>
-void relax_dispatch(uint32_t LG, bool st, const Graph& g, const Window& W, const uint32_t* rcap, const Reduced& red,
-                    uint32_t* X, bool plain, uint32_t source, Frontier& f, Workspace& ws, hipStream_t s, QueryOut& qo) {
-#define EVQ_RX(LG_)                                                                          \
-    case LG_:                                                                                \
-        if (st) relax_phase<A, LG_, true>(g, W, rcap, red, X, plain, source, f, ws, s, qo); \
-        else relax_phase<A, LG_, false>(g, W, rcap, red, X, plain, source, f, ws, s, qo);   \
+void relax_dispatch(uint32_t LG, bool st, const Graph& g, const Window& W, const Window& PW, const uint32_t* rcap,
+                    const Reduced& red, uint32_t* X, bool plain, uint32_t source, Frontier& f, Workspace& ws,
+                    hipStream_t s, QueryOut& qo) {
+#define EVQ_RX(LG_)                                                                               \
+    case LG_:                                                                                     \
+        if (st) relax_phase<A, LG_, true>(g, W, PW, rcap, red, X, plain, source, f, ws, s, qo);  \
+        else relax_phase<A, LG_, false>(g, W, PW, rcap, red, X, plain, source, f, ws, s, qo);    \
         break;
     switch (LG) {
+        EVQ_RX(1)
         EVQ_RX(8)
         EVQ_RX(16)
         EVQ_RX(32)
@@ -737,14 +793,16 @@ void relax_dispatch(uint32_t LG, bool st, const Graph& g, const Window& W, const
 #undef EVQ_RX
 }
 
-void relax_algo(uint32_t algo, uint32_t LG, bool st, const Graph& g, const Window& W, const uint32_t* rcap,
-                const Reduced& red, uint32_t* X, bool plain, uint32_t source, Frontier& f, Workspace& ws, hipStream_t s,
-                QueryOut& qo) {
+// PW: the window whose bounds rcap belongs to (seeding edges are partial in
+// it); W: the snapshots relaxed (W == PW, or one snapshot of PW).
+void relax_algo(uint32_t algo, uint32_t LG, bool st, const Graph& g, const Window& W, const Window& PW,
+                const uint32_t* rcap, const Reduced& red, uint32_t* X, bool plain, uint32_t source, Frontier& f,
+                Workspace& ws, hipStream_t s, QueryOut& qo) {
     switch (algo) {
-    case EVQ_SSSP: relax_dispatch<EVQ_SSSP>(LG, st, g, W, rcap, red, X, plain, source, f, ws, s, qo); break;
-    case EVQ_BFS: relax_dispatch<EVQ_BFS>(LG, st, g, W, rcap, red, X, plain, source, f, ws, s, qo); break;
-    case EVQ_SSWP: relax_dispatch<EVQ_SSWP>(LG, st, g, W, rcap, red, X, plain, source, f, ws, s, qo); break;
-    default: relax_dispatch<EVQ_SSNP>(LG, st, g, W, rcap, red, X, plain, source, f, ws, s, qo); break;
+    case EVQ_SSSP: relax_dispatch<EVQ_SSSP>(LG, st, g, W, PW, rcap, red, X, plain, source, f, ws, s, qo); break;
+    case EVQ_BFS: relax_dispatch<EVQ_BFS>(LG, st, g, W, PW, rcap, red, X, plain, source, f, ws, s, qo); break;
+    case EVQ_SSWP: relax_dispatch<EVQ_SSWP>(LG, st, g, W, PW, rcap, red, X, plain, source, f, ws, s, qo); break;
+    default: relax_dispatch<EVQ_SSNP>(LG, st, g, W, PW, rcap, red, X, plain, source, f, ws, s, qo); break;
     }
 }
 
@@ -834,7 +892,7 @@ void tail_impl(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     } else if (red.nU) {
         X = ws.buf<uint32_t>(Workspace::kX, (uint64_t)red.nU * LG);
     }
-    if (red.nU) relax_algo(algo, LG, st, g, W, rcap, red, X, false, source, f, ws, s, qo);
+    if (red.nU) relax_algo(algo, LG, st, g, W, W, rcap, red, X, false, source, f, ws, s, qo);
     tm.mark();
     if (d_values) writeback(LG, g.V, W.L, red.cid_of, rcap, X, d_values, s);
     tm.mark();
@@ -947,6 +1005,70 @@ void expand_compact(uint32_t V, uint32_t L, const uint32_t* rcap, const uint32_t
     }
 }
 
+// Ablation: the snapshots of the window one after another on the window's
+// reduced subgraph (Algorithm 1's per-snapshot evaluation), each as a
+// one-lane relaxation (one edge per lane), instead of all of them at once.
+void run_sequential(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values,
+                    QueryOut& qo, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    init_mempool(g.device);
+    Workspace& ws = Workspace::get(s);
+    Mailbox& mb = Mailbox::get();
+    const bool st = qo.want_stats;
+    Timer tm(st, s);
+    tm.mark();
+    Frontier f = make_frontier(g, ws, s);
+    f.delta = choose_delta(algo);
+    uint32_t* rcap = ws.buf<uint32_t>(Workspace::kRcap, g.V);
+    uint32_t* rcup = ws.buf<uint32_t>(Workspace::kRcup, g.V);
+    bounds_impl(g, algo, source, W, rcap, rcup, f, qo, s, tm);
+    uint32_t* T = ws.buf<uint32_t>(Workspace::kBatchCap, (uint64_t)W.L * g.V);
+    Reduced red;
+    uint64_t iters = 0, visits = 0, lanes = 0, seeds = 0;
+    for (uint32_t i = 0; i < W.L; ++i) {
+        Window Wi;
+        Wi.b = (W.b + i) % g.K;
+        Wi.L = 1;
+        Wi.K = g.K;
+        Wi.w[Wi.b >> 6] = 1ull << (Wi.b & 63);
+        Wi.full = g.K == 1;
+        if (i == 0) red = reduce_graph(g, rcap, rcup, false, Wi, 1, f, ws, mb, s);
+        else if (red.nU) reduce_edges(g, red, Wi, 1, ws, s);
+        uint32_t* X = nullptr;
+        if (red.nU) {
+            X = ws.buf<uint32_t>(Workspace::kX, red.nU);
+            relax_algo(algo, 1, st, g, Wi, W, rcap, red, X, false, source, f, ws, s, qo);
+            iters += qo.st.iters_relax;
+            if (st) {
+                visits += read_stat(f.stats, 1, s);
+                lanes += read_stat(f.stats, 2, s);
+                seeds += read_stat(f.stats, 3, s);
+                EVQ_LAUNCH("query_init", k_init_frontier_stats, 1, 64, s, f.stats);
+            }
+        }
+        EVQ_LAUNCH("writeback", k_column, grid_for(g.V, 256 * 4, 65535), 256, s, g.V,
+                   red.nU ? red.cid_of : nullptr, rcap, X, T + (uint64_t)i * g.V);
+    }
+    tm.mark();
+    const uint64_t tiles = ((g.V + 63) / 64) * (((uint64_t)W.L + 63) / 64);
+    EVQ_LAUNCH("writeback", k_columns_to_rows, grid_for(tiles, 1, 65535), 256, s, T, W.L, g.V, d_values);
+    tm.mark();
+    ws.in_use = false;
+    qo.st.iters_relax = iters;
+    if (st) {
+        qo.st.ms_cap = tm.ms(0, 1);
+        qo.st.ms_cup = tm.ms(1, 2);
+        qo.st.ms_relax = tm.ms(2, 3);
+        qo.st.ms_writeback = tm.ms(3, 4);
+        qo.st.n_unstable = red.nU;
+        qo.st.edge_visits_relax = visits;
+        qo.st.lane_relaxations = lanes;
+        qo.st.n_seed_edges = seeds;
+        EVQ_HIP(hipStreamSynchronize(s));
+        qo.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+}
+
 void run_plain(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values, QueryOut& qo,
                hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
@@ -962,7 +1084,7 @@ void run_plain(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     Reduced red = reduce_graph(g, nullptr, nullptr, true, W, NLW, f, ws, mb, s);
     tm.mark();
     uint32_t* X = ws.buf<uint32_t>(Workspace::kX, (uint64_t)g.V * LG);
-    relax_algo(algo, LG, st, g, W, nullptr, red, X, true, source, f, ws, s, qo);
+    relax_algo(algo, LG, st, g, W, W, nullptr, red, X, true, source, f, ws, s, qo);
     tm.mark();
     writeback(LG, g.V, W.L, red.cid_of, nullptr, X, d_values, s);
     tm.mark();

@@ -4,9 +4,9 @@ import numpy as np
 import oracle
 
 
-def gpu_values(g, algo, source, b, L, plain=False, stats=False):
+def gpu_values(g, algo, source, b, L, plain=False, stats=False, sequential=False):
     import paper_2502_10579_amd as evq
-    fn = g.query_plain if plain else g.query
+    fn = g.query_plain if plain else (g.query_sequential if sequential else g.query)
     r = fn(algo, source, b, L, stats=stats)
     if stats:
         out, st = r

@@ -121,8 +121,10 @@ def test_query_small_config(evq, algo, seed):
     with _graph(evq, inst) as g:
         got = gpu_values(g, algo, 0, 0, inst.K)
         plain = gpu_values(g, algo, 0, 0, inst.K, plain=True)
+        seq = gpu_values(g, algo, 0, 0, inst.K, sequential=True)
     assert_equal_values(got, want, f"algo {algo} seed {seed}")
     assert_equal_values(plain, want, f"plain algo {algo} seed {seed}")
+    assert_equal_values(seq, want, f"sequential algo {algo} seed {seed}")
 
 
 @pytest.mark.parametrize("algo", ALGOS)
@@ -146,8 +148,10 @@ def test_query_lane_layouts(evq, algo, K, b, L):
     with _graph(evq, inst) as g:
         got = gpu_values(g, algo, src, b, L)
         plain = gpu_values(g, algo, src, b, L, plain=True)
+        seq = gpu_values(g, algo, src, b, L, sequential=True)
     assert_equal_values(got, want, f"algo {algo} K {K} window [{b},{b + L})")
     assert_equal_values(plain, want, f"plain algo {algo} K {K} window [{b},{b + L})")
+    assert_equal_values(seq, want, f"sequential algo {algo} K {K} window [{b},{b + L})")
 
 
 def test_worked_example(evq):
@@ -253,7 +257,7 @@ def test_near_far_scheduling(evq, algo, delta, monkeypatch):
 
 
 @pytest.mark.parametrize("algo", ALGOS)
-def test_query_many_blocks_method_and_plain(evq, algo):
+def test_query_many_blocks_method_plain_sequential(evq, algo):
     # enough vertices that compact ids are assigned by many blocks in any order
     inst = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=31)
     src = synth.pick_sources(inst, 1, seed=3)[0]
@@ -263,5 +267,7 @@ def test_query_many_blocks_method_and_plain(evq, algo):
         with _graph(evq, inst) as g:
             got = gpu_values(g, algo, src, b, L)
             plain = gpu_values(g, algo, src, b, L, plain=True)
+            seq = gpu_values(g, algo, src, b, L, sequential=True)
         assert_equal_values(got, want, f"algo {algo} [{b},{b + L})")
         assert_equal_values(plain, want, f"plain algo {algo} [{b},{b + L})")
+        assert_equal_values(seq, want, f"sequential algo {algo} [{b},{b + L})")
