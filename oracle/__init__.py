@@ -22,8 +22,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-SSSP, BFS, SSWP, SSNP = 0, 1, 2, 3
-ALGOS = {"sssp": SSSP, "bfs": BFS, "sswp": SSWP, "ssnp": SSNP}
+SSSP, BFS, SSWP, SSNP, VITERBI = 0, 1, 2, 3, 4
+ALGOS = {"sssp": SSSP, "bfs": BFS, "sswp": SSWP, "ssnp": SSNP, "viterbi": VITERBI}
 INF = 0xFFFFFFFF
 SAT = 0xFFFFFFFE
 

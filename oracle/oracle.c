@@ -20,21 +20,30 @@
  *              source 0xFFFFFFFF, unreachable 0
  *        SSNP  path value = max w along the path, best = min, source 0,
  *              unreachable 0xFFFFFFFF
+ *        VITERBI  path value = the source's 1.0 divided by each weight along
+ *              the path in turn, best = max; values are IEEE single floats
+ *              held as their 32-bit patterns (non-negative, so their order is
+ *              the integer order): each step divides in double precision and
+ *              rounds to single (to nearest even), and a quotient below the
+ *              smallest normal single counts as unreachable (0.0)
  *   - The intersection graph of a window holds the triples present in every
  *     snapshot of the window; the union graph those present in any
  *     (Section 3, Step 1).
  *
  * Each snapshot is materialised on its own and solved from scratch by
- * Dijkstra's algorithm (SSSP, SSWP, SSNP: the path values never improve when
- * a path is extended, so settling vertices best-first is exact) or by a FIFO
+ * Dijkstra's algorithm (SSSP, SSWP, SSNP, VITERBI: the path values never
+ * improve when a path is extended, so settling vertices best-first is exact)
+ * or by a FIFO
  * breadth-first search (BFS).  This shares no code with the GPU library.
  */
+#include <float.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <omp.h>
 
-enum { O_SSSP = 0, O_BFS = 1, O_SSWP = 2, O_SSNP = 3 };
+enum { O_SSSP = 0, O_BFS = 1, O_SSWP = 2, O_SSNP = 3, O_VIT = 4 };
+#define ONE_F32 0x3F800000u /* 1.0f */
 #define INF32 0xFFFFFFFFu
 #define SAT32 0xFFFFFFFEu
 
@@ -229,15 +238,28 @@ static uint32_t extend(int algo, uint32_t xu, uint32_t w) {
     }
     case O_SSWP: return xu < w ? xu : w;
     case O_SSNP: return xu == INF32 ? INF32 : (xu > w ? xu : w);
+    case O_VIT: {
+        if (xu == 0u) return 0u;
+        float x;
+        memcpy(&x, &xu, 4);
+        const double q = (double)x / (double)w;
+        if (q < (double)FLT_MIN) return 0u;
+        const float r = (float)q;
+        uint32_t out;
+        memcpy(&out, &r, 4);
+        return out;
+    }
     }
     return INF32;
 }
 
+static int max_type(int algo) { return algo == O_SSWP || algo == O_VIT; }
+
 /* a is a strictly better value than b */
-static int better(int algo, uint32_t a, uint32_t b) { return algo == O_SSWP ? a > b : a < b; }
+static int better(int algo, uint32_t a, uint32_t b) { return max_type(algo) ? a > b : a < b; }
 
 static int solve_adj(int algo, uint32_t V, const adj_t* a, uint32_t source, uint32_t* val) {
-    uint32_t unreach = algo == O_SSWP ? 0u : INF32;
+    uint32_t unreach = max_type(algo) ? 0u : INF32;
     for (uint32_t v = 0; v < V; ++v) val[v] = unreach;
     if (source >= V) return -1;
     uint64_t m = a->off[V];
@@ -258,9 +280,9 @@ static int solve_adj(int algo, uint32_t V, const adj_t* a, uint32_t source, uint
     }
     heap_t q = {(uint64_t*)malloc((m + 2) * sizeof(uint64_t)), 0};
     uint8_t* done = (uint8_t*)calloc(V, 1);
-    val[source] = algo == O_SSWP ? INF32 : 0u;
-    /* the heap pops the smallest priority: widest-path priorities are complemented */
-#define PRIO(x) ((uint64_t)(algo == O_SSWP ? ~(x) : (x)) << 32)
+    val[source] = algo == O_SSWP ? INF32 : (algo == O_VIT ? ONE_F32 : 0u);
+    /* the heap pops the smallest priority: priorities of max-type queries are complemented */
+#define PRIO(x) ((uint64_t)(max_type(algo) ? ~(x) : (x)) << 32)
     heap_push(&q, PRIO(val[source]) | source);
     while (q.n) {
         uint64_t it = heap_pop(&q);
@@ -285,7 +307,7 @@ static int solve_adj(int algo, uint32_t V, const adj_t* a, uint32_t source, uint
 
 /* Solve on an explicit edge list (n triples, duplicates allowed). */
 int oracle_solve(uint32_t V, uint64_t n, const uint32_t* trip, int algo, uint32_t source, uint32_t* out) {
-    if (algo < 0 || algo > 3) return -1;
+    if (algo < 0 || algo > 4) return -1;
     uint8_t* keep = (uint8_t*)malloc(n + 1);
     memset(keep, 1, n + 1);
     adj_t a = {0, 0, 0};
@@ -307,7 +329,7 @@ static int has_bit(const uint64_t* bits, uint64_t j, uint32_t t) {
  */
 int oracle_query(uint32_t V, uint64_t n, const uint32_t* trip, const uint64_t* bits, int algo,
                  uint32_t source, const uint32_t* snaps, uint32_t n_snaps, uint32_t* out, int nthreads) {
-    if (algo < 0 || algo > 3 || source >= V) return -1;
+    if (algo < 0 || algo > 4 || source >= V) return -1;
     int err = 0;
     if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
@@ -339,7 +361,7 @@ int oracle_query(uint32_t V, uint64_t n, const uint32_t* trip, const uint64_t* b
  */
 int oracle_bounds(uint32_t V, uint64_t n, const uint32_t* trip, const uint64_t* bits, int algo,
                   uint32_t source, uint32_t b, uint32_t L, uint32_t* r_cap, uint32_t* r_cup) {
-    if (algo < 0 || algo > 3 || source >= V || L == 0) return -1;
+    if (algo < 0 || algo > 4 || source >= V || L == 0) return -1;
     uint8_t* all = (uint8_t*)malloc(n + 1);
     uint8_t* any = (uint8_t*)malloc(n + 1);
     for (uint64_t e = 0; e < n; ++e) {

@@ -9,9 +9,27 @@ from collections import deque
 
 import numpy as np
 
-SSSP, BFS, SSWP, SSNP = 0, 1, 2, 3
+SSSP, BFS, SSWP, SSNP, VIT = 0, 1, 2, 3, 4
 INF = 0xFFFFFFFF
 SAT = 0xFFFFFFFE
+ONE = 0x3F800000  # 1.0 as an IEEE single
+FLT_MIN = float(np.finfo(np.float32).tiny)
+
+
+def max_type(algo):
+    return algo in (SSWP, VIT)
+
+
+def vit_step(bits, w):
+    """One Viterbi step: the single float with pattern `bits` divided by w in double precision, rounded to
+    single (nearest even); a quotient below the smallest normal single is unreachable (0)."""
+    if bits == 0:
+        return 0
+    x = float(np.array([bits], dtype=np.uint32).view(np.float32)[0])
+    q = x / float(w)
+    if q < FLT_MIN:
+        return 0
+    return int(np.array([q], dtype=np.float32).view(np.uint32)[0])
 
 
 def snapshot_sets(inst):
@@ -29,11 +47,11 @@ def snapshot_sets(inst):
 
 
 def unreachable(algo):
-    return 0 if algo == SSWP else INF
+    return 0 if max_type(algo) else INF
 
 
 def source_value(algo):
-    return INF if algo == SSWP else 0
+    return INF if algo == SSWP else (ONE if algo == VIT else 0)
 
 
 def path_value(algo, weights):
@@ -44,6 +62,11 @@ def path_value(algo, weights):
         return min(len(weights), SAT)
     if algo == SSWP:
         return min(weights) if weights else INF
+    if algo == VIT:
+        x = ONE
+        for w in weights:
+            x = vit_step(x, w)
+        return x
     return max(weights) if weights else 0
 
 
@@ -51,7 +74,7 @@ def best_of(algo, vals):
     vals = list(vals)
     if not vals:
         return None
-    return max(vals) if algo == SSWP else min(vals)
+    return max(vals) if max_type(algo) else min(vals)
 
 
 def enumerate_paths(V, edges, algo, s):
@@ -95,11 +118,13 @@ def bellman_ford(V, edges, algo, s):
                 c = min(xu + 1, SAT)
             elif algo == SSWP:
                 c = min(xu, w)
+            elif algo == VIT:
+                c = vit_step(xu, w)
             else:
                 if xu == INF:
                     continue
                 c = max(xu, w)
-            if (c > val[v]) if algo == SSWP else (c < val[v]):
+            if (c > val[v]) if max_type(algo) else (c < val[v]):
                 val[v] = c
                 changed = True
         if not changed:

@@ -12,7 +12,8 @@ import oracle
 import synth
 from fixtures import empty_batches_instance, instance_from, load_golden
 
-ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP]
+ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP, oracle.VITERBI]
+MAX_TYPE = (oracle.SSWP, oracle.VITERBI)
 INF = oracle.INF
 
 
@@ -126,12 +127,48 @@ def test_closed_forms_on_rmat(seed):
     assert (oracle.solve(V, e, oracle.SSNP, s) == brute.threshold_narrowest(V, el, s)).all()
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_viterbi_closed_forms(seed):
+    # weights 2^k: every division is exact while the value stays normal, so the value is 2^-d with d the
+    # shortest path in the exponents (scipy, independent of the oracle), or unreachable once d > 126
+    V, e = _rmat_graph(10, 6000, seed, 3)
+    el = [tuple(map(int, r)) for r in e]
+    deg = np.bincount(e[:, 0], minlength=V)
+    s = int(np.flatnonzero(deg > 0)[seed])
+    d = brute.scipy_sssp(V, el, s).astype(np.int64)
+    pw = e.copy()
+    pw[:, 2] = 1 << e[:, 2]
+    got = oracle.solve(V, pw, oracle.VITERBI, s)
+    want = np.zeros(V, dtype=np.uint32)
+    ok = (d != INF) & (d <= 126)
+    want[ok] = (np.ldexp(np.ones(ok.sum(), dtype=np.float32), -d[ok].astype(np.int32))).view(np.uint32)
+    assert (got == want).all()
+    # unit weights: 1.0 exactly where reachable
+    unit = e.copy()
+    unit[:, 2] = 1
+    reach = brute.reachable(V, el, s)
+    got = oracle.solve(V, unit, oracle.VITERBI, s)
+    assert (got == np.where(reach, brute.ONE, 0).astype(np.uint32)).all()
+
+
+def test_viterbi_rounding_and_underflow():
+    # 1/3 rounds to the nearest single; long chains of /100 leave the normal range and become unreachable
+    e = [(0, 1, 3), (1, 2, 3)] + [(i, i + 1, 100) for i in range(2, 30)]
+    got = oracle.solve(31, np.asarray(e, dtype=np.uint32), oracle.VITERBI, 0)
+    assert got[1] == np.array([1 / 3], dtype=np.float32).view(np.uint32)[0]
+    third = float(np.array([1 / 3], dtype=np.float32)[0])
+    assert got[2] == np.array([third / 3], dtype=np.float32).view(np.uint32)[0]
+    assert (got == brute.bellman_ford(31, e, oracle.VITERBI, 0)).all()
+    vals = got.view(np.float32)
+    assert (vals[vals > 0] >= np.finfo(np.float32).tiny).all() and got[30] == 0 and got[20] != 0
+
+
 def test_source_without_out_edges():
     e = np.asarray([[1, 2, 3], [2, 0, 4]], dtype=np.uint32)
     for algo in ALGOS:
         got = oracle.solve(3, e, algo, 0)
-        src = INF if algo == oracle.SSWP else 0
-        unr = 0 if algo == oracle.SSWP else INF
+        src = INF if algo == oracle.SSWP else (brute.ONE if algo == oracle.VITERBI else 0)
+        unr = 0 if algo in MAX_TYPE else INF
         assert got.tolist() == [src, unr, unr]
 
 
@@ -173,7 +210,7 @@ def test_theorems_1_and_2_on_small_rmat(algo):
     V, K = inst.num_vertices, inst.K
     vals = oracle.window_values(inst, algo, 0, 0, K, replayed=(trip, bits))
     rcap, rcup = oracle.bounds(V, trip, bits, algo, 0, 0, K)
-    lo, hi = (rcap, rcup) if algo == oracle.SSWP else (rcup, rcap)  # Table 1 directions
+    lo, hi = (rcap, rcup) if algo in MAX_TYPE else (rcup, rcap)  # Table 1 directions
     assert (vals >= lo[:, None]).all() and (vals <= hi[:, None]).all()
     stable = rcap == rcup
     assert (vals[stable] == rcap[stable][:, None]).all()
