@@ -211,6 +211,75 @@ def bench_served(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_sweep(args):
+    """Sensitivity (the paper's Fig. 12 analogue): R-MAT scale 20 (16,777,216 samples, w in [1,100]), SSSP
+    from a seeded source over the whole window, with K = 32 / 64 / 128 snapshots of 10k+10k updates and, at
+    K = 64, batches of 5k / 25k / 50k / 100k updates of each kind (0.03% - 0.6% of the edges per snapshot).
+    Per point: |U|, reduced-subgraph edges, and the method against the plain concurrent and the sequential
+    per-snapshot evaluations (all three checked equal on the device)."""
+    import torch
+
+    import paper_2502_10579_amd as evq
+    import synth
+
+    torch.cuda.set_device(0)
+    points = [(32, 10000), (64, 10000), (128, 10000), (64, 5000), (64, 25000), (64, 50000), (64, 100000)]
+    rows = []
+    for K, nb in points:
+        inst = synth.rmat_instance(20, 16777216, K, nb, nb, 1, 100, seed=args.seed)
+        src = synth.pick_sources(inst, 1, seed=args.seed)[0]
+        g = evq.Graph.from_instance(inst)
+        ex = g.export()
+        snap_edges = int(snapshot_edge_counts(ex, K).sum())
+        del ex
+        out = torch.empty((inst.num_vertices, K), dtype=torch.int32, device="cuda")
+        ref = torch.empty_like(out)
+        res = {}
+        for name, fn in (("method", g.query), ("plain", g.query_plain), ("sequential", g.query_sequential)):
+            fn(0, src, 0, K, out=out if name == "method" else ref)
+            torch.cuda.synchronize()
+            reps = 5 if name == "method" else 2
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn(0, src, 0, K, out=out if name == "method" else ref)
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t) * 1000.0 / reps
+            if name != "method":
+                res[name + "_identical"] = bool(torch.equal(out, ref))
+        _, st = g.query(0, src, 0, K, out=out, stats=True)
+        row = {"K": K, "batch": nb, "union_edges": g.info["num_edges"], "n_unstable": st["n_unstable"],
+               "unstable_frac": st["n_unstable"] / inst.num_vertices, "reduced_edges": st["n_relax_edges"],
+               "seed_edges": st["n_seed_edges"], "method_ms": round(res["method"], 3),
+               "plain_ms": round(res["plain"], 3), "sequential_ms": round(res["sequential"], 3),
+               "speedup_vs_plain": round(res["plain"] / res["method"], 2),
+               "speedup_vs_sequential": round(res["sequential"] / res["method"], 2),
+               "identical": res["plain_identical"] and res["sequential_identical"],
+               "snapshot_edges_per_s": snap_edges / (res["method"] / 1000.0)}
+        log(f"[sweep] {json.dumps(row)}")
+        rows.append(row)
+        g.close()
+        del out, ref
+    res = {
+        "metric": "snapshot-edge relaxations/s",
+        "value": rows[1]["snapshot_edges_per_s"],
+        "unit": "snapshot-edges/s",
+        "n_gpus": 1,
+        "steps": 5,
+        "warmup": 1,
+        "ms_per_step": rows[1]["method_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "sensitivity: R-MAT scale 20 (16777216 samples, w in [1,100]), SSSP over the "
+                               "whole window; K in {32,64,128} at 10k+10k updates, batch in {5k,25k,50k,100k} "
+                               "at K=64"},
+        "points": rows,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def bench_batched(args):
     """Batching: R-MAT scale 22, K = 128 snapshots of 20k + 20k updates, 256 queries (algorithm uniform over the
     four, source random with base out-degree > 0, start uniform in [0, 100], length uniform in [25, 100] clamped
@@ -319,6 +388,8 @@ def main():
         return bench_served(args)
     if args.config == "batched":
         return bench_batched(args)
+    if args.config == "sweep":
+        return bench_sweep(args)
 
     import torch
 

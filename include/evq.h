@@ -36,6 +36,11 @@
  *         unreachable 0
  *   SSNP  min over paths of the maximum weight; source 0; unreachable
  *         0xFFFFFFFF
+ *   VITERBI  max over paths of 1.0 divided by each weight along the path in
+ *         turn, as IEEE single floats held in the uint32 values (bit
+ *         patterns): each step divides in double precision and rounds to
+ *         single (to nearest even); a quotient below the smallest normal
+ *         single is unreachable.  Source 1.0 (0x3F800000); unreachable 0.0.
  */
 #ifndef EVQ_H
 #define EVQ_H
@@ -49,7 +54,7 @@ extern "C" {
 
 typedef int32_t evq_status;
 #define EVQ_OK 0
-#define EVQ_EINVAL (-1)    /* malformed argument: NULL pointer, id >= V, w == 0, K out of range */
+#define EVQ_EINVAL (-1)    /* malformed argument: NULL pointer, id >= V, w == 0, K out of range, unknown algo */
 #define EVQ_ERANGE (-2)    /* window / source / size out of the supported range */
 #define EVQ_ENOMEM (-3)    /* device or host allocation failed */
 #define EVQ_EDEVICE (-4)   /* a HIP runtime call failed */
@@ -60,6 +65,7 @@ typedef int32_t evq_status;
 #define EVQ_BFS 1
 #define EVQ_SSWP 2
 #define EVQ_SSNP 3
+#define EVQ_VITERBI 4
 
 #define EVQ_MAX_SNAPSHOTS 128
 
@@ -141,7 +147,7 @@ evq_status evq_graph_export(const evq_graph* g, uint32_t* row_ptr, uint32_t* row
 /*
  * Answer a query over the window [win_begin, win_begin + win_len) of
  * snapshots (Algorithm 1 followed by Algorithm 2).
- *   algo: EVQ_SSSP / EVQ_BFS / EVQ_SSWP / EVQ_SSNP; source < V.
+ *   algo: EVQ_SSSP / EVQ_BFS / EVQ_SSWP / EVQ_SSNP / EVQ_VITERBI; source < V.
  *   Snapshots are named by global id: the graph holds first .. first+K-1
  *   (first = first_snapshot of evq_graph_info, 0 until an evq_append), so
  *   first <= win_begin, 1 <= win_len and win_begin + win_len <= first + K.

@@ -13,8 +13,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("EVQ_LIBRARY") or os.path.join(_HERE, "libevq.so")
 
-SSSP, BFS, SSWP, SSNP = 0, 1, 2, 3
-ALGOS = {"sssp": SSSP, "bfs": BFS, "sswp": SSWP, "ssnp": SSNP}
+SSSP, BFS, SSWP, SSNP, VITERBI = 0, 1, 2, 3, 4
+ALGOS = {"sssp": SSSP, "bfs": BFS, "sswp": SSWP, "ssnp": SSNP, "viterbi": VITERBI}
 INF = 0xFFFFFFFF
 
 EVQ_OK, EVQ_EINVAL, EVQ_ERANGE, EVQ_ENOMEM, EVQ_EDEVICE, EVQ_ENOCONV = 0, -1, -2, -3, -4, -5
@@ -438,6 +438,11 @@ def set_batch_config(lanes=0, chunk=0, blocks=0, group=0):
 def to_u32(t) -> np.ndarray:
     """Host uint32 view of an int32 device tensor."""
     return t.detach().cpu().numpy().view(np.uint32)
+
+
+def to_f32(t) -> np.ndarray:
+    """Host float32 view of Viterbi values (IEEE single bit patterns in an int32 device tensor)."""
+    return t.detach().cpu().numpy().view(np.float32)
 
 
 def timing_enable(on=True):

@@ -43,7 +43,7 @@ evq_status bad(evq_status c, const char* msg) {
 // [b, b + L) (global ids; the graph holds first .. first + K - 1).
 evq_status make_window(const evq::Graph& g, uint32_t algo, uint32_t source, uint64_t b, uint32_t L,
                        evq::Window& W) {
-    if (algo > EVQ_SSNP) return bad(EVQ_EINVAL, "unknown algorithm");
+    if (algo > EVQ_VITERBI) return bad(EVQ_EINVAL, "unknown algorithm");
     if (source >= g.V) return bad(EVQ_ERANGE, "source vertex out of range");
     if (L == 0 || L > g.K || b < g.first || b - g.first > g.K - L) return bad(EVQ_ERANGE, "window out of range");
     W.b = (uint32_t)(b % g.K);

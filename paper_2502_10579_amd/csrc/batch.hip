@@ -283,7 +283,8 @@ void batch_bounds_mw(uint32_t algo, const Graph& g, BatchArgs a, uint32_t* Xcap,
     case EVQ_SSSP: batch_bounds_t<EVQ_SSSP, MW>(g, a, Xcap, Xcup, d_src, nq, tu, f, s, bt); break;
     case EVQ_BFS: batch_bounds_t<EVQ_BFS, MW>(g, a, Xcap, Xcup, d_src, nq, tu, f, s, bt); break;
     case EVQ_SSWP: batch_bounds_t<EVQ_SSWP, MW>(g, a, Xcap, Xcup, d_src, nq, tu, f, s, bt); break;
-    default: batch_bounds_t<EVQ_SSNP, MW>(g, a, Xcap, Xcup, d_src, nq, tu, f, s, bt); break;
+    case EVQ_SSNP: batch_bounds_t<EVQ_SSNP, MW>(g, a, Xcap, Xcup, d_src, nq, tu, f, s, bt); break;
+    default: batch_bounds_t<EVQ_VITERBI, MW>(g, a, Xcap, Xcup, d_src, nq, tu, f, s, bt); break;
     }
 }
 
@@ -508,7 +509,7 @@ void run_batch(const Graph& g, const BatchQuery* q, uint32_t n, Compact* out, ev
     // groups of one algorithm, up to 64 queries each
     std::vector<std::vector<uint32_t>> groups;
     if (tu.lanes == 1) {
-        for (uint32_t a = 0; a < 4; ++a) {
+        for (uint32_t a = 0; a <= EVQ_VITERBI; ++a) {
             std::vector<uint32_t> ids;
             for (uint32_t i = 0; i < n; ++i)
                 if (q[i].algo == a) ids.push_back(i);

@@ -305,8 +305,31 @@ struct Alg<EVQ_SSNP> {
     }
 };
 
-inline uint32_t host_unreached(uint32_t algo) { return algo == EVQ_SSWP ? 0u : kInf; }
-inline uint32_t host_at_source(uint32_t algo) { return algo == EVQ_SSWP ? kInf : 0u; }
+// Viterbi (Table 2: the best of Val(u) / w): IEEE single values held as
+// their bit patterns (non-negative, so the integer order is the float
+// order); a step divides in double precision and rounds to single, and a
+// quotient below the smallest normal single is unreachable (0).
+template <>
+struct Alg<EVQ_VITERBI> {
+    static constexpr uint32_t unreached = 0u, at_source = 0x3F800000u;  // 0.0f, 1.0f
+    __device__ static __forceinline__ uint32_t extend(uint32_t x, uint32_t w) {
+        if (x == 0u) return 0u;
+        const double q = (double)__uint_as_float(x) / (double)w;
+        if (q < 1.1754943508222875e-38) return 0u;  // FLT_MIN
+        return __float_as_uint((float)q);
+    }
+    __device__ static __forceinline__ bool better(uint32_t a, uint32_t b) { return a > b; }
+    __device__ static __forceinline__ uint32_t improve(uint32_t* p, uint32_t v) { return atomicMax(p, v); }
+    __device__ static __forceinline__ void improve_nr(uint32_t* p, uint32_t v) {
+        __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+inline bool max_type(uint32_t algo) { return algo == EVQ_SSWP || algo == EVQ_VITERBI; }
+inline uint32_t host_unreached(uint32_t algo) { return max_type(algo) ? 0u : kInf; }
+inline uint32_t host_at_source(uint32_t algo) {
+    return algo == EVQ_SSWP ? kInf : (algo == EVQ_VITERBI ? 0x3F800000u : 0u);
+}
 
 // Snapshot-mask helpers: MW 64-bit words per edge.
 template <int MW>

@@ -802,7 +802,8 @@ void relax_algo(uint32_t algo, uint32_t LG, bool st, const Graph& g, const Windo
     case EVQ_SSSP: relax_dispatch<EVQ_SSSP>(LG, st, g, W, PW, rcap, red, X, plain, source, f, ws, s, qo); break;
     case EVQ_BFS: relax_dispatch<EVQ_BFS>(LG, st, g, W, PW, rcap, red, X, plain, source, f, ws, s, qo); break;
     case EVQ_SSWP: relax_dispatch<EVQ_SSWP>(LG, st, g, W, PW, rcap, red, X, plain, source, f, ws, s, qo); break;
-    default: relax_dispatch<EVQ_SSNP>(LG, st, g, W, PW, rcap, red, X, plain, source, f, ws, s, qo); break;
+    case EVQ_SSNP: relax_dispatch<EVQ_SSNP>(LG, st, g, W, PW, rcap, red, X, plain, source, f, ws, s, qo); break;
+    default: relax_dispatch<EVQ_VITERBI>(LG, st, g, W, PW, rcap, red, X, plain, source, f, ws, s, qo); break;
     }
 }
 
@@ -821,8 +822,9 @@ void writeback(uint32_t LG, uint32_t V, uint32_t L, const uint32_t* cid_of, cons
 }  // namespace
 
 uint32_t choose_delta(uint32_t algo) {
-    static const char* names[4] = {"EVQ_DELTA_SSSP", "EVQ_DELTA_BFS", "EVQ_DELTA_SSWP", "EVQ_DELTA_SSNP"};
-    const char* e = getenv(names[algo & 3]);
+    static const char* names[5] = {"EVQ_DELTA_SSSP", "EVQ_DELTA_BFS", "EVQ_DELTA_SSWP", "EVQ_DELTA_SSNP",
+                                   "EVQ_DELTA_VITERBI"};
+    const char* e = getenv(names[algo <= EVQ_VITERBI ? algo : 0]);
     if (!e) e = getenv("EVQ_DELTA");
     if (e) return (uint32_t)strtoul(e, nullptr, 10);
     return 0u;

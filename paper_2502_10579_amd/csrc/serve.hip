@@ -68,7 +68,7 @@ struct evq_server {
     uint64_t next_ticket = 1;
     uint64_t inflight_bytes = 0;
     uint32_t inflight = 0, groups = 0;
-    double est_unstable[4] = {0, 0, 0, 0};  // running estimate of |U| / V per algorithm
+    double est_unstable[5] = {0, 0, 0, 0, 0};  // running estimate of |U| / V per algorithm
     bool stop = false;
     std::thread dispatcher;
 
@@ -83,7 +83,7 @@ namespace {
 uint64_t estimate(const evq_server* sv, const Graph& g, uint32_t algo, uint32_t L) {
     const uint64_t V = g.V;
     const uint64_t LG = pick_lg(L);
-    const double fu = sv->est_unstable[algo & 3] > 0 ? sv->est_unstable[algo & 3] : 0.0625;
+    const double fu = sv->est_unstable[algo] > 0 ? sv->est_unstable[algo] : 0.0625;
     return 8 * V + (uint64_t)(fu * (double)V) * (LG * 4 + 4);
 }
 
@@ -102,7 +102,7 @@ void complete(evq_server* sv, SQuery* q, const Graph& g, hipStream_t s) {
     if (e != hipSuccess && q->status == EVQ_OK) q->status = EVQ_EDEVICE;
     std::lock_guard<std::mutex> lk(sv->mu);
     if (q->status == EVQ_OK) {
-        double& est = sv->est_unstable[q->algo & 3];
+        double& est = sv->est_unstable[q->algo];
         const double f = (double)q->c.nU / (double)g.V;
         est = est > 0 ? 0.875 * est + 0.125 * f : f;
     }
@@ -373,7 +373,7 @@ evq_status evq_server_create(evq_graph* h, const evq_server_config* c, evq_serve
 evq_status evq_server_submit(evq_server* sv, uint32_t algo, uint32_t source, uint32_t win_len, uint64_t* ticket) {
     evq::g_last_error.clear();
     if (!sv || !ticket) return sbad(EVQ_EINVAL, "NULL argument");
-    if (algo > EVQ_SSNP) return sbad(EVQ_EINVAL, "unknown algorithm");
+    if (algo > EVQ_VITERBI) return sbad(EVQ_EINVAL, "unknown algorithm");
     auto gp = sv->h->get();
     if (source >= gp->V) return sbad(EVQ_ERANGE, "source vertex out of range");
     if (win_len == 0) return sbad(EVQ_ERANGE, "window length must be >= 1");

@@ -82,7 +82,7 @@ __device__ __forceinline__ bool partial_in(const uint64_t* __restrict__ mask, ui
 
 template <int A>
 __device__ __forceinline__ uint32_t order_key(uint32_t x) {
-    return A == EVQ_SSWP ? ~x : x;
+    return (A == EVQ_SSWP || A == EVQ_VITERBI) ? ~x : x;
 }
 
 template <int MODE>
@@ -344,7 +344,8 @@ uint64_t dispatch_cap(uint32_t algo, const Graph& g, const Window& W, uint32_t s
     case EVQ_SSSP: return solve_cap_t<EVQ_SSSP, MW, ST>(g, W, source, R, f, s);
     case EVQ_BFS: return solve_cap_t<EVQ_BFS, MW, ST>(g, W, source, R, f, s);
     case EVQ_SSWP: return solve_cap_t<EVQ_SSWP, MW, ST>(g, W, source, R, f, s);
-    default: return solve_cap_t<EVQ_SSNP, MW, ST>(g, W, source, R, f, s);
+    case EVQ_SSNP: return solve_cap_t<EVQ_SSNP, MW, ST>(g, W, source, R, f, s);
+    default: return solve_cap_t<EVQ_VITERBI, MW, ST>(g, W, source, R, f, s);
     }
 }
 
@@ -354,7 +355,8 @@ uint64_t dispatch_cup(uint32_t algo, const Graph& g, const Window& W, uint32_t* 
     case EVQ_SSSP: return solve_cup_t<EVQ_SSSP, MW, ST>(g, W, R, f, s);
     case EVQ_BFS: return solve_cup_t<EVQ_BFS, MW, ST>(g, W, R, f, s);
     case EVQ_SSWP: return solve_cup_t<EVQ_SSWP, MW, ST>(g, W, R, f, s);
-    default: return solve_cup_t<EVQ_SSNP, MW, ST>(g, W, R, f, s);
+    case EVQ_SSNP: return solve_cup_t<EVQ_SSNP, MW, ST>(g, W, R, f, s);
+    default: return solve_cup_t<EVQ_VITERBI, MW, ST>(g, W, R, f, s);
     }
 }
 

@@ -62,6 +62,13 @@ def test_batch_small_mixed(evq, lanes, seed):
     _check_batch(evq, inst, qs, lanes)
 
 
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_batch_viterbi(evq, lanes):
+    inst = synth.config_instance("small", seed=6)
+    qs = synth.batch_queries(inst, 20, seed=6, start_max=7, len_min=1, len_max=8, algos=(4, 2))
+    _check_batch(evq, inst, qs, lanes)
+
+
 @pytest.mark.parametrize("chunk,group", [(4, 64), (8, 16), (16, 5), (8, 1)])
 def test_batch_chunks_grids_groups(evq, chunk, group):
     inst = synth.config_instance("small", seed=4)

@@ -19,7 +19,7 @@ from gpu_util import assert_equal_values
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP]
+ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP, oracle.VITERBI]
 
 
 @pytest.fixture(scope="module")
@@ -75,7 +75,7 @@ def test_appends_while_querying(evq):
             i = 0
             with torch.cuda.stream(st):
                 while not done.is_set() or i < 3:
-                    a = ALGOS[(tid + i) % 4]
+                    a = ALGOS[(tid + i) % 5]
                     s = src[(tid + i) % len(src)]
                     L = 1 + (i * 5 + tid) % K
                     try:
@@ -96,7 +96,7 @@ def test_appends_while_querying(evq):
             with torch.cuda.stream(st):
                 while not done.is_set() or i < 2:
                     first = g.first
-                    qs = [(ALGOS[k % 4], src[k], first + K - 1 - k, 1 + k) for k in range(6)]
+                    qs = [(ALGOS[k % 5], src[k], first + K - 1 - k, 1 + k) for k in range(6)]
                     try:
                         res = g.query_batch(qs, stream=st.cuda_stream)
                         st.synchronize()

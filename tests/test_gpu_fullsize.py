@@ -1,6 +1,6 @@
 """GPU parity at the full workload sizes, in the configuration bench.py times.
 
-mid   (R-MAT scale 20, K = 64): SSSP and BFS from the seeded source, every one
+mid   (R-MAT scale 20, K = 64): SSSP, BFS and Viterbi from the seeded source, every one
       of the 64 snapshots compared with the oracle, plus the bounds.
 large (R-MAT scale 23, K = 100, weights [1, 1000], two-word masks): SSWP and
       SSNP; three sampled snapshots compared with the oracle, and on all 100
@@ -39,7 +39,7 @@ def large():
     return inst, oracle.replay(inst), synth.pick_sources(inst, 1, seed=1)[0]
 
 
-@pytest.mark.parametrize("algo", [oracle.SSSP, oracle.BFS])
+@pytest.mark.parametrize("algo", [oracle.SSSP, oracle.BFS, oracle.VITERBI])
 def test_mid_all_snapshots(evq, mid, algo):
     inst, rep, src = mid
     V, K = inst.num_vertices, inst.K

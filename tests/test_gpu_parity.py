@@ -14,7 +14,7 @@ from gpu_util import assert_equal_values, gpu_bounds, gpu_values, oracle_triples
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP]
+ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP, oracle.VITERBI]
 
 
 @pytest.fixture(scope="module")

@@ -24,7 +24,7 @@ from gpu_util import assert_equal_values, union_triples_from_export
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP]
+ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP, oracle.VITERBI]
 
 
 @pytest.fixture(scope="module")
@@ -137,7 +137,7 @@ def test_ring_queries_wrap(evq, K, A):
         first = g.first
         wins = _windows(first, K, rng, 10) + [(first, K), (first + K - 1, 1)]
         src = synth.pick_sources(inst, len(wins), seed=K)
-        qs = [(ALGOS[i % 4], src[i], b, L) for i, (b, L) in enumerate(wins)]
+        qs = [(ALGOS[i % 5], src[i], b, L) for i, (b, L) in enumerate(wins)]
         wrapped = sum(1 for (_, _, b, L) in qs if (b % K) + L > K)
         print(f"ring K={K} first={first}: {len(qs)} windows, {wrapped} wrap", flush=True)
         want = [oracle.window_values(inst, a, s, b, L, replayed=rep) for (a, s, b, L) in qs]

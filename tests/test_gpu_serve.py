@@ -16,7 +16,7 @@ from gpu_util import assert_equal_values
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP]
+ALGOS = [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP, oracle.VITERBI]
 
 
 @pytest.fixture(scope="module")
@@ -69,7 +69,7 @@ def test_serve_mix_equals_alone_and_oracle(evq, mode):
     with evq.Graph.from_instance(inst) as g:
         with evq.Server(g, mode=mode) as srv:
             for i in range(60):
-                srv.submit(ALGOS[int(rng.integers(0, 4))], src[i], int(rng.integers(1, 21)))
+                srv.submit(ALGOS[int(rng.integers(0, 5))], src[i], int(rng.integers(1, 21)))
             comps = collect(srv, 60)
             assert sorted(c["ticket"] for c in comps) == list(range(1, 61))
             for c in comps:
@@ -89,7 +89,7 @@ def test_serve_with_appends(evq):
             k = 0
             for a in range(A + 1):
                 for _ in range(8):
-                    srv.submit(ALGOS[k % 4], src[k], int(rng.integers(1, K + 1)))
+                    srv.submit(ALGOS[k % 5], src[k], int(rng.integers(1, K + 1)))
                     k += 1
                 if a < A:
                     comps += srv.poll(256, 0)
@@ -108,7 +108,7 @@ def test_serve_budget_admits_one_at_a_time(evq):
     with evq.Graph.from_instance(inst) as g:
         with evq.Server(g, mode="batch", mem_budget=1) as srv:
             for i in range(12):
-                srv.submit(ALGOS[i % 4], src[i], 1 + i % K)
+                srv.submit(ALGOS[i % 5], src[i], 1 + i % K)
             comps = sorted(collect(srv, 12), key=lambda c: c["t_admit_ms"])
             for prev, nxt in zip(comps, comps[1:]):
                 assert nxt["t_admit_ms"] >= prev["t_done_ms"] - 1e-3, "two queries in flight under a one-query budget"
@@ -123,7 +123,7 @@ def test_serve_single_query_groups(evq):
     with evq.Graph.from_instance(inst) as g:
         with evq.Server(g, mode="batch", max_batch=1, max_groups=4) as srv:
             for i in range(16):
-                srv.submit(ALGOS[i % 4], src[i], 1 + i % K)
+                srv.submit(ALGOS[i % 5], src[i], 1 + i % K)
             check(evq, g, inst, rep, collect(srv, 16))
 
 
@@ -133,7 +133,7 @@ def test_serve_destroy_with_queued_queries(evq):
     with evq.Graph.from_instance(inst) as g:
         srv = evq.Server(g, mode="plain")
         for i in range(200):
-            srv.submit(ALGOS[i % 4], src[i], 8)
+            srv.submit(ALGOS[i % 5], src[i], 8)
         srv.close()  # queued ones are dropped, running ones finish, uncollected results released
         with pytest.raises(evq.EvqError):
             evq.Server(g, mode="batch", max_batch=65)
