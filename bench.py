@@ -246,14 +246,28 @@ def bench_sweep(args):
             res[name] = (time.perf_counter() - t) * 1000.0 / reps
             if name != "method":
                 res[name + "_identical"] = bool(torch.equal(out, ref))
-        _, st = g.query(0, src, 0, K, out=out, stats=True)
-        row = {"K": K, "batch": nb, "union_edges": g.info["num_edges"], "n_unstable": st["n_unstable"],
-               "unstable_frac": st["n_unstable"] / inst.num_vertices, "reduced_edges": st["n_relax_edges"],
-               "seed_edges": st["n_seed_edges"], "method_ms": round(res["method"], 3),
+        # the same query with sub-window splitting on (more than 35% unstable: two halves, recursively)
+        os.environ["EVQ_SPLIT_FRAC"] = "0.35"
+        g.query(0, src, 0, K, out=ref)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            g.query(0, src, 0, K, out=ref)
+        torch.cuda.synchronize()
+        res["split"] = (time.perf_counter() - t) * 1000.0 / 3
+        _, st = g.query(0, src, 0, K, out=ref, stats=True)
+        del os.environ["EVQ_SPLIT_FRAC"]
+        res["split_identical"] = bool(torch.equal(out, ref))
+        _, st0 = g.query(0, src, 0, K, out=out, stats=True)
+        row = {"K": K, "batch": nb, "union_edges": g.info["num_edges"], "n_unstable": st0["n_unstable"],
+               "unstable_frac": st0["n_unstable"] / inst.num_vertices, "reduced_edges": st0["n_relax_edges"],
+               "seed_edges": st0["n_seed_edges"], "subwindows": st["subwindows"],
+               "unstable_after_split": st["n_unstable"], "method_ms": round(res["method"], 3),
+               "method_split_ms": round(res["split"], 3),
                "plain_ms": round(res["plain"], 3), "sequential_ms": round(res["sequential"], 3),
                "speedup_vs_plain": round(res["plain"] / res["method"], 2),
                "speedup_vs_sequential": round(res["sequential"] / res["method"], 2),
-               "identical": res["plain_identical"] and res["sequential_identical"],
+               "identical": res["plain_identical"] and res["sequential_identical"] and res["split_identical"],
                "snapshot_edges_per_s": snap_edges / (res["method"] / 1000.0)}
         log(f"[sweep] {json.dumps(row)}")
         rows.append(row)

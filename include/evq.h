@@ -110,6 +110,7 @@ typedef struct {
     uint64_t updates_cap, updates_cup;    /* improving value updates of the two bound solves */
     uint64_t items_cap, items_cup;        /* frontier vertices expanded by the two bound solves */
     uint64_t seed_visits_cup;             /* partial edges examined to seed the union solve */
+    uint64_t subwindows;                  /* windows relaxed (more than 1 when the window was split) */
 } evq_query_stats;
 
 /*
@@ -159,6 +160,10 @@ evq_status evq_graph_export(const evq_graph* g, uint32_t* row_ptr, uint32_t* row
  * The graph is only read, so queries may run concurrently on several streams.
  * The call returns once the last frontier loop has drained (it reads frontier
  * sizes back); the values are complete when `stream` reaches that point.
+ * With the environment variable EVQ_SPLIT_FRAC set to f > 0, a window with
+ * more than f * V unstable vertices is answered as two halves (at least
+ * EVQ_SPLIT_MIN snapshots each, default 8; to depth 4), each with its own
+ * bounds; the values are the same.  Off by default.
  */
 evq_status evq_query(const evq_graph* g, uint32_t algo, uint32_t source, uint32_t win_begin,
                      uint32_t win_len, uint32_t* d_values, evq_query_stats* stats, void* stream);

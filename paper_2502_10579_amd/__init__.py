@@ -48,7 +48,8 @@ class QueryStats(ctypes.Structure):
                [(n, ctypes.c_uint64) for n in ("n_unstable", "n_seed_edges", "n_relax_edges", "iters_cap",
                                                "iters_cup", "iters_relax", "edges_cap", "edges_cup",
                                                "edge_visits_relax", "lane_relaxations", "updates_cap",
-                                               "updates_cup", "items_cap", "items_cup", "seed_visits_cup")]
+                                               "updates_cup", "items_cap", "items_cup", "seed_visits_cup",
+                                               "subwindows")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

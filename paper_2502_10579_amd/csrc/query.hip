@@ -507,11 +507,11 @@ __global__ void k_mark_source(uint8_t* flags, const uint32_t* __restrict__ cid_o
 }
 
 // values[v * L + i], four values per lane (L % 4 == 0, 16-byte aligned rows).
-__global__ void __launch_bounds__(kBlock) k_writeback4(uint32_t V, uint32_t L, uint32_t S,
+__global__ void __launch_bounds__(kBlock) k_writeback4(uint32_t V, uint32_t L, uint32_t S, uint32_t OS,
                                                        const uint32_t* __restrict__ cid_of,
                                                        const uint32_t* __restrict__ rcap,
                                                        const uint32_t* __restrict__ X, uint32_t* __restrict__ out) {
-    const uint32_t Lq = L >> 2;
+    const uint32_t Lq = L >> 2, OSq = OS >> 2;
     const uint32_t rows = kBlock / Lq;
     const uint32_t r = threadIdx.x / Lq, j = threadIdx.x - r * Lq;
     if (r >= rows) return;
@@ -526,12 +526,12 @@ __global__ void __launch_bounds__(kBlock) k_writeback4(uint32_t V, uint32_t L, u
         } else {
             val = x4[(uint64_t)c * (S >> 2) + j];
         }
-        o4[v * Lq + j] = val;
+        o4[v * OSq + j] = val;
     }
 }
 
 // values[v * L + i], one value per lane (any L).
-__global__ void __launch_bounds__(kBlock) k_writeback1(uint32_t V, uint32_t L, uint32_t S,
+__global__ void __launch_bounds__(kBlock) k_writeback1(uint32_t V, uint32_t L, uint32_t S, uint32_t OS,
                                                        const uint32_t* __restrict__ cid_of,
                                                        const uint32_t* __restrict__ rcap,
                                                        const uint32_t* __restrict__ X, uint32_t* __restrict__ out) {
@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(kBlock) k_writeback1(uint32_t V, uint32_t L, u
         const uint64_t v = k / L;
         const uint32_t i = (uint32_t)(k - v * L);
         const uint32_t c = cid_of ? cid_of[v] : kNone;
-        out[k] = c == kNone ? rcap[v] : X[(uint64_t)c * S + i];
+        out[v * OS + i] = c == kNone ? rcap[v] : X[(uint64_t)c * S + i];
     }
 }
 
@@ -662,6 +662,7 @@ struct Reduced {
     uint32_t* ruo = nullptr;
     uint32_t* kc = nullptr;
     void* recs = nullptr;
+    bool split = false;  // |U| exceeded the caller's threshold: no subgraph was built
 };
 
 void reduce_edges(const Graph& g, Reduced& r, const Window& W, uint32_t NLW, Workspace& ws, hipStream_t s);
@@ -669,7 +670,8 @@ void reduce_edges(const Graph& g, Reduced& r, const Window& W, uint32_t NLW, Wor
 // Builds U's compact ids and the reduced subgraph.  all_vertices: U = V.
 // One host read-back (|U|, rows, edges) sizes the subgraph buffer.
 Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup, bool all_vertices, const Window& W,
-                     uint32_t NLW, const Frontier& f, Workspace& ws, Mailbox& mb, hipStream_t s) {
+                     uint32_t NLW, const Frontier& f, Workspace& ws, Mailbox& mb, hipStream_t s,
+                     uint32_t split_above = 0xFFFFFFFFu) {
     Reduced r;
     const uint32_t V = g.V;
     r.cid_of = ws.buf<uint32_t>(Workspace::kCidOf, V);
@@ -689,6 +691,10 @@ Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup,
     r.nR = (uint32_t)(hc[1] >> 32);
     r.TU = (uint32_t)hc[1];
     if (r.nU == 0) return r;
+    if (r.nU > split_above) {
+        r.split = true;
+        return r;
+    }
     reduce_edges(g, r, W, NLW, ws, s);
     return r;
 }
@@ -807,14 +813,17 @@ void relax_algo(uint32_t algo, uint32_t LG, bool st, const Graph& g, const Windo
     }
 }
 
+// values[v * OS + i], i < L (OS: the output's row stride, >= L).
 void writeback(uint32_t LG, uint32_t V, uint32_t L, const uint32_t* cid_of, const uint32_t* rcap, const uint32_t* X,
-               uint32_t* out, hipStream_t s) {
-    const bool vec = (L % 4 == 0) && ((uintptr_t)out % 16 == 0);
+               uint32_t* out, hipStream_t s, uint32_t OS = 0) {
+    if (OS == 0) OS = L;
+    const bool vec = (L % 4 == 0) && (OS % 4 == 0) && ((uintptr_t)out % 16 == 0);
     if (vec) {
         const uint32_t rows = kBlock / (L / 4);
-        EVQ_LAUNCH("writeback", k_writeback4, grid_for(V, rows, 65535), kBlock, s, V, L, LG, cid_of, rcap, X, out);
+        EVQ_LAUNCH("writeback", k_writeback4, grid_for(V, rows, 65535), kBlock, s, V, L, LG, OS, cid_of, rcap, X,
+                   out);
     } else {
-        EVQ_LAUNCH("writeback", k_writeback1, grid_for((uint64_t)V * L, kBlock * 4, 65535), kBlock, s, V, L, LG,
+        EVQ_LAUNCH("writeback", k_writeback1, grid_for((uint64_t)V * L, kBlock * 4, 65535), kBlock, s, V, L, LG, OS,
                    cid_of, rcap, X, out);
     }
 }
@@ -868,14 +877,15 @@ void bounds_impl(const Graph& g, uint32_t algo, uint32_t source, const Window& W
 // Steps 2-3 and Algorithm 2: reduction, then the multi-snapshot relaxation
 // into X (the workspace, or a compact result's rows), then the writeback of
 // values[V][L] when d_values is given.
-void tail_impl(const Graph& g, uint32_t algo, uint32_t source, const Window& W, const uint32_t* rcap,
+bool tail_impl(const Graph& g, uint32_t algo, uint32_t source, const Window& W, const uint32_t* rcap,
                const uint32_t* rcup, Frontier& f, Workspace& ws, uint32_t* d_values, Compact* c, QueryOut& qo,
-               hipStream_t s, Timer& tm) {
+               hipStream_t s, Timer& tm, uint32_t OS = 0, uint32_t split_above = 0xFFFFFFFFu) {
     const bool st = qo.want_stats;
     Mailbox& mb = Mailbox::get();
     const uint32_t LG = pick_lg(W.L);
     const uint32_t NLW = LG > 64 ? 2 : 1;
-    Reduced red = reduce_graph(g, rcap, rcup, false, W, NLW, f, ws, mb, s);
+    Reduced red = reduce_graph(g, rcap, rcup, false, W, NLW, f, ws, mb, s, split_above);
+    if (red.split) return false;
     tm.mark();
     uint32_t* X = nullptr;
     if (c) {
@@ -896,14 +906,68 @@ void tail_impl(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     }
     if (red.nU) relax_algo(algo, LG, st, g, W, W, rcap, red, X, false, source, f, ws, s, qo);
     tm.mark();
-    if (d_values) writeback(LG, g.V, W.L, red.cid_of, rcap, X, d_values, s);
+    if (d_values) writeback(LG, g.V, W.L, red.cid_of, rcap, X, d_values, s, OS);
     tm.mark();
+    qo.st.n_unstable += red.nU;
+    qo.st.subwindows += 1;
     if (st) {
-        qo.st.n_unstable = red.nU;
-        qo.st.n_relax_edges = red.nU ? sum_u32(red.kc, red.nU, s) : 0;
+        qo.st.n_relax_edges += red.nU ? sum_u32(red.kc, red.nU, s) : 0;
+        // cumulative over the sub-windows of a split query
         qo.st.edge_visits_relax = read_stat(f.stats, 1, s);
         qo.st.lane_relaxations = read_stat(f.stats, 2, s);
         qo.st.n_seed_edges = read_stat(f.stats, 3, s);
+    }
+    return true;
+}
+
+// Sub-window splitting (off unless EVQ_SPLIT_FRAC > 0): a window whose
+// unstable set holds more than EVQ_SPLIT_FRAC of the vertices is answered as
+// two halves of at least EVQ_SPLIT_MIN snapshots each (default 8), each with
+// its own bound solves (the intersection grows and the union shrinks as the
+// window narrows, so fewer vertices stay unstable), to depth 4.  Under churn
+// spread evenly over the window the halves stay about as unstable and the
+// extra bound solves cost more than they save, hence off by default.
+struct SplitRule {
+    double frac = 0.0;
+    uint32_t min_len = 8;
+    static SplitRule get() {
+        SplitRule r;
+        if (const char* e = getenv("EVQ_SPLIT_FRAC")) r.frac = atof(e);
+        if (const char* e = getenv("EVQ_SPLIT_MIN")) r.min_len = (uint32_t)strtoul(e, nullptr, 10);
+        if (r.min_len < 1) r.min_len = 1;
+        return r;
+    }
+};
+
+Window sub_window(const Graph& g, const Window& W, uint32_t off, uint32_t len) {
+    Window S;
+    S.b = (W.b + off) % g.K;
+    S.L = len;
+    S.K = g.K;
+    for (uint32_t i = 0; i < len; ++i) {
+        const uint32_t t = (S.b + i) % g.K;
+        S.w[t >> 6] |= 1ull << (t & 63);
+    }
+    S.full = len == g.K;
+    return S;
+}
+
+// The tail of window W (whose bounds are in rcap / rcup) into out, row stride OS.
+void answer(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* rcap, uint32_t* rcup,
+            Frontier& f, Workspace& ws, uint32_t* out, uint32_t OS, QueryOut& qo, hipStream_t s, Timer& tm,
+            uint32_t depth, const SplitRule& sr) {
+    const bool can = sr.frac > 0.0 && W.L >= 2 * sr.min_len && depth < 4;
+    const uint32_t above = can ? (uint32_t)(sr.frac * (double)g.V) : 0xFFFFFFFFu;
+    if (tail_impl(g, algo, source, W, rcap, rcup, f, ws, out, nullptr, qo, s, tm, OS, above)) return;
+    const uint32_t L1 = W.L / 2;
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t off = h ? L1 : 0, len = h ? W.L - L1 : L1;
+        const Window S = sub_window(g, W, off, len);
+        QueryOut qs;
+        qs.want_stats = false;
+        Timer quiet(false, s);
+        bounds_impl(g, algo, source, S, rcap, rcup, f, qs, s, quiet);
+        answer(g, algo, source, S, rcap, rcup, f, ws, out + off, OS, qo, s, quiet, depth + 1, sr);
     }
 }
 
@@ -927,7 +991,7 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
         ws.in_use = false;
         return;
     }
-    tail_impl(g, algo, source, W, rcap, rcup, f, ws, d_values, nullptr, qo, s, tm);
+    answer(g, algo, source, W, rcap, rcup, f, ws, d_values, W.L, qo, s, tm, 0, SplitRule::get());
     ws.in_use = false;
     if (st) {
         qo.st.ms_cap = tm.ms(0, 1);

@@ -271,3 +271,23 @@ def test_query_many_blocks_method_plain_sequential(evq, algo):
         assert_equal_values(got, want, f"algo {algo} [{b},{b + L})")
         assert_equal_values(plain, want, f"plain algo {algo} [{b},{b + L})")
         assert_equal_values(seq, want, f"sequential algo {algo} [{b},{b + L})")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("K,b,L,min_len", [(20, 3, 17, 2), (64, 0, 64, 8), (100, 13, 87, 3), (128, 0, 128, 1)])
+def test_split_subwindows_equal_oracle(evq, algo, K, b, L, min_len, monkeypatch):
+    # a threshold of 0 unstable vertices forces every window of 2 * min_len or more to split, to depth 4
+    inst = synth.rmat_instance(11, 12000, K, 12, 12, wmin=1, wmax=30, seed=K + b + 7)
+    src = synth.pick_sources(inst, 1, seed=K + 1)[0]
+    want = oracle.window_values(inst, algo, src, b, L)
+    monkeypatch.setenv("EVQ_SPLIT_FRAC", "1e-9")
+    monkeypatch.setenv("EVQ_SPLIT_MIN", str(min_len))
+    with _graph(evq, inst) as g:
+        got, st = gpu_values(g, algo, src, b, L, stats=True)
+        monkeypatch.setenv("EVQ_SPLIT_FRAC", "0")
+        one, st1 = gpu_values(g, algo, src, b, L, stats=True)
+    assert_equal_values(got, want, f"split algo {algo} K {K} [{b},{b + L})")
+    assert_equal_values(one, want, f"unsplit algo {algo} K {K} [{b},{b + L})")
+    assert st1["subwindows"] == 1
+    if st1["n_unstable"] > 0:
+        assert st["subwindows"] > 1
