@@ -164,6 +164,11 @@ evq_status evq_graph_export(const evq_graph* g, uint32_t* row_ptr, uint32_t* row
  * more than f * V unstable vertices is answered as two halves (at least
  * EVQ_SPLIT_MIN snapshots each, default 8; to depth 4), each with its own
  * bounds; the values are the same.  Off by default.
+ * Scheduling of the bound solves (the values never change): EVQ_DELTA[_SSSP,
+ * _BFS, _SSWP, _SSNP, _VITERBI] = d > 0 defers vertices whose order key is not
+ * below a threshold that steps by d (near/far); with EVQ_HEAVY[_ALGO] = h > 0
+ * only vertices with at least h edges are deferred and the threshold follows
+ * the frontier's best key plus d.  Both off by default.
  */
 evq_status evq_query(const evq_graph* g, uint32_t algo, uint32_t source, uint32_t win_begin,
                      uint32_t win_len, uint32_t* d_values, evq_query_stats* stats, void* stream);

@@ -20,11 +20,15 @@ struct Frontier {
     unsigned long long* aux = nullptr;    // 128 bytes of scratch counters for the reduction
     int p = 0;                            // parity of the next compaction (continues across phases)
     uint32_t delta = 0;                   // near/far step of the bound solves (0: off)
+    uint32_t heavy = 0;                   // with delta: gate only vertices with this many edges (0: all)
     uint64_t items = 0;                   // frontier items processed so far (published counts)
 };
 
 // Near/far step for a query: EVQ_DELTA overrides, else a per-algorithm default.
 uint32_t choose_delta(uint32_t algo);
+// Edge count from which vertices are gated: EVQ_HEAVY overrides, else a
+// per-algorithm default (0: every vertex is gated).
+uint32_t choose_heavy(uint32_t algo);
 
 
 Frontier make_frontier(const Graph& g, Workspace& ws, hipStream_t s);

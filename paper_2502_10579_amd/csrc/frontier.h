@@ -26,6 +26,8 @@ struct FrontierCounters {
     uint32_t fmin[2];              // smallest order key among those ids, by parity
     uint32_t thr;                  // near/far threshold of the bound solves (order keys below it are near)
     uint32_t delta;                // threshold step (0: every id is near)
+    uint32_t heavy;                // with delta > 0: only ids with at least this many edges are gated (0: all)
+    uint32_t kall[2];              // smallest order key over the compacted ids with edges, by parity (heavy > 0)
 };
 
 __device__ __forceinline__ uint32_t items_of(unsigned long long x) { return (uint32_t)(x >> 32); }
@@ -42,18 +44,25 @@ inline uint64_t flag_bytes(uint64_t n) { return (n + 7) & ~uint64_t(7); }
 // publish the item count to the host slot.
 // When nothing was near but ids were deferred, the threshold moves to the
 // smallest deferred order key plus delta, so the next compaction releases the
-// best of them.
+// best of them.  When only heavy ids are gated, the threshold also follows the
+// frontier: it rises to the smallest key of this iteration's ids plus delta,
+// so a heavy id is expanded once its value is within delta of the best one
+// still moving (and, with positive steps, close to final).
 __device__ __forceinline__ unsigned long long expand_prologue(FrontierCounters* c, int p, uint32_t* slot) {
     const unsigned long long x = c->packed[p];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const uint32_t f = c->far[p];
-        if (items_of(x) == 0 && f) {
-            const uint64_t t = (uint64_t)c->fmin[p] + c->delta;
-            c->thr = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
+        uint64_t t = c->thr;
+        if (items_of(x) == 0 && f) t = (uint64_t)c->fmin[p] + c->delta;
+        if (c->heavy && c->kall[p] != 0xFFFFFFFFu) {
+            const uint64_t u = (uint64_t)c->kall[p] + c->delta;
+            t = u > t ? u : t;
         }
+        c->thr = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
         c->packed[p ^ 1] = 0ull;
         c->far[p ^ 1] = 0u;
         c->fmin[p ^ 1] = 0xFFFFFFFFu;
+        c->kall[p ^ 1] = 0xFFFFFFFFu;
         __hip_atomic_store(slot, items_of(x) + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     return x;
@@ -101,7 +110,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // and returns false to defer the id: its flag stays set, it is counted in
 // *far and its order key enters the minimum *fmin.  emit(id, item, edge,
 // items, edges) writes an id's work.  Ids appear in ascending order within a
-// block.
+// block.  With kall non-null, size_of gives every id with edges its order key
+// and the smallest of them enters the minimum *kall.
 constexpr int kCompactBlock = 512;
 constexpr int kCompactWaves = kCompactBlock / 64;
 constexpr int kIdsPerWave = 512;
@@ -110,10 +120,11 @@ constexpr int kIdSteps = kIdsPerWave / 64;
 
 template <typename SizeFn, typename EmitFn>
 __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint32_t n, unsigned long long* cnt,
-                                              uint32_t* far, uint32_t* fmin, SizeFn size_of, EmitFn emit) {
+                                              uint32_t* far, uint32_t* fmin, SizeFn size_of, EmitFn emit,
+                                              uint32_t* kall = nullptr) {
     __shared__ uint32_t ids[kCompactWaves][kIdsPerWave];
     __shared__ uint32_t keep[kCompactWaves][64];
-    __shared__ uint32_t wtot[kCompactWaves][4];
+    __shared__ uint32_t wtot[kCompactWaves][5];
     __shared__ unsigned long long bbase;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     uint2* __restrict__ f8 = reinterpret_cast<uint2*>(flags);
@@ -132,13 +143,13 @@ __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint3
         const uint32_t incl = wave_incl_scan(pc);
         const uint32_t tot = __shfl(incl, 63, 64);
         uint32_t id[kIdSteps], ni[kIdSteps], ne[kIdSteps], pi[kIdSteps], pe[kIdSteps];
-        uint32_t ti = 0, te = 0, tf = 0, tk = 0xFFFFFFFFu;
+        uint32_t ti = 0, te = 0, tf = 0, tk = 0xFFFFFFFFu, ta = 0xFFFFFFFFu;
         if (tot) {
             keep[wave][lane] = 0;
             uint32_t k = incl - pc;
             for (uint32_t m = word; m; m &= m - 1) ids[wave][k++] = g0 + (uint32_t)__builtin_ctz(m);
             wave_lds_sync();
-            uint32_t nf = 0, kmin = 0xFFFFFFFFu;
+            uint32_t nf = 0, kmin = 0xFFFFFFFFu, amin = 0xFFFFFFFFu;
 #pragma unroll
             for (int s = 0; s < kIdSteps; ++s) {
                 const uint32_t j = s * 64 + lane;
@@ -147,8 +158,10 @@ __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint3
                 ne[s] = 0;
                 if (j < tot) {
                     id[s] = ids[wave][j];
-                    uint32_t key = 0;
-                    if (!size_of(id[s], ni[s], ne[s], key)) {  // deferred: its flag stays set
+                    uint32_t key = 0xFFFFFFFFu;
+                    const bool near = size_of(id[s], ni[s], ne[s], key);
+                    amin = key < amin ? key : amin;
+                    if (!near) {  // deferred: its flag stays set
                         ni[s] = ne[s] = 0;
                         ++nf;
                         kmin = key < kmin ? key : kmin;
@@ -172,6 +185,14 @@ __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint3
                 kmin = o < kmin ? o : kmin;
             }
             tk = kmin;
+            if (kall) {
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) {
+                    const uint32_t o = __shfl_xor(amin, d, 64);
+                    amin = o < amin ? o : amin;
+                }
+                ta = amin;
+            }
             wave_lds_sync();
             if (word) {
                 const uint32_t kb = keep[wave][lane];
@@ -189,21 +210,25 @@ __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint3
             wtot[wave][1] = te;
             wtot[wave][2] = tf;
             wtot[wave][3] = tk;
+            wtot[wave][4] = ta;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned long long sum = 0;
-            uint32_t fsum = 0, kmin = 0xFFFFFFFFu;
+            uint32_t fsum = 0, kmin = 0xFFFFFFFFu, amin = 0xFFFFFFFFu;
             for (int w = 0; w < kCompactWaves; ++w) {
                 sum += ((unsigned long long)wtot[w][0] << 32) | wtot[w][1];
                 fsum += wtot[w][2];
                 kmin = wtot[w][3] < kmin ? wtot[w][3] : kmin;
+                amin = wtot[w][4] < amin ? wtot[w][4] : amin;
             }
             bbase = sum ? atomicAdd(cnt, sum) : 0ull;
             if (fsum) {
                 atomicAdd(far, fsum);
                 atomicMin(fmin, kmin);
             }
+            // a plain read first: most blocks hold no new minimum and skip the atomic
+            if (kall && amin < __hip_atomic_load(kall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(kall, amin);
         }
         __syncthreads();
         if (ti) {
@@ -250,10 +275,13 @@ uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_it
 
 void wait_slot(volatile uint32_t* slot, hipStream_t s, const char* what);
 
+// Iterations kept in flight by drive_loop: EVQ_LAUNCH_DEPTH (1..32), default 3.
+uint64_t launch_depth();
+
 template <typename IssueFn>
 uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_iters, const char* what,
                     uint64_t* items) {
-    constexpr uint64_t kDepth = 3;
+    const uint64_t kDepth = launch_depth();
     HostSlots& hs = HostSlots::get();
     uint64_t issued = 0, consumed = 0;
     const uint64_t base = hs.next;

@@ -506,27 +506,108 @@ __global__ void k_mark_source(uint8_t* flags, const uint32_t* __restrict__ cid_o
     if (threadIdx.x == 0) flags[cid_of[source]] = 1;
 }
 
-// values[v * L + i], four values per lane (L % 4 == 0, 16-byte aligned rows).
+// 16-byte store that streams past the caches (the output is written once and
+// not read again by the query).
+__device__ __forceinline__ void stream_store(uint4 v, uint4* p) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(p));
+}
+
+// values[v * OS + i], i < L (L % 4 == 0, L <= 256, 16-byte aligned rows of
+// stride OS).  A wave takes 64 consecutive vertices: one coalesced load of
+// their compact ids (and of R_cap for the stable ones), then their rows as
+// lane-contiguous 16-byte streaming stores, 64 / (L / 4) rows per
+// instruction, with eight instructions' values gathered before any is
+// stored, so that the per-row loads do not serialise the stores.
 __global__ void __launch_bounds__(kBlock) k_writeback4(uint32_t V, uint32_t L, uint32_t S, uint32_t OS,
                                                        const uint32_t* __restrict__ cid_of,
                                                        const uint32_t* __restrict__ rcap,
                                                        const uint32_t* __restrict__ X, uint32_t* __restrict__ out) {
-    const uint32_t Lq = L >> 2, OSq = OS >> 2;
-    const uint32_t rows = kBlock / Lq;
-    const uint32_t r = threadIdx.x / Lq, j = threadIdx.x - r * Lq;
-    if (r >= rows) return;
+    const uint32_t Lq = L >> 2, OSq = OS >> 2, Sq = S >> 2;
+    const uint32_t lane = lane_id();
+    const uint32_t rpi = 64 / Lq;  // rows per store instruction
+    const uint32_t r = lane / Lq, j = lane - r * Lq;
+    const bool on = r < rpi;
+    const uint32_t steps = (64 + rpi - 1) / rpi;
+    const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
     uint4* __restrict__ o4 = reinterpret_cast<uint4*>(out);
     const uint4* __restrict__ x4 = reinterpret_cast<const uint4*>(X);
-    for (uint64_t v = (uint64_t)blockIdx.x * rows + r; v < V; v += (uint64_t)gridDim.x * rows) {
-        const uint32_t c = cid_of ? cid_of[v] : kNone;
-        uint4 val;
-        if (c == kNone) {
-            const uint32_t b = rcap[v];
-            val = make_uint4(b, b, b, b);
-        } else {
-            val = x4[(uint64_t)c * (S >> 2) + j];
+    for (uint64_t w = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w * 64 < V; w += nw) {
+        const uint64_t v0 = w * 64;
+        uint32_t c = kNone, b = 0;
+        if (v0 + lane < V) {
+            if (cid_of) c = cid_of[v0 + lane];
+            if (c == kNone) b = rcap[v0 + lane];
         }
-        o4[v * OSq + j] = val;
+        for (uint32_t s0 = 0; s0 < steps; s0 += 8) {
+            uint4 val[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const uint32_t k = (s0 + t) * rpi + r;  // row within the wave's 64
+                const uint32_t ck = (uint32_t)__shfl((int)c, (int)(k & 63), 64);
+                const uint32_t bk = (uint32_t)__shfl((int)b, (int)(k & 63), 64);
+                val[t] = make_uint4(bk, bk, bk, bk);
+                if (on && k < 64 && v0 + k < V && ck != kNone) val[t] = x4[(uint64_t)ck * Sq + j];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const uint32_t k = (s0 + t) * rpi + r;
+                if (on && k < 64 && v0 + k < V) stream_store(val[t], &o4[(v0 + k) * OSq + j]);
+            }
+        }
+    }
+}
+
+// values[v * L + i] with rows stored back to back (4 <= L <= 256): the 64 rows
+// of a wave are one contiguous range of 64 L values that starts 256-byte
+// aligned, written as lane-contiguous 16-byte streaming stores, one of which
+// may straddle two rows.  The rows' compact ids and R_cap values are staged in
+// LDS; magic = floor(2^32 / L) + 1 turns the row lookup into a multiply-high,
+// exact for offsets below 64 L.
+__global__ void __launch_bounds__(kBlock) k_writeback_flat(uint32_t V, uint32_t L, uint32_t S, uint32_t magic,
+                                                           const uint32_t* __restrict__ cid_of,
+                                                           const uint32_t* __restrict__ rcap,
+                                                           const uint32_t* __restrict__ X,
+                                                           uint32_t* __restrict__ out) {
+    __shared__ uint32_t sc[kBlock / 64][64], sb[kBlock / 64][64];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t w = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w * 64 < V; w += nw) {
+        const uint64_t v0 = w * 64;
+        const uint32_t rows = V - v0 < 64 ? (uint32_t)(V - v0) : 64u;
+        uint32_t c = kNone, b = 0;
+        if (lane < rows) {
+            if (cid_of) c = cid_of[v0 + lane];
+            if (c == kNone) b = rcap[v0 + lane];
+        }
+        sc[wave][lane] = c;
+        sb[wave][lane] = b;
+        wave_lds_sync();
+        const uint32_t n = rows * L, n4 = n >> 2;
+        uint32_t* __restrict__ o = out + v0 * L;
+        for (uint32_t q = lane; q < n4; q += 64) {
+            uint32_t row = __umulhi(q * 4, magic);
+            uint32_t col = q * 4 - row * L;
+            uint32_t val[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (col >= L) {
+                    col -= L;
+                    ++row;
+                }
+                const uint32_t cr = sc[wave][row];
+                val[t] = cr == kNone ? sb[wave][row] : X[(uint64_t)cr * S + col];
+                ++col;
+            }
+            stream_store(make_uint4(val[0], val[1], val[2], val[3]), reinterpret_cast<uint4*>(o) + q);
+        }
+        for (uint32_t e = n4 * 4 + lane; e < n; e += 64) {  // a last partial wave's n % 4 values
+            const uint32_t row = __umulhi(e, magic), col = e - row * L;
+            const uint32_t cr = sc[wave][row];
+            __builtin_nontemporal_store(cr == kNone ? sb[wave][row] : X[(uint64_t)cr * S + col], &o[e]);
+        }
+        wave_lds_sync();
     }
 }
 
@@ -540,7 +621,7 @@ __global__ void __launch_bounds__(kBlock) k_writeback1(uint32_t V, uint32_t L, u
         const uint64_t v = k / L;
         const uint32_t i = (uint32_t)(k - v * L);
         const uint32_t c = cid_of ? cid_of[v] : kNone;
-        out[v * OS + i] = c == kNone ? rcap[v] : X[(uint64_t)c * S + i];
+        __builtin_nontemporal_store(c == kNone ? rcap[v] : X[(uint64_t)c * S + i], &out[v * OS + i]);
     }
 }
 
@@ -817,10 +898,16 @@ void relax_algo(uint32_t algo, uint32_t LG, bool st, const Graph& g, const Windo
 void writeback(uint32_t LG, uint32_t V, uint32_t L, const uint32_t* cid_of, const uint32_t* rcap, const uint32_t* X,
                uint32_t* out, hipStream_t s, uint32_t OS = 0) {
     if (OS == 0) OS = L;
-    const bool vec = (L % 4 == 0) && (OS % 4 == 0) && ((uintptr_t)out % 16 == 0);
+    if (OS == L && L >= 4 && L <= 256 && (uintptr_t)out % 16 == 0) {
+        const uint32_t magic = (uint32_t)((1ull << 32) / L + 1);
+        EVQ_LAUNCH("writeback", k_writeback_flat, grid_for(V, kBlock, 65535), kBlock, s, V, L, LG, magic, cid_of,
+                   rcap, X, out);
+        return;
+    }
+    const bool vec = (L % 4 == 0) && (L <= 256) && (OS % 4 == 0) && ((uintptr_t)out % 16 == 0) &&
+                     (X == nullptr || LG % 4 == 0);
     if (vec) {
-        const uint32_t rows = kBlock / (L / 4);
-        EVQ_LAUNCH("writeback", k_writeback4, grid_for(V, rows, 65535), kBlock, s, V, L, LG, OS, cid_of, rcap, X,
+        EVQ_LAUNCH("writeback", k_writeback4, grid_for(V, kBlock, 65535), kBlock, s, V, L, LG, OS, cid_of, rcap, X,
                    out);
     } else {
         EVQ_LAUNCH("writeback", k_writeback1, grid_for((uint64_t)V * L, kBlock * 4, 65535), kBlock, s, V, L, LG, OS,
@@ -835,6 +922,15 @@ uint32_t choose_delta(uint32_t algo) {
                                    "EVQ_DELTA_VITERBI"};
     const char* e = getenv(names[algo <= EVQ_VITERBI ? algo : 0]);
     if (!e) e = getenv("EVQ_DELTA");
+    if (e) return (uint32_t)strtoul(e, nullptr, 10);
+    return 0u;
+}
+
+uint32_t choose_heavy(uint32_t algo) {
+    static const char* names[5] = {"EVQ_HEAVY_SSSP", "EVQ_HEAVY_BFS", "EVQ_HEAVY_SSWP", "EVQ_HEAVY_SSNP",
+                                   "EVQ_HEAVY_VITERBI"};
+    const char* e = getenv(names[algo <= EVQ_VITERBI ? algo : 0]);
+    if (!e) e = getenv("EVQ_HEAVY");
     if (e) return (uint32_t)strtoul(e, nullptr, 10);
     return 0u;
 }
@@ -983,6 +1079,7 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     tm.mark();
     Frontier f = make_frontier(g, ws, s);
     f.delta = choose_delta(algo);
+    f.heavy = choose_heavy(algo);
     uint32_t* rcap = d_rcap_out ? d_rcap_out : ws.buf<uint32_t>(Workspace::kRcap, g.V);
     uint32_t* rcup = d_rcup_out ? d_rcup_out : ws.buf<uint32_t>(Workspace::kRcup, g.V);
     bounds_impl(g, algo, source, W, rcap, rcup, f, qo, s, tm);
@@ -1011,6 +1108,7 @@ void run_bounds(const Graph& g, uint32_t algo, uint32_t source, const Window& W,
     Timer tm(false, s);
     Frontier f = make_frontier(g, ws, s);
     f.delta = choose_delta(algo);
+    f.heavy = choose_heavy(algo);
     bounds_impl(g, algo, source, W, rcap, rcup, f, qo, s, tm);
     ws.in_use = false;
 }
@@ -1025,6 +1123,7 @@ void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Win
     tm.mark();
     Frontier f = make_frontier(g, ws, s);
     f.delta = choose_delta(algo);
+    f.heavy = choose_heavy(algo);
     uint32_t* rcup = ws.buf<uint32_t>(Workspace::kRcup, g.V);
     bounds_impl(g, algo, source, W, c.rcap, rcup, f, qo, s, tm);
     tail_impl(g, algo, source, W, c.rcap, rcup, f, ws, nullptr, &c, qo, s, tm);
@@ -1085,6 +1184,7 @@ void run_sequential(const Graph& g, uint32_t algo, uint32_t source, const Window
     tm.mark();
     Frontier f = make_frontier(g, ws, s);
     f.delta = choose_delta(algo);
+    f.heavy = choose_heavy(algo);
     uint32_t* rcap = ws.buf<uint32_t>(Workspace::kRcap, g.V);
     uint32_t* rcup = ws.buf<uint32_t>(Workspace::kRcup, g.V);
     bounds_impl(g, algo, source, W, rcap, rcup, f, qo, s, tm);

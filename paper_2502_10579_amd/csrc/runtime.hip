@@ -200,6 +200,15 @@ HostSlots& HostSlots::get() {
     return *hs;
 }
 
+uint64_t launch_depth() {
+    static const uint64_t d = [] {
+        const char* e = getenv("EVQ_LAUNCH_DEPTH");
+        const unsigned long v = e ? strtoul(e, nullptr, 10) : 3ul;
+        return (uint64_t)(v < 1 ? 1 : (v > 32 ? 32 : v));
+    }();
+    return d;
+}
+
 void wait_slot(volatile uint32_t* slot, hipStream_t s, const char* what) {
     if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) != HostSlots::kEmpty) return;
     const auto t0 = std::chrono::steady_clock::now();

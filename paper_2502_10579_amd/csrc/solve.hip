@@ -110,13 +110,18 @@ __device__ __forceinline__ void count_visits(const SolveArgs& a, uint32_t n) {
 // Flags -> frontier items of parity p, clearing the flags it reads; vertices
 // without edges in this solve's graph are dropped.
 // With near/far scheduling on (delta > 0), a vertex whose order key (its
-// value, complemented for widest paths, so smaller is better) is not below the
-// threshold keeps its flag for a later iteration.
+// value, complemented where larger is better, so smaller is better) is not
+// below the threshold keeps its flag for a later iteration.  With a heavy
+// bound, only vertices with at least that many edges in this solve's graph
+// are gated: re-expanding a vertex costs its whole row, and the rows of the
+// few high-degree vertices carry most of the repeated edge visits, while light
+// vertices keep the iterations full.
 template <int A, int MODE>
 __global__ void __launch_bounds__(kCompactBlock) k_compact_frontier(SolveArgs a, int p, int first) {
     if (nothing_pending(a.cnt, p, first)) return;
     const uint32_t thr = a.cnt->thr;
     const bool nf = a.cnt->delta != 0;
+    const uint32_t heavy = nf ? a.cnt->heavy : 0u;
     compact_flags(
         a.flags, a.V, &a.cnt->packed[p], &a.cnt->far[p], &a.cnt->fmin[p],
         [&](uint32_t v, uint32_t& items, uint32_t& edges, uint32_t& key) {
@@ -124,14 +129,15 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact_frontier(SolveArgs a,
             items = edges ? 1u : 0u;
             if (!nf || !edges) return true;
             key = order_key<A>(a.R[v]);
-            return key < thr;
+            return key < thr || edges < heavy;
         },
         [&](uint32_t v, uint32_t item, uint32_t edge, uint32_t, uint32_t) {
             a.fo[item] = edge;
             a.fd[item] = a.row_ptr[v] - edge;
             if (MODE != 0) a.fs[item] = a.row_split[v];
             a.fv[item] = v;
-        });
+        },
+        heavy ? &a.cnt->kall[p] : nullptr);
 }
 
 // One 64-edge step of a walker over the frontier's edge range: the lane's
@@ -233,12 +239,14 @@ __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int 
 }
 
 // Start of a solve: the threshold starts one step above the best key.
-__global__ void k_solve_start(FrontierCounters* c, uint32_t delta, uint32_t* R, uint8_t* flags, uint32_t source,
-                              uint32_t at_source) {
+__global__ void k_solve_start(FrontierCounters* c, uint32_t delta, uint32_t heavy, uint32_t* R, uint8_t* flags,
+                              uint32_t source, uint32_t at_source) {
     if (threadIdx.x == 0) {
         c->delta = delta;
+        c->heavy = delta ? heavy : 0u;
         c->thr = delta ? delta : 0xFFFFFFFFu;
         c->fmin[0] = c->fmin[1] = 0xFFFFFFFFu;
+        c->kall[0] = c->kall[1] = 0xFFFFFFFFu;
         if (R) {
             R[source] = at_source;
             flags[source] = 1;
@@ -322,7 +330,8 @@ template <int A, int MW, bool ST>
 uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t* R, Frontier& f, hipStream_t s) {
     SolveArgs a = make_args(g, f, R);
     fill_u32(R, g.V, Alg<A>::unreached, s);
-    EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, f.delta, R, f.flags, source, Alg<A>::at_source);
+    EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, f.delta, f.heavy, R, f.flags, source,
+               Alg<A>::at_source);
     if (W.full) return frontier_loop<A, 0, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
     return frontier_loop<A, 1, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
 }
@@ -330,7 +339,8 @@ uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t*
 template <int A, int MW, bool ST>
 uint64_t solve_cup_t(const Graph& g, const Window& W, uint32_t* R, Frontier& f, hipStream_t s) {
     SolveArgs a = make_args(g, f, R);
-    EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, f.delta, (uint32_t*)nullptr, f.flags, 0u, 0u);
+    EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, f.delta, f.heavy, (uint32_t*)nullptr, f.flags, 0u,
+               0u);
     if (g.n_partial)
         EVQ_LAUNCH("solve_seed_partial", (k_seed_partial<A, MW, ST>), grid_for(g.n_partial, kBlock, 16384), kBlock, s,
                    a, window_mask<MW>(W), g.p_src, g.p_eid, (uint32_t)g.n_partial);
@@ -367,6 +377,8 @@ __global__ void k_init_frontier(FrontierCounters* c, unsigned long long* st, int
         c->fmin[0] = c->fmin[1] = 0xFFFFFFFFu;
         c->thr = 0xFFFFFFFFu;
         c->delta = 0u;
+        c->heavy = 0u;
+        c->kall[0] = c->kall[1] = 0xFFFFFFFFu;
     }
     if ((int)threadIdx.x < n) st[threadIdx.x] = 0ull;
 }

@@ -237,11 +237,13 @@ def test_determinism_repeat(evq):
             assert np.array_equal(a, gpu_values(g, oracle.SSSP, 0, 0, 8))
 
 
-@pytest.mark.parametrize("delta", [1, 7, 60])
+@pytest.mark.parametrize("delta,heavy", [(1, 0), (7, 0), (60, 0), (3, 4), (20, 2)])
 @pytest.mark.parametrize("algo", ALGOS)
-def test_near_far_scheduling(evq, algo, delta, monkeypatch):
-    # near/far ordering of the bound solves changes the schedule, never the values
+def test_near_far_scheduling(evq, algo, delta, heavy, monkeypatch):
+    # near/far ordering of the bound solves (every vertex gated, or only those
+    # with at least `heavy` edges) changes the schedule, never the values
     monkeypatch.setenv("EVQ_DELTA", str(delta))
+    monkeypatch.setenv("EVQ_HEAVY", str(heavy))
     for seed in (1, 2):
         inst = synth.config_instance("small", seed=seed)
         trip, bits = oracle.replay(inst)
@@ -254,6 +256,25 @@ def test_near_far_scheduling(evq, algo, delta, monkeypatch):
         assert_equal_values(got, want, f"delta {delta} seed {seed}")
         assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
         assert_equal_values(sub, want[:, 2:7], f"delta {delta} seed {seed} window [2,7)")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_heavy_gating_many_blocks(evq, algo, monkeypatch):
+    # only vertices with >= 16 edges deferred, threshold following the frontier
+    inst = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=37)
+    src = synth.pick_sources(inst, 1, seed=5)[0]
+    trip, bits = oracle.replay(inst)
+    delta = {oracle.BFS: 1, oracle.VITERBI: 1 << 23}.get(algo, 20)
+    monkeypatch.setenv("EVQ_DELTA", str(delta))
+    monkeypatch.setenv("EVQ_HEAVY", "16")
+    for (b, L) in [(0, 16), (5, 7)]:
+        want = oracle.window_values(inst, algo, src, b, L, replayed=(trip, bits))
+        rc_o, ru_o = oracle.bounds(inst.num_vertices, trip, bits, algo, src, b, L)
+        with _graph(evq, inst) as g:
+            got = gpu_values(g, algo, src, b, L)
+            rc, ru = gpu_bounds(g, algo, src, b, L)
+        assert_equal_values(got, want, f"heavy gating algo {algo} [{b},{b + L})")
+        assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
 
 
 @pytest.mark.parametrize("algo", ALGOS)
