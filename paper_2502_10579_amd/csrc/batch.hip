@@ -171,7 +171,8 @@ __global__ void k_bsources(uint32_t* X, uint8_t* flags, const uint32_t* __restri
 // that lane from the intersection values (one partial edge per lane group).
 template <int A, int MW>
 __global__ void __launch_bounds__(kBlock) k_bseed(BatchArgs a, const uint32_t* __restrict__ p_src,
-                                                  const uint32_t* __restrict__ p_eid, uint32_t n_partial) {
+                                                  const uint32_t* __restrict__ p_dst, const uint32_t* __restrict__ p_w,
+                                                  const uint64_t* __restrict__ p_mask, uint32_t n_partial) {
     const uint32_t LQ = a.LQ;
     const LaneGroup lg(LQ);
     const uint32_t q = lg.q;
@@ -187,14 +188,13 @@ __global__ void __launch_bounds__(kBlock) k_bseed(BatchArgs a, const uint32_t* _
     for (uint32_t ib = gw * lg.G; ib < n_partial; ib += nw * lg.G) {
         const uint32_t i = ib + lg.g;
         bool act = false;
-        uint32_t u = 0, e = 0;
+        uint32_t u = 0;
         if (i < n_partial) {
-            e = p_eid[i];
             u = p_src[i];
             bool any = false, all = true;
 #pragma unroll
             for (int j = 0; j < MW; ++j) {
-                const uint64_t m = a.mask[(uint64_t)e * MW + j] & w[j];
+                const uint64_t m = p_mask[(uint64_t)i * MW + j] & w[j];
                 any |= m != 0;
                 all &= m == w[j];
             }
@@ -204,15 +204,15 @@ __global__ void __launch_bounds__(kBlock) k_bseed(BatchArgs a, const uint32_t* _
         bool imp = false;
         uint32_t v = 0;
         if (act) {
-            v = a.col[e];
-            const uint32_t cand = Alg<A>::extend(a.X[(uint64_t)u * LQ + q], a.wgt[e]);
+            v = p_dst[i];
+            const uint32_t cand = Alg<A>::extend(a.X[(uint64_t)u * LQ + q], p_w[i]);
             uint32_t* px = &a.X[(uint64_t)v * LQ + q];
             if (Alg<A>::better(cand, *px)) {
                 Alg<A>::improve_nr(px, cand);
                 imp = true;
             }
         }
-        // the group's lanes share e and so v; any improving lane marks it
+        // the group's lanes share the partial edge and so v; any improving lane marks it
         const uint64_t bal = __ballot(imp) & lg.gmask;
         if (bal && lane_id() == (uint32_t)__ffsll((unsigned long long)bal) - 1) mark(a.flags, v);
     }
@@ -271,7 +271,7 @@ void batch_bounds_t(const Graph& g, BatchArgs a, uint32_t* Xcap, uint32_t* Xcup,
     a.X = Xcup;
     if (g.n_partial)
         EVQ_LAUNCH("batch_seed", (k_bseed<A, MW>), grid_for((g.n_partial + 63) / 64 * a.LQ, kBlock / 64, 16384), kBlock,
-                   s, a, g.p_src, g.p_eid, (uint32_t)g.n_partial);
+                   s, a, g.p_src, g.p_dst, g.p_w, g.p_mask, (uint32_t)g.n_partial);
     batch_loop<A, true, MW>(a, tu.chunk, tu.blocks, f, s, (uint64_t)g.V + 2, &bt.iters_cup);
 }
 

@@ -263,7 +263,8 @@ __global__ void k_partition(const uint32_t* __restrict__ c_src, const uint32_t* 
                             const uint32_t* __restrict__ c_full, const uint32_t* __restrict__ fb, uint64_t E,
                             const uint32_t* __restrict__ row_ptr, uint32_t* __restrict__ col,
                             uint32_t* __restrict__ wgt, uint64_t* __restrict__ mask, uint32_t* __restrict__ p_src,
-                            uint32_t* __restrict__ p_eid) {
+                            uint32_t* __restrict__ p_dst, uint32_t* __restrict__ p_w,
+                            uint64_t* __restrict__ p_mask) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < E; i += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t u = c_src[i];
         uint32_t c0 = row_ptr[u], c1 = row_ptr[u + 1];
@@ -276,7 +277,10 @@ __global__ void k_partition(const uint32_t* __restrict__ c_src, const uint32_t* 
             pos = c0 + nf + ((uint32_t)i - c0 - fr);
             uint32_t p = (uint32_t)i - fb[i];
             p_src[p] = u;
-            p_eid[p] = pos;
+            p_dst[p] = c_dst[i];
+            p_w[p] = c_w[i];
+#pragma unroll
+            for (int q = 0; q < MW; ++q) p_mask[(uint64_t)p * MW + q] = c_mask[i * MW + q];
         }
         col[pos] = c_dst[i];
         wgt[pos] = c_w[i];
@@ -340,12 +344,14 @@ void finish_build(Graph* g, KT* sorted, uint64_t N, KeyLayout L, uint64_t* mtmp,
     EVQ_HIP(hipStreamSynchronize(s));
     const uint64_t n_full = mb.h[0];
     g->n_partial = E - n_full;
-    g->p_src = (uint32_t*)stream_alloc(g->n_partial * 4, s);
-    g->p_eid = (uint32_t*)stream_alloc(g->n_partial * 4, s);
-    g->bytes += g->n_partial * 8;
+    g->p_src = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
+    g->p_dst = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
+    g->p_w = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
+    g->p_mask = (uint64_t*)stream_alloc(g->n_partial * 8 * MW + 16, s);
+    g->bytes += g->n_partial * (12 + 8 * MW);
     if (E > 0)
         EVQ_LAUNCH("build_partition", k_partition<MW>, grid_for(E, 256), 256, s, c_src, c_dst, c_w, c_mask, c_full, fb,
-                   E, g->row_ptr, g->col, g->wgt, g->mask, g->p_src, g->p_eid);
+                   E, g->row_ptr, g->col, g->wgt, g->mask, g->p_src, g->p_dst, g->p_w, g->p_mask);
     EVQ_LAUNCH("build_row_split", k_row_split, grid_for(g->V, 256), 256, s, g->row_ptr, fb, g->V, g->row_split);
     EVQ_HIP(hipStreamSynchronize(s));
 }
@@ -475,7 +481,7 @@ void append_impl(const Graph& old, Graph* g, const uint32_t* d_ev, uint64_t n_de
 
 void free_graph(Graph* g, hipStream_t s) {
     if (!g) return;
-    void* arrays[7] = {g->row_ptr, g->row_split, g->col, g->wgt, g->mask, g->p_src, g->p_eid};
+    void* arrays[9] = {g->row_ptr, g->row_split, g->col, g->wgt, g->mask, g->p_src, g->p_dst, g->p_w, g->p_mask};
     for (void* p : arrays)
         if (p) (void)hipFreeAsync(p, s);
     for (hipEvent_t e : g->uses) (void)hipEventDestroy(e);
@@ -552,7 +558,9 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
             g->wgt = (uint32_t*)stream_alloc(4, s);
             g->mask = (uint64_t*)stream_alloc(16, s);
             g->p_src = (uint32_t*)stream_alloc(4, s);
-            g->p_eid = (uint32_t*)stream_alloc(4, s);
+            g->p_dst = (uint32_t*)stream_alloc(4, s);
+            g->p_w = (uint32_t*)stream_alloc(4, s);
+            g->p_mask = (uint64_t*)stream_alloc(16, s);
             g->bytes = ((uint64_t)V + 1) * 8;
             EVQ_HIP(hipStreamSynchronize(s));
         } else if (L.total() <= 64) {
@@ -620,7 +628,9 @@ Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
             g->wgt = (uint32_t*)stream_alloc(4, s);
             g->mask = (uint64_t*)stream_alloc(16, s);
             g->p_src = (uint32_t*)stream_alloc(4, s);
-            g->p_eid = (uint32_t*)stream_alloc(4, s);
+            g->p_dst = (uint32_t*)stream_alloc(4, s);
+            g->p_w = (uint32_t*)stream_alloc(4, s);
+            g->p_mask = (uint64_t*)stream_alloc(16, s);
             g->bytes = ((uint64_t)V + 1) * 8;
         } else if (L.total() <= 64) {
             if (g->MW == 1) append_impl<uint64_t, 1>(old, g, d_ev, b.n_del, n_ev, L, ib, s, ar);

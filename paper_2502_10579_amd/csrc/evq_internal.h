@@ -44,8 +44,12 @@ struct Graph {
     uint32_t* col = nullptr;        // E
     uint32_t* wgt = nullptr;        // E
     uint64_t* mask = nullptr;       // E * MW, bit i of the 128/64-bit word group = snapshot i
-    uint32_t* p_src = nullptr;      // n_partial: source of each partial edge (ascending edge id)
-    uint32_t* p_eid = nullptr;      // n_partial: edge id of each partial edge
+    // Edges present in some but not all K snapshots, in edge-id order, as a
+    // table of their own so that the passes over them stream it:
+    uint32_t* p_src = nullptr;      // n_partial: source
+    uint32_t* p_dst = nullptr;      // n_partial: destination
+    uint32_t* p_w = nullptr;        // n_partial: weight
+    uint64_t* p_mask = nullptr;     // n_partial * MW: presence mask
     int device = 0;
     uint64_t bytes = 0;
     double build_ms = 0.0;

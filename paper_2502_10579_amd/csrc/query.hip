@@ -335,10 +335,9 @@ __global__ void __launch_bounds__(kCompactBlock) k_relax_compact(RelaxArgs r, in
 // one LG-lane group per edge.
 template <int A, int MW, int LG, bool ST>
 __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32_t* __restrict__ p_src,
-                                                       const uint32_t* __restrict__ p_eid, uint32_t n_partial,
-                                                       const uint32_t* __restrict__ col,
-                                                       const uint32_t* __restrict__ wgt,
-                                                       const uint64_t* __restrict__ mask,
+                                                       const uint32_t* __restrict__ p_dst,
+                                                       const uint32_t* __restrict__ p_w,
+                                                       const uint64_t* __restrict__ p_mask, uint32_t n_partial,
                                                        const uint32_t* __restrict__ cid_of,
                                                        const uint32_t* __restrict__ rcap, uint32_t b, uint32_t L,
                                                        uint32_t K, uint32_t pb, uint32_t pL) {
@@ -356,20 +355,19 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
 #pragma unroll
         for (int j = 0; j < T::NLW; ++j) lanes[j] = 0;
         if (act) {
-            const uint32_t e = p_eid[q];
-            cv = cid_of[col[e]];
+            cv = cid_of[p_dst[q]];
             act = cv != kNone;
             if (act) {
                 // seeded lanes: the relaxed window (b, L); the edge must be
                 // partial in the bound window (pb, pL), which contains it
                 uint64_t pl[2];
-                edge_lanes<MW, 2>(mask, e, false, pb, pL, K, pl);
-                edge_lanes<MW, T::NLW>(mask, e, false, b, L, K, lanes);
+                edge_lanes<MW, 2>(p_mask, q, false, pb, pL, K, pl);
+                edge_lanes<MW, T::NLW>(p_mask, q, false, b, L, K, lanes);
                 bool any = false;
 #pragma unroll
                 for (int j = 0; j < T::NLW; ++j) any |= lanes[j] != 0;
                 act = any && lanes_partial<2>(pl, pL);
-                if (act) cand = Alg<A>::extend(rcap[p_src[q]], wgt[e]);
+                if (act) cand = Alg<A>::extend(rcap[p_src[q]], p_w[q]);
             }
         }
         uint64_t bal = __ballot(act);
@@ -845,7 +843,7 @@ void relax_phase(const Graph& g, const Window& W, const Window& PW, const uint32
             const uint32_t waves = (uint32_t)((g.n_partial + 63) / 64);
 #define EVQ_SEED(MW_)                                                                                             \
     EVQ_LAUNCH("relax_seed", (k_relax_seed<A, MW_, LG, ST>), grid_for(waves, kBlock / 64, 8192), kBlock, s, ra,   \
-               g.p_src, g.p_eid, (uint32_t)g.n_partial, g.col, g.wgt, g.mask, red.cid_of, rcap, W.b, W.L, g.K, PW.b, PW.L)
+               g.p_src, g.p_dst, g.p_w, g.p_mask, (uint32_t)g.n_partial, red.cid_of, rcap, W.b, W.L, g.K, PW.b, PW.L)
             if (g.MW == 1) EVQ_SEED(1);
             else EVQ_SEED(2);
 #undef EVQ_SEED

@@ -258,14 +258,15 @@ __global__ void k_solve_start(FrontierCounters* c, uint32_t delta, uint32_t heav
 // snapshots of the window, from the values in R (the intersection result).
 template <int A, int MW, bool ST>
 __global__ void __launch_bounds__(kBlock) k_seed_partial(SolveArgs a, Mask<MW> W, const uint32_t* __restrict__ p_src,
-                                                         const uint32_t* __restrict__ p_eid, uint32_t n_partial) {
+                                                         const uint32_t* __restrict__ p_dst,
+                                                         const uint32_t* __restrict__ p_w,
+                                                         const uint64_t* __restrict__ p_mask, uint32_t n_partial) {
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t base = blockIdx.x * kBlock; base < n_partial; base += stride) {
         const uint32_t q = base + threadIdx.x;
         bool act = false;
         if (q < n_partial) {
-            const uint32_t e = p_eid[q];
-            Mask<MW> m = load_mask<MW>(a.mask, e);
+            Mask<MW> m = load_mask<MW>(p_mask, q);
             bool any = false, all = true;
 #pragma unroll
             for (int j = 0; j < MW; ++j) {
@@ -274,8 +275,8 @@ __global__ void __launch_bounds__(kBlock) k_seed_partial(SolveArgs a, Mask<MW> W
             }
             act = any && !all;
             if (act) {
-                const uint32_t v = a.col[e];
-                const uint32_t cand = Alg<A>::extend(a.R[p_src[q]], a.wgt[e]);
+                const uint32_t v = p_dst[q];
+                const uint32_t cand = Alg<A>::extend(a.R[p_src[q]], p_w[q]);
                 if (Alg<A>::better(cand, a.R[v])) {
                     Alg<A>::improve_nr(&a.R[v], cand);
                     mark(a.flags, v);
@@ -343,7 +344,7 @@ uint64_t solve_cup_t(const Graph& g, const Window& W, uint32_t* R, Frontier& f, 
                0u);
     if (g.n_partial)
         EVQ_LAUNCH("solve_seed_partial", (k_seed_partial<A, MW, ST>), grid_for(g.n_partial, kBlock, 16384), kBlock, s,
-                   a, window_mask<MW>(W), g.p_src, g.p_eid, (uint32_t)g.n_partial);
+                   a, window_mask<MW>(W), g.p_src, g.p_dst, g.p_w, g.p_mask, (uint32_t)g.n_partial);
     return frontier_loop<A, 2, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
 }
 
