@@ -111,17 +111,22 @@ __device__ __forceinline__ void wave_lds_sync() {
 // *far and its order key enters the minimum *fmin.  emit(id, item, edge,
 // items, edges) writes an id's work.  Ids appear in ascending order within a
 // block.  With kall non-null, size_of gives every id with edges its order key
-// and the smallest of them enters the minimum *kall.
+// and the smallest of them enters the minimum *kall.  post() runs on every
+// thread of the block after each group of ids has been emitted (and the block
+// synchronised), before the next group is compacted.
+struct NoPost {
+    __device__ void operator()() const {}
+};
 constexpr int kCompactBlock = 512;
 constexpr int kCompactWaves = kCompactBlock / 64;
 constexpr int kIdsPerWave = 512;
 constexpr int kCompactIds = kCompactWaves * kIdsPerWave;
 constexpr int kIdSteps = kIdsPerWave / 64;
 
-template <typename SizeFn, typename EmitFn>
+template <typename SizeFn, typename EmitFn, typename PostFn = NoPost>
 __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint32_t n, unsigned long long* cnt,
                                               uint32_t* far, uint32_t* fmin, SizeFn size_of, EmitFn emit,
-                                              uint32_t* kall = nullptr) {
+                                              uint32_t* kall = nullptr, PostFn post = PostFn()) {
     __shared__ uint32_t ids[kCompactWaves][kIdsPerWave];
     __shared__ uint32_t keep[kCompactWaves][64];
     __shared__ uint32_t wtot[kCompactWaves][5];
@@ -242,6 +247,7 @@ __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint3
                 if (ni[s]) emit(id[s], bi + pi[s], be + pe[s], ni[s], ne[s]);
         }
         __syncthreads();
+        post();
     }
 }
 

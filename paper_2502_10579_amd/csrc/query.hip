@@ -314,9 +314,16 @@ __device__ __forceinline__ void add_stat(unsigned long long* p, uint32_t v) {
 }
 
 // Bitmap of improved compact ids -> relaxation tasks of parity p, one task per
-// kRelaxChunk reduced-subgraph edges of each improved vertex.
+// kRelaxChunk reduced-subgraph edges of each improved vertex.  A vertex with
+// few tasks has them written by the lane that holds it; the tasks of larger
+// ones (a hub can have 10^5) are listed in LDS and written by the whole block.
+constexpr uint32_t kLaneTasks = 4;
+constexpr uint32_t kBigCap = 256;
 __global__ void __launch_bounds__(kCompactBlock) k_relax_compact(RelaxArgs r, int p, int first) {
     if (nothing_pending(r.cnt, p, first)) return;
+    __shared__ uint32_t big_n, big_c[kBigCap], big_item[kBigCap], big_items[kBigCap];
+    if (threadIdx.x == 0) big_n = 0;
+    __syncthreads();
     compact_flags(
         r.flags, r.nU, &r.cnt->packed[p], &r.cnt->far[p], &r.cnt->fmin[p],
         [&](uint32_t c, uint32_t& items, uint32_t& edges, uint32_t&) {
@@ -325,7 +332,26 @@ __global__ void __launch_bounds__(kCompactBlock) k_relax_compact(RelaxArgs r, in
             return true;
         },
         [&](uint32_t c, uint32_t item, uint32_t, uint32_t items, uint32_t) {
-            for (uint32_t q = 0; q < items; ++q) r.tasks[item + q] = ((uint64_t)q << 32) | c;
+            uint32_t k = kBigCap;
+            if (items > kLaneTasks) k = atomicAdd(&big_n, 1u);
+            if (k < kBigCap) {
+                big_c[k] = c;
+                big_item[k] = item;
+                big_items[k] = items;
+            } else {
+                for (uint32_t q = 0; q < items; ++q) r.tasks[item + q] = ((uint64_t)q << 32) | c;
+            }
+        },
+        nullptr,
+        [&]() {
+            const uint32_t nb = big_n < kBigCap ? big_n : kBigCap;
+            for (uint32_t k = 0; k < nb; ++k) {
+                const uint32_t c = big_c[k], item = big_item[k], items = big_items[k];
+                for (uint32_t q = threadIdx.x; q < items; q += kCompactBlock)
+                    r.tasks[item + q] = ((uint64_t)q << 32) | c;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) big_n = 0;
         });
 }
 
