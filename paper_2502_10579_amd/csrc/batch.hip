@@ -59,15 +59,12 @@ struct LaneGroup {
     __device__ bool any(bool x) const { return (__ballot(x) & gmask) != 0; }
 };
 
-// Frontier vertices -> tasks of `chunk` edges of their union rows.  The tasks
-// of a vertex with many (a hub's row) are written by the whole block.
-constexpr uint32_t kLaneTasks = 4;
-constexpr uint32_t kBigCap = 256;
+// Frontier vertices -> tasks of `chunk` edges of their union rows (written
+// through a block task list).
 __global__ void __launch_bounds__(kCompactBlock) k_bcompact(BatchArgs a, int p, int first) {
     if (nothing_pending(a.cnt, p, first)) return;
-    __shared__ uint32_t big_n, big_v[kBigCap], big_item[kBigCap], big_items[kBigCap];
-    if (threadIdx.x == 0) big_n = 0;
-    __syncthreads();
+    __shared__ TaskList tl;
+    task_list_init(tl);
     compact_flags(
         a.flags, a.V, &a.cnt->packed[p], &a.cnt->far[p], &a.cnt->fmin[p],
         [&](uint32_t v, uint32_t& items, uint32_t& edges, uint32_t&) {
@@ -76,27 +73,10 @@ __global__ void __launch_bounds__(kCompactBlock) k_bcompact(BatchArgs a, int p, 
             return true;
         },
         [&](uint32_t v, uint32_t item, uint32_t, uint32_t items, uint32_t) {
-            uint32_t k = kBigCap;
-            if (items > kLaneTasks) k = atomicAdd(&big_n, 1u);
-            if (k < kBigCap) {
-                big_v[k] = v;
-                big_item[k] = item;
-                big_items[k] = items;
-            } else {
-                for (uint32_t q = 0; q < items; ++q) a.tasks[item + q] = ((uint64_t)q << 32) | v;
-            }
+            if (items == 1) a.tasks[item] = v;
+            else task_list_add(tl, a.tasks, v, item, items);
         },
-        nullptr,
-        [&]() {
-            const uint32_t nb = big_n < kBigCap ? big_n : kBigCap;
-            for (uint32_t k = 0; k < nb; ++k) {
-                const uint32_t v = big_v[k], item = big_item[k], items = big_items[k];
-                for (uint32_t q = threadIdx.x; q < items; q += kCompactBlock)
-                    a.tasks[item + q] = ((uint64_t)q << 32) | v;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) big_n = 0;
-        });
+        nullptr, [&]() { task_list_flush(tl, a.tasks); });
 }
 
 template <int MW>

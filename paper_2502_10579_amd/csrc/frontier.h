@@ -251,6 +251,77 @@ __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint3
     }
 }
 
+// Task lists of a compaction whose ids expand to several tasks each (task q
+// of id c is the 64-bit word (q << 32) | c).  An id with one task has it
+// written by the lane that holds it; an id with more is listed in LDS, and
+// after each group of ids (post() of compact_flags) the whole block writes the
+// listed tasks, each thread finding the id of its task by a binary search over
+// the list's running task counts, so a hub's 10^5 tasks and many small ids
+// are written at the same rate.  A full list falls back to the holding lane.
+constexpr uint32_t kTaskListCap = 2048;
+struct TaskList {
+    uint32_t n;
+    uint32_t id[kTaskListCap], first[kTaskListCap], cnt[kTaskListCap], pre[kTaskListCap];
+    uint32_t wsum[kCompactWaves];
+};
+
+__device__ __forceinline__ void task_list_init(TaskList& tl) {
+    if (threadIdx.x == 0) tl.n = 0;
+    __syncthreads();
+}
+
+__device__ __forceinline__ void task_list_add(TaskList& tl, uint64_t* __restrict__ tasks, uint32_t c, uint32_t first,
+                                              uint32_t items) {
+    uint32_t k = kTaskListCap;
+    if (items > 1) k = atomicAdd(&tl.n, 1u);
+    if (k < kTaskListCap) {
+        tl.id[k] = c;
+        tl.first[k] = first;
+        tl.cnt[k] = items;
+    } else {
+        for (uint32_t q = 0; q < items; ++q) tasks[first + q] = ((uint64_t)q << 32) | c;
+    }
+}
+
+// Every thread of the block (kCompactBlock of them) calls it.
+__device__ __forceinline__ void task_list_flush(TaskList& tl, uint64_t* __restrict__ tasks) {
+    constexpr uint32_t kPer = kTaskListCap / kCompactBlock;
+    const uint32_t nb = tl.n < kTaskListCap ? tl.n : kTaskListCap;
+    if (nb) {
+        const uint32_t lane = lane_id(), wave = threadIdx.x >> 6, k0 = threadIdx.x * kPer;
+        uint32_t s = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) s += k0 + j < nb ? tl.cnt[k0 + j] : 0u;
+        const uint32_t incl = wave_incl_scan(s);
+        if (lane == 63) tl.wsum[wave] = incl;
+        __syncthreads();
+        uint32_t off = incl - s, tot = 0;
+        for (uint32_t w = 0; w < kCompactWaves; ++w) {
+            off += w < wave ? tl.wsum[w] : 0u;
+            tot += tl.wsum[w];
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j)
+            if (k0 + j < nb) {
+                tl.pre[k0 + j] = off;
+                off += tl.cnt[k0 + j];
+            }
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < tot; t += kCompactBlock) {
+            uint32_t lo = 0, hi = nb;  // largest k with pre[k] <= t
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (tl.pre[mid] <= t) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t q = t - tl.pre[lo];
+            tasks[tl.first[lo] + q] = ((uint64_t)q << 32) | tl.id[lo];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) tl.n = 0;
+}
+
 // Host side: launch-ahead driver of a frontier loop.
 class HostSlots {
   public:
@@ -283,6 +354,8 @@ void wait_slot(volatile uint32_t* slot, hipStream_t s, const char* what);
 
 // Iterations kept in flight by drive_loop: EVQ_LAUNCH_DEPTH (1..32), default 3.
 uint64_t launch_depth();
+// EVQ_TRACE_LOOPS=1: drive_loop prints each iteration's published count to stderr.
+bool trace_loops();
 
 template <typename IssueFn>
 uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_iters, const char* what,
@@ -309,6 +382,7 @@ uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_it
         }
         volatile uint32_t* slot = hs.host() + ((base + consumed) % HostSlots::kSlots);
         wait_slot(slot, s, what);
+        if (trace_loops()) fprintf(stderr, "[evq] %s iteration %llu: %u\n", what, (unsigned long long)consumed, *slot);
         if (*slot == 0) break;
         if (items) *items += *slot;
         if (++consumed > max_iters) fail(EVQ_ENOCONV, std::string(what) + " exceeded its iteration cap");

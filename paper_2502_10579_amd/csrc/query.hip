@@ -26,7 +26,19 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr uint32_t kRowChunk = 1024;   // union-row edges per compaction task
-constexpr uint32_t kRelaxChunk = 8;    // reduced-subgraph edges per relaxation task
+#ifndef EVQ_RELAX_CHUNK
+#define EVQ_RELAX_CHUNK 8
+#endif
+#ifndef EVQ_RELAX_BLOCKS
+#define EVQ_RELAX_BLOCKS 4096
+#endif
+constexpr uint32_t kRelaxChunk = EVQ_RELAX_CHUNK;  // reduced-subgraph edges per relaxation task
+// Largest task count (reduced edges / kRelaxChunk + vertices) whose tasks the
+// relax compaction writes itself: EVQ_DIRECT_TASKS overrides (read per query).
+uint64_t direct_tasks_limit() {
+    const char* e = getenv("EVQ_DIRECT_TASKS");
+    return e ? strtoull(e, nullptr, 10) : (1ull << 18);
+}
 
 
 template <int NLW>
@@ -292,7 +304,13 @@ struct RelaxArgs {
     const void* recs;
     uint32_t* X;
     uint8_t* flags;    // next-frontier flags over compact ids
-    uint64_t* tasks;   // (chunk << 32 | compact id), rewritten by each compaction
+    // Frontier items written by each compaction, one per improved vertex with
+    // edges: its first task in the iteration's task range [0, T) (a task is
+    // kRelaxChunk consecutive reduced-subgraph edges of one vertex) and its
+    // compact id; then each task as (chunk << 32 | compact id).
+    uint32_t* fo;
+    uint32_t* fv;
+    uint64_t* tasks;
     FrontierCounters* cnt;
     unsigned long long* stats;  // [1] edge visits, [2] lane relaxations, [3] seed edges
     uint32_t nU;
@@ -313,46 +331,83 @@ __device__ __forceinline__ void add_stat(unsigned long long* p, uint32_t v) {
     if (lane_id() == 0 && s) atomicAdd(p, (unsigned long long)s);
 }
 
-// Bitmap of improved compact ids -> relaxation tasks of parity p, one task per
-// kRelaxChunk reduced-subgraph edges of each improved vertex.  A vertex with
-// few tasks has them written by the lane that holds it; the tasks of larger
-// ones (a hub can have 10^5) are listed in LDS and written by the whole block.
-constexpr uint32_t kLaneTasks = 4;
-constexpr uint32_t kBigCap = 256;
+// Bitmap of improved compact ids -> frontier items of parity p: per vertex its
+// running task offset (the packed reservation counts vertices and tasks) and
+// its compact id.  DIRECT: the compaction also writes the tasks itself (through
+// a block task list), which saves k_relax_tasks' launch when the reduced
+// subgraph is small; with a large one the block that holds a hub would write
+// most of an iteration's tasks alone, so k_relax_tasks writes them instead.
+template <bool DIRECT>
 __global__ void __launch_bounds__(kCompactBlock) k_relax_compact(RelaxArgs r, int p, int first) {
     if (nothing_pending(r.cnt, p, first)) return;
-    __shared__ uint32_t big_n, big_c[kBigCap], big_item[kBigCap], big_items[kBigCap];
-    if (threadIdx.x == 0) big_n = 0;
-    __syncthreads();
+    __shared__ TaskList tl;
+    if (DIRECT) task_list_init(tl);
     compact_flags(
         r.flags, r.nU, &r.cnt->packed[p], &r.cnt->far[p], &r.cnt->fmin[p],
-        [&](uint32_t c, uint32_t& items, uint32_t& edges, uint32_t&) {
-            edges = r.kc[c];
-            items = (edges + kRelaxChunk - 1) / kRelaxChunk;
+        [&](uint32_t c, uint32_t& items, uint32_t& tasks, uint32_t&) {
+            tasks = (r.kc[c] + kRelaxChunk - 1) / kRelaxChunk;
+            items = tasks ? 1u : 0u;
             return true;
         },
-        [&](uint32_t c, uint32_t item, uint32_t, uint32_t items, uint32_t) {
-            uint32_t k = kBigCap;
-            if (items > kLaneTasks) k = atomicAdd(&big_n, 1u);
-            if (k < kBigCap) {
-                big_c[k] = c;
-                big_item[k] = item;
-                big_items[k] = items;
+        [&](uint32_t c, uint32_t item, uint32_t task, uint32_t, uint32_t tasks) {
+            if (!DIRECT) {
+                r.fo[item] = task;
+                r.fv[item] = c;
+            } else if (tasks == 1) {
+                r.tasks[task] = c;
             } else {
-                for (uint32_t q = 0; q < items; ++q) r.tasks[item + q] = ((uint64_t)q << 32) | c;
+                task_list_add(tl, r.tasks, c, task, tasks);
             }
         },
-        nullptr,
-        [&]() {
-            const uint32_t nb = big_n < kBigCap ? big_n : kBigCap;
-            for (uint32_t k = 0; k < nb; ++k) {
-                const uint32_t c = big_c[k], item = big_item[k], items = big_items[k];
-                for (uint32_t q = threadIdx.x; q < items; q += kCompactBlock)
-                    r.tasks[item + q] = ((uint64_t)q << 32) | c;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) big_n = 0;
+        nullptr, [&]() {
+            if (DIRECT) task_list_flush(tl, r.tasks);
         });
+}
+
+// Frontier items of parity p -> the iteration's tasks.  The task range [0, T)
+// is cut into equal contiguous slices, one per wave, so that a hub's many
+// tasks are written at the rate of the whole grid: a wave finds the item of
+// its first task with a 64-ary search over fo[], then writes 64 consecutive
+// tasks per step, each lane locating its task's item among 64 offsets held in
+// registers.
+__global__ void __launch_bounds__(kBlock) k_relax_tasks(RelaxArgs r, int p) {
+    const unsigned long long cx = r.cnt->packed[p];
+    const uint32_t n = items_of(cx), NT = edges_of(cx);
+    if (NT == 0) return;
+    const uint32_t lane = lane_id();
+    const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
+    const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
+    uint64_t Rw = (NT + nw - 1) / nw;
+    Rw = (Rw + 63) & ~63ull;
+    const uint64_t b0 = gw * Rw;
+    if (b0 >= NT) return;
+    uint32_t base = (uint32_t)b0;
+    const uint32_t end = (uint32_t)(b0 + Rw < NT ? b0 + Rw : NT);
+    uint32_t cur = wave_search(r.fo, n, base);
+    while (base < end) {
+        const uint32_t idx = cur + lane;
+        uint32_t off = 0xFFFFFFFFu, iv = 0;
+        if (idx < n) {
+            off = r.fo[idx];
+            iv = r.fv[idx];
+        }
+        const uint32_t t = base + lane;
+        int o = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const uint32_t q = __shfl(off, o + step, 64);
+            if (q <= t) o += step;
+        }
+        const uint32_t first = __shfl(off, o, 64), c = __shfl(iv, o, 64);
+        if (t < end) r.tasks[t] = ((uint64_t)(t - first) << 32) | c;
+        // the next step starts at the item that owns base + 64
+        const uint32_t nb = base + 64;
+        const uint32_t have = (uint32_t)__popcll(__ballot(off <= nb));
+        uint32_t adv = have - 1;
+        if (have == 64 && cur + 64 < n && r.fo[cur + 64] <= nb) adv = 64;
+        cur += adv;
+        base = nb;
+    }
 }
 
 // Seeding pass (the parfor over the reduced addition batches in Algorithm 2):
@@ -433,7 +488,7 @@ template <int A, int LG, bool ST>
 __global__ void __launch_bounds__(kBlock) k_relax(RelaxArgs r, int p, uint32_t* slot) {
     using T = Lanes<LG>;
     const unsigned long long cx = expand_prologue(r.cnt, p, slot);
-    const uint32_t n = items_of(cx);
+    const uint32_t n = edges_of(cx);  // tasks (the items are their vertices)
     if (n == 0) return;
     const uint64_t* __restrict__ tasks = r.tasks;
     const Rec<T::NLW>* __restrict__ recs = static_cast<const Rec<T::NLW>*>(r.recs);
@@ -854,6 +909,8 @@ void relax_phase(const Graph& g, const Window& W, const Window& PW, const uint32
     ra.recs = red.recs;
     ra.X = X;
     ra.flags = f.flags;
+    ra.fo = f.fo;  // V entries each, free once the bound solves are done (nU <= V)
+    ra.fv = f.fv;
     ra.tasks = ws.buf<uint64_t>(Workspace::kTasks, (uint64_t)red.nU + red.TU / kRelaxChunk + 64);
     ra.cnt = f.cnt;
     ra.stats = f.stats;
@@ -876,9 +933,16 @@ void relax_phase(const Graph& g, const Window& W, const Window& PW, const uint32
         }
     }
     const uint32_t cblocks = grid_for(red.nU, kCompactIds, 4096);
-    const uint32_t rblocks = grid_for(((uint64_t)red.nU + red.TU / kRelaxChunk + T::G - 1) / T::G, kBlock / 64, 4096);
+    const bool direct = red.TU / kRelaxChunk + red.nU <= direct_tasks_limit();
+    const uint32_t tblocks = grid_for(((uint64_t)red.nU + red.TU / kRelaxChunk + 63) / 64, kBlock / 64, 2048);
+    const uint32_t rblocks = grid_for(((uint64_t)red.nU + red.TU / kRelaxChunk + T::G - 1) / T::G, kBlock / 64, EVQ_RELAX_BLOCKS);
     auto issue = [&](uint64_t, int p, bool first, uint32_t* slot) {
-        EVQ_LAUNCH("relax_compact", k_relax_compact, cblocks, kCompactBlock, s, ra, p, first ? 1 : 0);
+        if (direct) {
+            EVQ_LAUNCH("relax_compact", k_relax_compact<true>, cblocks, kCompactBlock, s, ra, p, first ? 1 : 0);
+        } else {
+            EVQ_LAUNCH("relax_compact", k_relax_compact<false>, cblocks, kCompactBlock, s, ra, p, first ? 1 : 0);
+            EVQ_LAUNCH("relax_tasks", k_relax_tasks, tblocks, kBlock, s, ra, p);
+        }
         EVQ_LAUNCH("relax", (k_relax<A, LG, ST>), rblocks, kBlock, s, ra, p, slot);
     };
     qo.st.iters_relax = drive_loop(issue, f.p, s, (uint64_t)g.V + 2, "snapshot relaxation");

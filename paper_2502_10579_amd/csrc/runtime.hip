@@ -209,6 +209,14 @@ uint64_t launch_depth() {
     return d;
 }
 
+bool trace_loops() {
+    static const bool t = [] {
+        const char* e = getenv("EVQ_TRACE_LOOPS");
+        return e && *e && *e != '0';
+    }();
+    return t;
+}
+
 void wait_slot(volatile uint32_t* slot, hipStream_t s, const char* what) {
     if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) != HostSlots::kEmpty) return;
     const auto t0 = std::chrono::steady_clock::now();

@@ -277,6 +277,27 @@ def test_heavy_gating_many_blocks(evq, algo, monkeypatch):
         assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
 
 
+@pytest.mark.parametrize("direct", ["0", "1000000000"])
+@pytest.mark.parametrize("algo", ALGOS)
+def test_relax_task_paths(evq, algo, direct, monkeypatch):
+    # relaxation tasks written by a kernel of their own (limit 0) or by the
+    # compaction (a limit above any task count): same values
+    monkeypatch.setenv("EVQ_DIRECT_TASKS", direct)
+    inst = synth.rmat_instance(15, 200000, 16, 2000, 2000, wmin=1, wmax=100, seed=41)
+    src = synth.pick_sources(inst, 2, seed=9)
+    trip, bits = oracle.replay(inst)
+    with _graph(evq, inst) as g:
+        for s in src:
+            for (b, L) in [(0, 16), (4, 9)]:
+                want = oracle.window_values(inst, algo, s, b, L, replayed=(trip, bits))
+                assert_equal_values(gpu_values(g, algo, s, b, L), want, f"tasks limit {direct} algo {algo} [{b},{b + L})")
+                assert_equal_values(gpu_values(g, algo, s, b, L, plain=True), want, f"plain, limit {direct}")
+    small = synth.config_instance("small", seed=3)
+    with _graph(evq, small) as g:
+        want = oracle.window_values(small, algo, 0, 0, small.K)
+        assert_equal_values(gpu_values(g, algo, 0, 0, small.K), want, f"small, limit {direct}")
+
+
 @pytest.mark.parametrize("algo", ALGOS)
 def test_query_many_blocks_method_plain_sequential(evq, algo):
     # enough vertices that compact ids are assigned by many blocks in any order
