@@ -21,6 +21,7 @@
 #include <thread>
 
 #include "batch.h"
+#include "tasks.h"
 
 namespace evq {
 
@@ -39,6 +40,8 @@ struct BatchArgs {
     const uint64_t* win;  // [LQ][2] window bits per lane (0 for an unused lane)
     uint8_t* flags;
     uint64_t* tasks;      // (chunk << 32 | vertex)
+    uint32_t* fo;         // frontier items: first task of each vertex in the iteration's task range
+    uint32_t* fv;         //   and the vertex
     FrontierCounters* cnt;
     uint32_t V;
     uint32_t chunk;       // edges per task
@@ -59,24 +62,27 @@ struct LaneGroup {
     __device__ bool any(bool x) const { return (__ballot(x) & gmask) != 0; }
 };
 
-// Frontier vertices -> tasks of `chunk` edges of their union rows (written
-// through a block task list).
+// Frontier vertices -> items (first task, vertex), a task being `chunk` edges
+// of a union row; the packed reservation counts vertices and tasks.  Union
+// rows of hubs have 10^4-10^5 tasks, so k_btasks writes them (write_tasks).
 __global__ void __launch_bounds__(kCompactBlock) k_bcompact(BatchArgs a, int p, int first) {
     if (nothing_pending(a.cnt, p, first)) return;
-    __shared__ TaskList tl;
-    task_list_init(tl);
     compact_flags(
         a.flags, a.V, &a.cnt->packed[p], &a.cnt->far[p], &a.cnt->fmin[p],
-        [&](uint32_t v, uint32_t& items, uint32_t& edges, uint32_t&) {
-            edges = a.row_ptr[v + 1] - a.row_ptr[v];
-            items = (edges + a.chunk - 1) / a.chunk;
+        [&](uint32_t v, uint32_t& items, uint32_t& tasks, uint32_t&) {
+            tasks = (a.row_ptr[v + 1] - a.row_ptr[v] + a.chunk - 1) / a.chunk;
+            items = tasks ? 1u : 0u;
             return true;
         },
-        [&](uint32_t v, uint32_t item, uint32_t, uint32_t items, uint32_t) {
-            if (items == 1) a.tasks[item] = v;
-            else task_list_add(tl, a.tasks, v, item, items);
-        },
-        nullptr, [&]() { task_list_flush(tl, a.tasks); });
+        [&](uint32_t v, uint32_t item, uint32_t task, uint32_t, uint32_t) {
+            a.fo[item] = task;
+            a.fv[item] = v;
+        });
+}
+
+__global__ void __launch_bounds__(256) k_btasks(BatchArgs a, int p) {
+    const unsigned long long cx = a.cnt->packed[p];
+    write_tasks(a.fo, a.fv, items_of(cx), edges_of(cx), a.tasks);
 }
 
 template <int MW>
@@ -99,7 +105,7 @@ __device__ __forceinline__ bool lane_has(const uint64_t* __restrict__ mask, uint
 template <int A, bool CUP, int MW, int CH>
 __global__ void __launch_bounds__(kBlock) k_bexpand(BatchArgs a, int p, uint32_t* slot) {
     const unsigned long long cx = expand_prologue(a.cnt, p, slot);
-    const uint32_t n = items_of(cx);
+    const uint32_t n = edges_of(cx);  // tasks (the items are their vertices)
     if (n == 0) return;
     const uint32_t LQ = a.LQ;
     const LaneGroup lg(LQ);
@@ -251,9 +257,11 @@ template <int A, bool CUP, int MW>
 void batch_loop(BatchArgs a, uint32_t chunk, uint32_t blocks, Frontier& f, hipStream_t s, uint64_t max_iters,
                 uint64_t* iters) {
     const uint32_t cblocks = grid_for(a.V, kCompactIds, 4096);
+    const uint32_t tblocks = 2048;
     a.chunk = chunk;
     auto issue = [&](uint64_t, int p, bool first, uint32_t* slot) {
         EVQ_LAUNCH("batch_compact", k_bcompact, cblocks, kCompactBlock, s, a, p, first ? 1 : 0);
+        EVQ_LAUNCH("batch_tasks", k_btasks, tblocks, 256, s, a, p);
         switch (chunk) {
         case 4: EVQ_LAUNCH("batch_expand", (k_bexpand<A, CUP, MW, 4>), blocks, kBlock, s, a, p, slot); break;
         case 16: EVQ_LAUNCH("batch_expand", (k_bexpand<A, CUP, MW, 16>), blocks, kBlock, s, a, p, slot); break;
@@ -336,6 +344,8 @@ void batch_bounds(const Graph& g, uint32_t algo, const Window* wins, const uint3
     a.win = d_win;
     a.flags = f.flags;
     a.tasks = ws.buf<uint64_t>(Workspace::kTasks, (uint64_t)g.V + g.E / 4 + 64);
+    a.fo = f.fo;
+    a.fv = f.fv;
     a.cnt = f.cnt;
     a.V = g.V;
     a.chunk = tu.chunk;

@@ -19,6 +19,7 @@
 #include <chrono>
 
 #include "bounds.h"
+#include "tasks.h"
 
 namespace evq {
 
@@ -364,50 +365,10 @@ __global__ void __launch_bounds__(kCompactBlock) k_relax_compact(RelaxArgs r, in
         });
 }
 
-// Frontier items of parity p -> the iteration's tasks.  The task range [0, T)
-// is cut into equal contiguous slices, one per wave, so that a hub's many
-// tasks are written at the rate of the whole grid: a wave finds the item of
-// its first task with a 64-ary search over fo[], then writes 64 consecutive
-// tasks per step, each lane locating its task's item among 64 offsets held in
-// registers.
+// Frontier items of parity p -> the iteration's tasks (write_tasks).
 __global__ void __launch_bounds__(kBlock) k_relax_tasks(RelaxArgs r, int p) {
     const unsigned long long cx = r.cnt->packed[p];
-    const uint32_t n = items_of(cx), NT = edges_of(cx);
-    if (NT == 0) return;
-    const uint32_t lane = lane_id();
-    const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
-    const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
-    uint64_t Rw = (NT + nw - 1) / nw;
-    Rw = (Rw + 63) & ~63ull;
-    const uint64_t b0 = gw * Rw;
-    if (b0 >= NT) return;
-    uint32_t base = (uint32_t)b0;
-    const uint32_t end = (uint32_t)(b0 + Rw < NT ? b0 + Rw : NT);
-    uint32_t cur = wave_search(r.fo, n, base);
-    while (base < end) {
-        const uint32_t idx = cur + lane;
-        uint32_t off = 0xFFFFFFFFu, iv = 0;
-        if (idx < n) {
-            off = r.fo[idx];
-            iv = r.fv[idx];
-        }
-        const uint32_t t = base + lane;
-        int o = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            const uint32_t q = __shfl(off, o + step, 64);
-            if (q <= t) o += step;
-        }
-        const uint32_t first = __shfl(off, o, 64), c = __shfl(iv, o, 64);
-        if (t < end) r.tasks[t] = ((uint64_t)(t - first) << 32) | c;
-        // the next step starts at the item that owns base + 64
-        const uint32_t nb = base + 64;
-        const uint32_t have = (uint32_t)__popcll(__ballot(off <= nb));
-        uint32_t adv = have - 1;
-        if (have == 64 && cur + 64 < n && r.fo[cur + 64] <= nb) adv = 64;
-        cur += adv;
-        base = nb;
-    }
+    write_tasks(r.fo, r.fv, items_of(cx), edges_of(cx), r.tasks);
 }
 
 // Seeding pass (the parfor over the reduced addition batches in Algorithm 2):
