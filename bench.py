@@ -542,7 +542,7 @@ def main():
     # window; on the headline workload the relaxation is a few small launches.
     relax_heavy = None
     if not args.no_roofline and not args.no_heavy and args.config == "mid":
-        hv = synth.rmat_instance(seed=args.seed, **dict(synth.CONFIGS["mid"], n_del=100000, n_add=100000))
+        hv = synth.config_instance("churn", seed=args.seed)
         gh = evq.Graph.from_instance(hv)
         hsrc = synth.pick_sources(hv, 1, seed=args.seed)[0]
         hout = torch.empty_like(out)

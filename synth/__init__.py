@@ -163,6 +163,8 @@ CONFIGS = {
     "small": dict(scale=12, n_samples=32768, K=8, n_del=33, n_add=33, wmin=1, wmax=100),
     # R-MAT scale 20, 16M samples, K = 64, 10k + 10k
     "mid": dict(scale=20, n_samples=16777216, K=64, n_del=10000, n_add=10000, wmin=1, wmax=100),
+    # the mid graph with heavy churn: 100k + 100k per snapshot (about half the vertices unstable)
+    "churn": dict(scale=20, n_samples=16777216, K=64, n_del=100000, n_add=100000, wmin=1, wmax=100),
     # R-MAT scale 23, 134M samples, K = 100, 50k + 50k, weights [1, 1000]
     "large": dict(scale=23, n_samples=134217728, K=100, n_del=50000, n_add=50000, wmin=1, wmax=1000),
     # R-MAT scale 22, 67M samples, K = 128, 20k + 20k
