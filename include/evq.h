@@ -27,6 +27,19 @@
  *     ownership.  Device pointers belong to the caller unless stated.
  *   - Edge weights are uint32 >= 1; vertex ids are uint32 < num_vertices.
  *
+ * Environment switches (none changes a value, only how the work is
+ * scheduled; defaults are the measured best):
+ *   EVQ_SPLIT_FRAC, EVQ_SPLIT_MIN   sub-window splitting (see evq_query)
+ *   EVQ_DELTA[_ALGO], EVQ_HEAVY[_ALGO]  near/far scheduling of the bound
+ *                                   solves (see evq_query)
+ *   EVQ_BATCH_LANES/CHUNK/BLOCKS/GROUP/WORKERS  batched execution choices
+ *                                   (see evq_batch_config)
+ *   EVQ_DIRECT_TASKS=n   reduced subgraphs of at most n relaxation tasks
+ *                        have them written by the frontier compaction, larger
+ *                        ones by a kernel of their own (default 262144)
+ *   EVQ_LAUNCH_DEPTH=d   frontier iterations kept in flight, 1..32 (default 3)
+ *   EVQ_TRACE_LOOPS=1    print each frontier iteration's count to stderr
+ *
  * Query values (Table 2 edge functions; sentinels are this library's reading
  * where the paper is silent):
  *   SSSP  min over paths of the weight sum, saturating at 0xFFFFFFFE;
