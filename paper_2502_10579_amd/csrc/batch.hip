@@ -596,7 +596,8 @@ void run_batch(const Graph& g, const BatchQuery* q, uint32_t n, Compact* out, ev
                             spawn(st, [&, i, ru, gi, st](hipStream_t ts) {
                                 try {
                                     EVQ_HIP(hipStreamWaitEvent(ts, gev[gi], 0));
-                                    if (st->ok()) run_tail_compact(g, q[i].algo, q[i].source, q[i].W, ru, out[i], qo[i], ts);
+                                    if (st->ok())
+                                        run_tail_compact(g, q[i].algo, q[i].source, q[i].W, ru, out[i], qo[i], ts);
                                 } catch (...) {
                                     st->record_current();
                                 }

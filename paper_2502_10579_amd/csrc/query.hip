@@ -896,7 +896,8 @@ void relax_phase(const Graph& g, const Window& W, const Window& PW, const uint32
     const uint32_t cblocks = grid_for(red.nU, kCompactIds, 4096);
     const bool direct = red.TU / kRelaxChunk + red.nU <= direct_tasks_limit();
     const uint32_t tblocks = grid_for(((uint64_t)red.nU + red.TU / kRelaxChunk + 63) / 64, kBlock / 64, 2048);
-    const uint32_t rblocks = grid_for(((uint64_t)red.nU + red.TU / kRelaxChunk + T::G - 1) / T::G, kBlock / 64, EVQ_RELAX_BLOCKS);
+    const uint32_t rblocks =
+        grid_for(((uint64_t)red.nU + red.TU / kRelaxChunk + T::G - 1) / T::G, kBlock / 64, EVQ_RELAX_BLOCKS);
     auto issue = [&](uint64_t, int p, bool first, uint32_t* slot) {
         if (direct) {
             EVQ_LAUNCH("relax_compact", k_relax_compact<true>, cblocks, kCompactBlock, s, ra, p, first ? 1 : 0);
