@@ -29,7 +29,7 @@ constexpr int kBlock = 256;
 #define EVQ_EXPAND_BLOCKS 2048
 #endif
 #ifndef EVQ_WALKERS
-#define EVQ_WALKERS 2
+#define EVQ_WALKERS 1
 #endif
 #ifndef EVQ_NT_EDGES
 #define EVQ_NT_EDGES 0
