@@ -38,6 +38,9 @@
  *                        have them written by the frontier compaction, larger
  *                        ones by a kernel of their own (default 262144)
  *   EVQ_LAUNCH_DEPTH=d   frontier iterations kept in flight, 1..32 (default 3)
+ *   EVQ_APPEND_REBUILD=1 evq_append rebuilds the versioned graph from all
+ *                        held edges and the batch instead of updating it
+ *                        incrementally (same result)
  *   EVQ_TRACE_LOOPS=1    print each frontier iteration's count to stderr
  *
  * Query values (Table 2 edge functions; sentinels are this library's reading

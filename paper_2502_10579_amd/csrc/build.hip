@@ -481,6 +481,477 @@ void append_impl(const Graph& old, Graph* g, const uint32_t* d_ev, uint64_t n_de
     finish_build<KT, MW>(g, sorted, N, L, mtmp, flag, s, ar);
 }
 
+
+// ------------------------------------------------------------------ incremental ring append
+//
+// An append changes one mask bit of every held edge (the recycled slot takes
+// presence in the new snapshot) and adds or drops the few triples its events
+// touch, so it need not re-sort the held edges.  It (1) sorts the events and
+// merges each triple's run into delete / add flags, (2) looks every distinct
+// event triple up in its row (both parts of a row are sorted by (dst, w)),
+// (3) recomputes every mask in one streaming pass and classes each edge
+// (stays in its part, moves to the other part, or is dropped), (4) sorts the
+// movers and the new triples ("inserts") by (row, part, dst, w), and (5)
+// places each staying edge at its part's new start + its rank among the
+// part's stayers + the inserts before it, and each insert at its rank among
+// the part's inserts + the stayers before it.  Every part stays sorted by
+// (dst, w), so the arrays equal those of a full rebuild.
+
+enum : uint8_t { kDrop = 0, kStayFull = 1, kToFull = 2, kToPartial = 3, kStayPartial = 4 };
+
+// src_of holds the exclusive scan of A (rows starting at each edge); the
+// source of edge e is the number of rows starting at or before e, minus one.
+__global__ void k_src_of(const uint32_t* __restrict__ A, uint64_t E, uint32_t* __restrict__ src_of) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < E; e += (uint64_t)gridDim.x * blockDim.x)
+        src_of[e] = src_of[e] + A[e] - 1u;
+}
+
+template <typename KT>
+__global__ void k_ev_keys(const uint32_t* __restrict__ ev, uint64_t n_del, uint64_t n_ev, KeyLayout L,
+                          KT* __restrict__ keys) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_ev; i += (uint64_t)gridDim.x * blockDim.x)
+        keys[i] = make_key<KT>(ev[3 * i], ev[3 * i + 1], ev[3 * i + 2], i < n_del ? 1u : 2u, L);
+}
+
+template <typename KT>
+__global__ void k_ev_heads(const KT* __restrict__ keys, uint64_t n, int tb, uint32_t* __restrict__ head) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        head[i] = (i == 0 || (keys[i] >> tb) != (keys[i - 1] >> tb)) ? 1u : 0u;
+}
+
+// Distinct event triples (sorted) and their flags: bit 0 deleted, bit 1 added.
+template <typename KT>
+__global__ void k_ev_unique(const KT* __restrict__ keys, uint64_t n, int tb, const uint32_t* __restrict__ head,
+                            const uint32_t* __restrict__ hpos, KT* __restrict__ utrip, uint32_t* __restrict__ ufl) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (!head[i]) continue;
+        const KT trip = keys[i] >> tb;
+        uint32_t fl = 0;
+        for (uint64_t j = i; j < n && (keys[j] >> tb) == trip; ++j) fl |= (uint32_t)(keys[j] & 3u);
+        utrip[hpos[i]] = trip;
+        ufl[hpos[i]] = fl;
+    }
+}
+
+// First edge of [lo, hi) whose (col, wgt) is not below (d, w) (the range is sorted).
+__device__ __forceinline__ uint32_t lower_edge(const uint32_t* __restrict__ col, const uint32_t* __restrict__ wgt,
+                                               uint32_t lo, uint32_t hi, uint32_t d, uint32_t w) {
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        const uint32_t c = col[mid];
+        if (c < d || (c == d && wgt[mid] < w)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int MW>
+__device__ __forceinline__ bool mask_bit(const uint64_t* __restrict__ mask, uint64_t e, uint32_t slot) {
+    return (mask[e * MW + (slot >> 6)] >> (slot & 63)) & 1ull;
+}
+
+// Each distinct event triple: an edge it names gets its new-snapshot bit
+// (added, or present in the newest snapshot and not deleted) in ovr; an added
+// triple held in no snapshot is new.
+template <typename KT, int MW>
+__global__ void k_ev_lookup(const KT* __restrict__ utrip, const uint32_t* __restrict__ ufl, uint32_t nu, KeyLayout L,
+                            const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ row_split,
+                            const uint32_t* __restrict__ col, const uint32_t* __restrict__ wgt,
+                            const uint64_t* __restrict__ mask, uint32_t s_prev, uint8_t* __restrict__ ovr,
+                            uint32_t* __restrict__ isnew) {
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < nu; k += (uint64_t)gridDim.x * blockDim.x) {
+        const KT t = utrip[k];
+        const uint32_t w = (uint32_t)(t & (((KT)1 << L.wb) - 1));
+        const uint32_t d = (uint32_t)((t >> L.wb) & (((KT)1 << L.vb) - 1));
+        const uint32_t u = (uint32_t)(t >> (L.wb + L.vb));
+        const bool del = ufl[k] & 1u, add = (ufl[k] >> 1) & 1u;
+        const uint32_t a = row_ptr[u], sp = row_split[u], z = row_ptr[u + 1];
+        uint32_t e = lower_edge(col, wgt, a, sp, d, w);
+        if (!(e < sp && col[e] == d && wgt[e] == w)) {
+            e = lower_edge(col, wgt, sp, z, d, w);
+            if (!(e < z && col[e] == d && wgt[e] == w)) e = kNone;
+        }
+        if (e != kNone) {
+            const bool nb = add || (mask_bit<MW>(mask, e, s_prev) && !del);
+            ovr[e] = (uint8_t)(2u | (nb ? 1u : 0u));
+        }
+        isnew[k] = (e == kNone && add) ? 1u : 0u;
+    }
+}
+
+template <int MW>
+__device__ __forceinline__ void new_mask(const uint64_t* __restrict__ mask, const uint8_t* __restrict__ ovr,
+                                         uint64_t e, uint32_t s_prev, uint32_t s_new, uint64_t (&m)[MW]) {
+#pragma unroll
+    for (int q = 0; q < MW; ++q) m[q] = mask[e * MW + q];
+    const uint8_t o = ovr[e];
+    const bool nb = (o & 2u) ? (o & 1u) : ((m[s_prev >> 6] >> (s_prev & 63)) & 1ull);
+    m[s_new >> 6] &= ~(1ull << (s_new & 63));
+    if (nb) m[s_new >> 6] |= 1ull << (s_new & 63);
+}
+
+template <int MW>
+__device__ __forceinline__ bool mask_eq(const uint64_t (&m)[MW], const Mask<MW>& all) {
+    bool eq = true;
+#pragma unroll
+    for (int q = 0; q < MW; ++q) eq &= m[q] == all.w[q];
+    return eq;
+}
+
+template <int MW>
+__device__ __forceinline__ bool mask_any(const uint64_t (&m)[MW]) {
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < MW; ++q) any |= m[q] != 0;
+    return any;
+}
+
+template <int MW>
+__global__ void k_classify(const uint64_t* __restrict__ mask, const uint8_t* __restrict__ ovr, uint64_t E,
+                           uint32_t s_prev, uint32_t s_new, Mask<MW> all, uint8_t* __restrict__ cls,
+                           uint32_t* __restrict__ stay, uint32_t* __restrict__ mover) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < E; e += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t m0[MW], m[MW];
+#pragma unroll
+        for (int q = 0; q < MW; ++q) m0[q] = mask[e * MW + q];
+        new_mask<MW>(mask, ovr, e, s_prev, s_new, m);
+        const bool was = mask_eq<MW>(m0, all), full = mask_eq<MW>(m, all), kept = mask_any<MW>(m);
+        uint8_t c = kDrop;
+        if (kept) c = was ? (full ? kStayFull : kToPartial) : (full ? kToFull : kStayPartial);
+        cls[e] = c;
+        stay[e] = (c == kStayFull || c == kStayPartial) ? 1u : 0u;
+        mover[e] = (c == kToFull || c == kToPartial) ? 1u : 0u;
+    }
+}
+
+// Insert keys (u128): u | part | dst | w | payload (32 bits: a mover's edge id,
+// or (1 << 31) | the index of a new triple among the distinct event triples).
+struct InsLayout {
+    int vb, wb;
+    __host__ __device__ int total() const { return 2 * vb + wb + 1 + 32; }
+};
+
+__device__ __forceinline__ u128 ins_key(uint32_t u, uint32_t part, uint32_t d, uint32_t w, uint32_t payload,
+                                        InsLayout L) {
+    u128 k = (u128)u;
+    k = (k << 1) | (u128)part;
+    k = (k << L.vb) | (u128)d;
+    k = (k << L.wb) | (u128)w;
+    return (k << 32) | (u128)payload;
+}
+
+struct InsFields {
+    uint32_t u, part, d, w, payload;
+};
+
+__device__ __forceinline__ InsFields ins_fields(u128 k, InsLayout L) {
+    InsFields f;
+    f.payload = (uint32_t)k;
+    k >>= 32;
+    f.w = (uint32_t)(k & (((u128)1 << L.wb) - 1));
+    k >>= L.wb;
+    f.d = (uint32_t)(k & (((u128)1 << L.vb) - 1));
+    k >>= L.vb;
+    f.part = (uint32_t)(k & 1u);
+    f.u = (uint32_t)(k >> 1);
+    return f;
+}
+
+__global__ void k_ins_movers(const uint8_t* __restrict__ cls, const uint32_t* __restrict__ mpos, uint64_t E,
+                             const uint32_t* __restrict__ src_of, const uint32_t* __restrict__ col,
+                             const uint32_t* __restrict__ wgt, InsLayout L, u128* __restrict__ ikeys) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < E; e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint8_t c = cls[e];
+        if (c != kToFull && c != kToPartial) continue;
+        ikeys[mpos[e]] = ins_key(src_of[e], c == kToFull ? 0u : 1u, col[e], wgt[e], (uint32_t)e, L);
+    }
+}
+
+template <typename KT, int MW>
+__global__ void k_ins_new(const KT* __restrict__ utrip, const uint32_t* __restrict__ isnew,
+                          const uint32_t* __restrict__ npos, uint32_t nu, uint32_t nm, KeyLayout EL, InsLayout L,
+                          uint32_t s_new, Mask<MW> all, u128* __restrict__ ikeys) {
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < nu; k += (uint64_t)gridDim.x * blockDim.x) {
+        if (!isnew[k]) continue;
+        const KT t = utrip[k];
+        const uint32_t w = (uint32_t)(t & (((KT)1 << EL.wb) - 1));
+        const uint32_t d = (uint32_t)((t >> EL.wb) & (((KT)1 << EL.vb) - 1));
+        const uint32_t u = (uint32_t)(t >> (EL.wb + EL.vb));
+        uint64_t m[MW];
+#pragma unroll
+        for (int q = 0; q < MW; ++q) m[q] = 0;
+        m[s_new >> 6] = 1ull << (s_new & 63);
+        const uint32_t part = mask_eq<MW>(m, all) ? 0u : 1u;  // full only when K == 1
+        ikeys[nm + npos[k]] = ins_key(u, part, d, w, (1u << 31) | (uint32_t)k, L);
+    }
+}
+
+// Per (row, part): the inserts' count and first index in the sorted list.
+__global__ void k_ins_rows(const u128* __restrict__ ikeys, uint32_t ni, InsLayout L, uint32_t V,
+                           uint32_t* __restrict__ icnt, uint32_t* __restrict__ ioff) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < ni; i += (uint64_t)gridDim.x * blockDim.x) {
+        const InsFields f = ins_fields(ikeys[i], L);
+        const uint64_t slot = (uint64_t)f.part * V + f.u;
+        atomicAdd(&icnt[slot], 1u);
+        bool head = i == 0;
+        if (!head) {
+            const InsFields p = ins_fields(ikeys[i - 1], L);
+            head = p.u != f.u || p.part != f.part;
+        }
+        if (head) ioff[slot] = (uint32_t)i;
+    }
+}
+
+__global__ void k_new_rows(const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ row_split,
+                           const uint32_t* __restrict__ cS, const uint32_t* __restrict__ icnt, uint32_t V,
+                           uint32_t* __restrict__ len, uint32_t* __restrict__ nf) {
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < V; u += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t a = row_ptr[u], sp = row_split[u], z = row_ptr[u + 1];
+        const uint32_t f = cS[sp] - cS[a] + icnt[u];
+        nf[u] = f;
+        len[u] = f + (cS[z] - cS[sp]) + icnt[(uint64_t)V + u];
+    }
+}
+
+// The new arrays.
+template <int MW>
+struct NewCsr {
+    uint32_t *rp, *nf, *fx;  // row starts, full edges per row, full edges before each row
+    uint32_t *col, *wgt;
+    uint64_t* mask;
+    uint32_t *p_src, *p_dst, *p_w;
+    uint64_t* p_mask;
+};
+
+template <int MW>
+__device__ __forceinline__ void put_edge(const NewCsr<MW>& o, uint32_t u, uint32_t part, uint32_t pos, uint32_t d,
+                                         uint32_t w, const uint64_t (&m)[MW]) {
+    o.col[pos] = d;
+    o.wgt[pos] = w;
+#pragma unroll
+    for (int q = 0; q < MW; ++q) o.mask[(uint64_t)pos * MW + q] = m[q];
+    if (part) {
+        const uint32_t p = pos - (o.fx[u] + o.nf[u]);
+        o.p_src[p] = u;
+        o.p_dst[p] = d;
+        o.p_w[p] = w;
+#pragma unroll
+        for (int q = 0; q < MW; ++q) o.p_mask[(uint64_t)p * MW + q] = m[q];
+    }
+}
+
+// Inserts of (u, part) in [i0, i0 + c) whose (dst, w) is below (d, w).
+__device__ __forceinline__ uint32_t ins_before(const u128* __restrict__ ikeys, uint32_t i0, uint32_t c, InsLayout L,
+                                               uint32_t d, uint32_t w) {
+    uint32_t lo = 0, hi = c;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        const InsFields f = ins_fields(ikeys[i0 + mid], L);
+        if (f.d < d || (f.d == d && f.w < w)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int MW>
+__global__ void k_place_stayers(uint64_t E, const uint8_t* __restrict__ cls, const uint32_t* __restrict__ src_of,
+                                const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ row_split,
+                                const uint32_t* __restrict__ col, const uint32_t* __restrict__ wgt,
+                                const uint64_t* __restrict__ mask, const uint8_t* __restrict__ ovr, uint32_t s_prev,
+                                uint32_t s_new, const uint32_t* __restrict__ cS, const uint32_t* __restrict__ icnt,
+                                const uint32_t* __restrict__ ioff, const u128* __restrict__ ikeys, InsLayout L,
+                                uint32_t V, NewCsr<MW> o) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < E; e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint8_t c = cls[e];
+        if (c != kStayFull && c != kStayPartial) continue;
+        const uint32_t u = src_of[e], part = c == kStayPartial ? 1u : 0u;
+        const uint32_t pstart = part ? row_split[u] : row_ptr[u];
+        const uint32_t d = col[e], w = wgt[e];
+        uint32_t pos = o.rp[u] + (part ? o.nf[u] : 0u) + (cS[e] - cS[pstart]);
+        const uint64_t slot = (uint64_t)part * V + u;
+        const uint32_t ic = icnt[slot];
+        if (ic) pos += ins_before(ikeys, ioff[slot], ic, L, d, w);
+        uint64_t m[MW];
+        new_mask<MW>(mask, ovr, e, s_prev, s_new, m);
+        put_edge<MW>(o, u, part, pos, d, w, m);
+    }
+}
+
+template <int MW>
+__global__ void k_place_inserts(uint32_t ni, const u128* __restrict__ ikeys, InsLayout L,
+                                const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ row_split,
+                                const uint32_t* __restrict__ col, const uint32_t* __restrict__ wgt,
+                                const uint64_t* __restrict__ mask, const uint8_t* __restrict__ ovr, uint32_t s_prev,
+                                uint32_t s_new, const uint32_t* __restrict__ cS, const uint32_t* __restrict__ ioff,
+                                uint32_t V, NewCsr<MW> o) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < ni; i += (uint64_t)gridDim.x * blockDim.x) {
+        const InsFields f = ins_fields(ikeys[i], L);
+        const uint32_t a = f.part ? row_split[f.u] : row_ptr[f.u];
+        const uint32_t z = f.part ? row_ptr[f.u + 1] : row_split[f.u];
+        const uint32_t ps = lower_edge(col, wgt, a, z, f.d, f.w);
+        const uint32_t pos = o.rp[f.u] + (f.part ? o.nf[f.u] : 0u) + (uint32_t)(i - ioff[(uint64_t)f.part * V + f.u]) +
+                             (cS[ps] - cS[a]);
+        uint64_t m[MW];
+        if (f.payload >> 31) {
+#pragma unroll
+            for (int q = 0; q < MW; ++q) m[q] = 0;
+            m[s_new >> 6] = 1ull << (s_new & 63);
+        } else {
+            new_mask<MW>(mask, ovr, f.payload, s_prev, s_new, m);
+        }
+        put_edge<MW>(o, f.u, f.part, pos, f.d, f.w, m);
+    }
+}
+
+__global__ void k_new_split(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ nf, uint32_t V,
+                            uint32_t* __restrict__ row_split) {
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < V; u += (uint64_t)gridDim.x * blockDim.x)
+        row_split[u] = rp[u] + nf[u];
+}
+
+template <typename KT, int MW>
+void append_incremental(const Graph& old, Graph* g, const uint32_t* d_ev, uint64_t n_del, uint64_t n_ev,
+                        hipStream_t s, Arena& ar) {
+    const uint32_t V = old.V, K = old.K;
+    const uint64_t E = old.E;
+    const uint32_t s_new = (uint32_t)(old.first % K), s_prev = (uint32_t)((old.first + K - 1) % K);
+    Mask<MW> all;
+#pragma unroll
+    for (int q = 0; q < MW; ++q) {
+        const int hi = (int)K - 64 * q;
+        all.w[q] = hi >= 64 ? ~0ull : (hi <= 0 ? 0ull : ((1ull << hi) - 1ull));
+    }
+    KeyLayout EL;
+    EL.vb = bits_for(V - 1);
+    EL.wb = bits_for(g->maxw);
+    EL.tb = 2;
+    InsLayout IL{EL.vb, EL.wb};
+    Mailbox mb(4);
+
+    // 1. distinct event triples
+    uint32_t nu = 0;
+    KT* utrip = ar.alloc<KT>(n_ev + 1);
+    uint32_t* ufl = ar.alloc<uint32_t>(n_ev + 1);
+    if (n_ev) {
+        KT* keys = ar.alloc<KT>(n_ev);
+        KT* tmp = ar.alloc<KT>(n_ev);
+        EVQ_LAUNCH("append_ev_keys", k_ev_keys<KT>, grid_for(n_ev, 256), 256, s, d_ev, n_del, n_ev, EL, keys);
+        KT* sorted = radix_sort<KT>(keys, tmp, n_ev, EL.total(), s, ar, EL.tb);
+        uint32_t* head = ar.alloc<uint32_t>(n_ev + 1);
+        uint32_t* hpos = ar.alloc<uint32_t>(n_ev + 1);
+        EVQ_LAUNCH("append_ev_heads", k_ev_heads<KT>, grid_for(n_ev, 256), 256, s, sorted, n_ev, EL.tb, head);
+        scan_exclusive(head, hpos, n_ev, hpos + n_ev, s, ar);
+        EVQ_LAUNCH("append_ev_unique", k_ev_unique<KT>, grid_for(n_ev, 256), 256, s, sorted, n_ev, EL.tb, head, hpos,
+                   utrip, ufl);
+        EVQ_HIP(hipMemcpyAsync(mb.h, hpos + n_ev, 4, hipMemcpyDeviceToHost, s));
+        EVQ_HIP(hipStreamSynchronize(s));
+        nu = mb.h[0];
+    }
+
+    // 2. event triples in the held rows; 3. new masks and classes
+    uint8_t* ovr = ar.alloc<uint8_t>(E + 4);
+    fill_u32(reinterpret_cast<uint32_t*>(ovr), (E + 4) / 4, 0u, s);
+    uint32_t* isnew = ar.alloc<uint32_t>(nu + 1);
+    uint32_t* npos = ar.alloc<uint32_t>(nu + 1);
+    if (nu) {
+        EVQ_LAUNCH("append_ev_lookup", (k_ev_lookup<KT, MW>), grid_for(nu, 256), 256, s, utrip, ufl, nu, EL,
+                   old.row_ptr, old.row_split, old.col, old.wgt, old.mask, s_prev, ovr, isnew);
+        scan_exclusive(isnew, npos, nu, npos + nu, s, ar);
+    } else {
+        fill_u32(npos, 1, 0u, s);
+    }
+    uint8_t* cls = ar.alloc<uint8_t>(E + 1);
+    uint32_t* cS = ar.alloc<uint32_t>(E + 1);
+    uint32_t* cM = ar.alloc<uint32_t>(E + 1);
+    if (E) {
+        EVQ_LAUNCH("append_classify", k_classify<MW>, grid_for(E, 256), 256, s, old.mask, ovr, E, s_prev, s_new, all,
+                   cls, cS, cM);
+        scan_exclusive(cS, cS, E, cS + E, s, ar);
+        scan_exclusive(cM, cM, E, cM + E, s, ar);
+    } else {
+        fill_u32(cS, 1, 0u, s);
+        fill_u32(cM, 1, 0u, s);
+    }
+    EVQ_HIP(hipMemcpyAsync(mb.h, cM + E, 4, hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipMemcpyAsync(mb.h + 1, npos + nu, 4, hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipStreamSynchronize(s));
+    const uint32_t nm = mb.h[0], nn = mb.h[1], ni = nm + nn;
+
+    // 4. inserts sorted by (row, part, dst, w), counted per (row, part)
+    u128* ikeys = ar.alloc<u128>(ni + 1);
+    uint32_t* icnt = ar.alloc<uint32_t>(2ull * V);
+    uint32_t* ioff = ar.alloc<uint32_t>(2ull * V);
+    fill_u32(icnt, 2ull * V, 0u, s);
+    uint32_t* src_of = nullptr;
+    if (nm) {
+        uint32_t* A = ar.alloc<uint32_t>(E + 1);
+        src_of = ar.alloc<uint32_t>(E + 1);
+        fill_u32(A, E + 1, 0u, s);
+        EVQ_LAUNCH("append_rows", k_row_starts, grid_for(V, 256), 256, s, old.row_ptr, V, E, A);
+        scan_exclusive(A, src_of, E, nullptr, s, ar);
+        EVQ_LAUNCH("append_src", k_src_of, grid_for(E, 256), 256, s, A, E, src_of);
+        ar.release(A);
+        EVQ_LAUNCH("append_ins_movers", k_ins_movers, grid_for(E, 256), 256, s, cls, cM, E, src_of, old.col, old.wgt, IL,
+                   ikeys);
+    }
+    if (nn)
+        EVQ_LAUNCH("append_ins_new", (k_ins_new<KT, MW>), grid_for(nu, 256), 256, s, utrip, isnew, npos, nu, nm, EL, IL,
+                   s_new, all, ikeys);
+    if (ni) {
+        u128* itmp = ar.alloc<u128>(ni);
+        u128* isorted = radix_sort<u128>(ikeys, itmp, ni, IL.total(), s, ar, 32);
+        ikeys = isorted;
+        EVQ_LAUNCH("append_ins_rows", k_ins_rows, grid_for(ni, 256), 256, s, ikeys, ni, IL, V, icnt, ioff);
+    }
+
+    // new row lengths and starts
+    NewCsr<MW> o;
+    o.rp = (uint32_t*)stream_alloc(((uint64_t)V + 1) * 4, s);
+    o.nf = ar.alloc<uint32_t>((uint64_t)V + 1);
+    o.fx = ar.alloc<uint32_t>((uint64_t)V + 1);
+    uint32_t* len = ar.alloc<uint32_t>((uint64_t)V + 1);
+    g->row_ptr = o.rp;
+    EVQ_LAUNCH("append_rows_new", k_new_rows, grid_for(V, 256), 256, s, old.row_ptr, old.row_split, cS, icnt, V, len,
+               o.nf);
+    scan_exclusive(len, o.rp, V, o.rp + V, s, ar);
+    scan_exclusive(o.nf, o.fx, V, o.fx + V, s, ar);
+    EVQ_HIP(hipMemcpyAsync(mb.h, o.rp + V, 4, hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipMemcpyAsync(mb.h + 1, o.fx + V, 4, hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipStreamSynchronize(s));
+    const uint64_t E2 = mb.h[0], NF = mb.h[1];
+    g->E = E2;
+    g->n_partial = E2 - NF;
+    g->row_split = (uint32_t*)stream_alloc((uint64_t)V * 4, s);
+    g->col = o.col = (uint32_t*)stream_alloc(E2 * 4 + 4, s);
+    g->wgt = o.wgt = (uint32_t*)stream_alloc(E2 * 4 + 4, s);
+    g->mask = o.mask = (uint64_t*)stream_alloc(E2 * 8 * MW + 16, s);
+    g->p_src = o.p_src = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
+    g->p_dst = o.p_dst = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
+    g->p_w = o.p_w = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
+    g->p_mask = o.p_mask = (uint64_t*)stream_alloc(g->n_partial * 8 * MW + 16, s);
+    g->bytes = ((uint64_t)V + 1) * 4 + (uint64_t)V * 4 + E2 * (8 + 8 * MW) + g->n_partial * (12 + 8 * MW);
+
+    // 5. placement
+    if (E) {
+        if (!src_of) {
+            uint32_t* A = ar.alloc<uint32_t>(E + 1);
+            src_of = ar.alloc<uint32_t>(E + 1);
+            fill_u32(A, E + 1, 0u, s);
+            EVQ_LAUNCH("append_rows", k_row_starts, grid_for(V, 256), 256, s, old.row_ptr, V, E, A);
+            scan_exclusive(A, src_of, E, nullptr, s, ar);
+            EVQ_LAUNCH("append_src", k_src_of, grid_for(E, 256), 256, s, A, E, src_of);
+            ar.release(A);
+        }
+        EVQ_LAUNCH("append_place", k_place_stayers<MW>, grid_for(E, 256), 256, s, E, cls, src_of, old.row_ptr,
+                   old.row_split, old.col, old.wgt, old.mask, ovr, s_prev, s_new, cS, icnt, ioff, ikeys, IL, V, o);
+    }
+    if (ni)
+        EVQ_LAUNCH("append_place_ins", k_place_inserts<MW>, grid_for(ni, 256), 256, s, ni, ikeys, IL, old.row_ptr,
+                   old.row_split, old.col, old.wgt, old.mask, ovr, s_prev, s_new, cS, ioff, V, o);
+    EVQ_LAUNCH("append_split", k_new_split, grid_for(V, 256), 256, s, o.rp, o.nf, V, g->row_split);
+    EVQ_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace
 
 void free_graph(Graph* g, hipStream_t s) {
@@ -585,6 +1056,13 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
     return g;
 }
 
+// EVQ_APPEND_REBUILD=1 rebuilds the versioned graph from all held edges and
+// the batch (one sort of everything) instead of the incremental append.
+bool append_rebuild() {
+    const char* e = getenv("EVQ_APPEND_REBUILD");
+    return e && *e && *e != '0';
+}
+
 Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     const uint32_t V = old.V;
@@ -636,6 +1114,15 @@ Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
             g->p_w = (uint32_t*)stream_alloc(4, s);
             g->p_mask = (uint64_t*)stream_alloc(16, s);
             g->bytes = ((uint64_t)V + 1) * 8;
+        } else if (!append_rebuild()) {
+            // incremental: event keys src | dst | w | tag
+            if (2 * L.vb + L.wb + 2 <= 64) {
+                if (g->MW == 1) append_incremental<uint64_t, 1>(old, g, d_ev, b.n_del, n_ev, s, ar);
+                else append_incremental<uint64_t, 2>(old, g, d_ev, b.n_del, n_ev, s, ar);
+            } else {
+                if (g->MW == 1) append_incremental<u128, 1>(old, g, d_ev, b.n_del, n_ev, s, ar);
+                else append_incremental<u128, 2>(old, g, d_ev, b.n_del, n_ev, s, ar);
+            }
         } else if (L.total() <= 64) {
             if (g->MW == 1) append_impl<uint64_t, 1>(old, g, d_ev, b.n_del, n_ev, L, ib, s, ar);
             else append_impl<uint64_t, 2>(old, g, d_ev, b.n_del, n_ev, L, ib, s, ar);
