@@ -528,6 +528,16 @@ def main():
             if traffic:
                 roof["traffic_GBps"] = round(traffic / (avg_us * 1e-6) / 1e9, 2)
                 roof["traffic_frac"] = round(traffic / (avg_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
+            if dom.startswith("solve_expand_"):
+                # the expansion's edge-visit rate against the same per-edge
+                # memory operations alone over this graph's edges
+                visits = st["edges_cup"] if dom == "solve_expand_cup" else st["edges_cap"]
+                rate = visits * reps / (tot_ms / 1000.0)
+                ceil = g.gather_ceiling(5)
+                roof["access_ceiling"] = {"kernel": "gather_ceiling", "edges_per_s": round(ceil, 0),
+                                          "expansion_edges_per_s": round(rate, 0),
+                                          "frac": round(rate / ceil, 4) if ceil else None}
+                log(f"[bench] {dom}: {rate / 1e9:.1f} G edge visits/s; gather ceiling {ceil / 1e9:.1f} G edges/s")
         relax_b = algorithmic_bytes("relax", st, L, inst.num_vertices)
         if "relax" in kernels and relax_b:
             rl, rt = kernels["relax"]

@@ -401,6 +401,24 @@ void evq_timing_enable(int on);
 void evq_timing_reset(void);
 int evq_timing_report(evq_kernel_time* out, int cap);
 
+/*
+ * Access-pattern ceiling of the bound solves' expansion (measurement only).
+ * The expansion's visit of an edge (Section 3, Step 1; Algorithm 2's
+ * relaxation of an edge) streams the edge's column and weight, gathers the
+ * destination's 4-byte value and, when the candidate is better, updates it
+ * with an atomic and marks the destination.  This call runs a kernel with
+ * exactly those memory operations over every edge of g in CSR order, with
+ * values that make the comparison fail (so no update is issued), and without
+ * the expansion's walk over frontier items.  It runs one untimed pass, then
+ * `launches` passes timed with HIP events on `stream`, and writes edges per
+ * second to *edges_per_s (0 for a graph without edges).  It allocates and
+ * frees 5 bytes per vertex of scratch from the device pool on `stream` and
+ * returns after synchronising on its own end event.
+ * Errors: EVQ_EINVAL (NULL graph or edges_per_s, launches == 0), EVQ_ENOMEM,
+ * EVQ_EDEVICE.
+ */
+evq_status evq_gather_ceiling(const evq_graph* g, uint32_t launches, double* edges_per_s, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

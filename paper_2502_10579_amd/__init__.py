@@ -141,12 +141,14 @@ _lib.evq_timing_reset.restype = None
 _lib.evq_timing_reset.argtypes = []
 _lib.evq_timing_report.restype = ctypes.c_int
 _lib.evq_timing_report.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int]
+_lib.evq_gather_ceiling.restype = ctypes.c_int32
+_lib.evq_gather_ceiling.argtypes = [_P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), _P]
 
 EXPORTED = ["evq_build", "evq_graph_info_get", "evq_graph_export", "evq_query", "evq_query_bounds",
             "evq_query_plain", "evq_query_sequential", "evq_query_batch", "evq_result_expand", "evq_result_free",
             "evq_batch_config_get", "evq_batch_config_set", "evq_batch_autotune", "evq_append", "evq_server_create",
             "evq_server_submit", "evq_server_poll", "evq_server_pending", "evq_server_destroy", "evq_free", "evq_last_error", "evq_timing_enable",
-            "evq_timing_reset", "evq_timing_report"]
+            "evq_timing_reset", "evq_timing_report", "evq_gather_ceiling"]
 
 
 class EvqError(RuntimeError):
@@ -251,6 +253,12 @@ class Graph:
         for k in ("col", "w", "mask"):
             out[k] = out[k][:E]
         return out
+
+    def gather_ceiling(self, launches: int = 5, stream=None) -> float:
+        """Edges/s of the expansion's per-edge memory operations alone over this graph (measurement only)."""
+        r = ctypes.c_double(0.0)
+        _check(_lib.evq_gather_ceiling(self._h, launches, ctypes.byref(r), _stream(stream)))
+        return r.value
 
     def _alloc(self, L, out):
         import torch

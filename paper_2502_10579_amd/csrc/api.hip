@@ -5,6 +5,7 @@
 #include <mutex>
 
 #include "batch.h"
+#include "ceiling.h"
 #include "evq_internal.h"
 #include "handle.h"
 
@@ -123,6 +124,22 @@ evq_status evq_graph_export(const evq_graph* h, uint32_t* row_ptr, uint32_t* row
             if (mask) EVQ_HIP(hipMemcpyAsync(mask, g.mask, g.E * 8 * g.MW, hipMemcpyDeviceToHost, s));
         }
         EVQ_HIP(hipStreamSynchronize(s));
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+evq_status evq_gather_ceiling(const evq_graph* h, uint32_t launches, double* edges_per_s, void* stream) {
+    g_last_error.clear();
+    if (!h || !edges_per_s) return bad(EVQ_EINVAL, "NULL argument");
+    if (launches == 0) return bad(EVQ_EINVAL, "launches must be positive");
+    try {
+        auto gp = h->get();
+        const evq::Graph& g = *gp;
+        hipStream_t s = (hipStream_t)stream;
+        evq::UseGuard ug{g, s};
+        *edges_per_s = evq::gather_ceiling(g, launches, s);
         return EVQ_OK;
     } catch (...) {
         return guard_exc();

@@ -237,6 +237,23 @@ def test_determinism_repeat(evq):
             assert np.array_equal(a, gpu_values(g, oracle.SSSP, 0, 0, 8))
 
 
+def test_gather_ceiling_measurement(evq):
+    # measurement entry point: a positive rate, 0 on a graph without edges,
+    # argument errors, and the graph (only read) answers the same afterwards
+    inst = synth.config_instance("small", seed=2)
+    with _graph(evq, inst) as g:
+        a = gpu_values(g, oracle.SSSP, 0, 0, 8)
+        assert g.gather_ceiling(2) > 0
+        with pytest.raises(evq.EvqError) as ei:
+            g.gather_ceiling(0)
+        assert ei.value.status == evq.EVQ_EINVAL
+        assert np.array_equal(a, gpu_values(g, oracle.SSSP, 0, 0, 8))
+    empty = synth.Instance(1, np.zeros((0, 3), np.uint32), [np.zeros((0, 3), np.uint32)],
+                           [np.zeros((0, 3), np.uint32)])
+    with _graph(evq, empty) as g:
+        assert g.gather_ceiling(1) == 0.0
+
+
 @pytest.mark.parametrize("delta,heavy", [(1, 0), (7, 0), (60, 0), (3, 4), (20, 2)])
 @pytest.mark.parametrize("algo", ALGOS)
 def test_near_far_scheduling(evq, algo, delta, heavy, monkeypatch):
