@@ -37,6 +37,13 @@
  *   EVQ_DIRECT_TASKS=n   reduced subgraphs of at most n relaxation tasks
  *                        have them written by the frontier compaction, larger
  *                        ones by a kernel of their own (default 262144)
+ *   EVQ_PULL_FRAC=f      full-window intersection solves: an iteration whose
+ *                        frontier holds at least this share of the
+ *                        all-present edges pulls (every vertex takes its best
+ *                        all-present in-edge) instead of pushing; the graph's
+ *                        reverse CSR (8 bytes per all-present edge) is built
+ *                        by the first such query on a graph version
+ *                        (default 0.5; above 1: never pull)
  *   EVQ_LAUNCH_DEPTH=d   frontier iterations kept in flight, 1..32 (default 3)
  *   EVQ_APPEND_REBUILD=1 evq_append rebuilds the versioned graph from all
  *                        held edges and the batch instead of updating it

@@ -33,6 +33,16 @@ uint32_t choose_heavy(uint32_t algo);
 
 Frontier make_frontier(const Graph& g, Workspace& ws, hipStream_t s);
 
+// Pull step of the full-window intersection solve: an expansion whose
+// frontier holds at least this share of the all-present edges (fixed point,
+// 1024 = all of them) takes every vertex's best candidate over its
+// all-present in-edges instead.  EVQ_PULL_FRAC (a fraction; above 1 turns the
+// pull step off) overrides the default.  Returns kNone when it is off.
+uint32_t pull_frac();
+// The graph's reverse CSR, built on s the first time (later callers' streams
+// wait for it).
+void ensure_reverse(const Graph& g, hipStream_t s);
+
 // R := values on the window's intersection graph.  Returns the iteration count.
 uint64_t solve_cap(const Graph& g, uint32_t algo, const Window& W, uint32_t source, uint32_t* R, Frontier& f,
                    hipStream_t s, bool stats);

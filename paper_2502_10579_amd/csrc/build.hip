@@ -956,9 +956,11 @@ void append_incremental(const Graph& old, Graph* g, const uint32_t* d_ev, uint64
 
 void free_graph(Graph* g, hipStream_t s) {
     if (!g) return;
-    void* arrays[9] = {g->row_ptr, g->row_split, g->col, g->wgt, g->mask, g->p_src, g->p_dst, g->p_w, g->p_mask};
+    void* arrays[14] = {g->row_ptr, g->row_split, g->col,   g->wgt,   g->mask,  g->p_src, g->p_dst,
+                        g->p_w,     g->p_mask,    g->rv_src, g->rv_w, g->rv_io, g->rv_iv, g->rv_cnt};
     for (void* p : arrays)
         if (p) (void)hipFreeAsync(p, s);
+    if (g->rv_ready) (void)hipEventDestroy(g->rv_ready);
     for (hipEvent_t e : g->uses) (void)hipEventDestroy(e);
     delete g;
 }

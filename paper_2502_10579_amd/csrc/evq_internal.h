@@ -58,6 +58,17 @@ struct Graph {
     // arrays are released (stream-ordered, after all of them) when it retires.
     mutable std::mutex use_mu;
     mutable std::vector<hipEvent_t> uses;
+    // Reverse CSR of the edges present in all K snapshots, grouped by
+    // destination (the pull step of the full-window intersection solve).  It
+    // is built on first use; later users on other streams wait for rv_ready.
+    mutable std::mutex rv_mu;
+    mutable bool rv_built = false;
+    mutable hipEvent_t rv_ready = nullptr;
+    mutable uint32_t* rv_src = nullptr;  // source of each in-edge (capacity E)
+    mutable uint32_t* rv_w = nullptr;    // its weight (capacity E)
+    mutable uint32_t* rv_io = nullptr;   // first in-edge of each destination with in-edges (capacity V)
+    mutable uint32_t* rv_iv = nullptr;   // that destination (capacity V)
+    mutable uint32_t* rv_cnt = nullptr;  // [0] destinations with in-edges, [1] in-edges (device)
 };
 
 // Records that work reading g was queued on s (call after the last launch).

@@ -61,6 +61,14 @@ struct SolveArgs {
     FrontierCounters* cnt;
     unsigned long long* stats;
     uint32_t V;
+    // pull step (full-window intersection only): reverse CSR and the share of
+    // the all-present edges from which an iteration pulls (kNone: never)
+    const uint32_t* rv_src;
+    const uint32_t* rv_w;
+    const uint32_t* rv_io;
+    const uint32_t* rv_iv;
+    const uint32_t* rv_cnt;
+    uint32_t pull_frac;
 };
 
 // MODE: 0 = intersection over all K snapshots (only the all-present prefix of
@@ -147,12 +155,115 @@ struct Step {
     bool act, want;
 };
 
+// Lane of the 64 held items (first offsets `off`, ascending, all-ones past
+// the list) that owns range position t: the last one starting at or before t.
+__device__ __forceinline__ int owner_lane(uint32_t off, uint32_t t) {
+    int o = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        const uint32_t q = __shfl(off, o + step, 64);
+        if (q <= t) o += step;
+    }
+    return o;
+}
+
+// Pull step of the full-window intersection solve.  When most of the graph
+// is in the frontier, pushing costs one atomic per improving edge; instead
+// every vertex takes the best candidate over its all-present in-edges from
+// the current values of their sources (a valid Bellman-Ford step: it only
+// ever lowers a value to that of a real path) and writes it once.  The
+// in-edges, grouped by destination, are one range [0, n_in) cut into equal
+// slices per wave as in the push walk; the lanes of a step holding one
+// destination reduce their candidates (segmented scan), and a destination
+// running on into the next step carries its partial best.  A destination
+// whose in-edges all lie in this wave's slice is written with a plain store
+// (no other wave writes it); one cut by a slice boundary uses the atomic.
+// Every improved vertex is marked for the next frontier, as in the push.
+template <int A, bool ST>
+__device__ __forceinline__ void pull_walk(const SolveArgs& a, uint32_t n, uint32_t T) {
+    const uint32_t lane = lane_id();
+    const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
+    const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
+    uint64_t Rw = (T + nw - 1) / nw;
+    Rw = (Rw + 63) & ~63ull;
+    const uint64_t b0 = gw * Rw;
+    if (b0 >= T) return;
+    const uint32_t beg = (uint32_t)b0;
+    const uint32_t end = (uint32_t)(b0 + Rw < T ? b0 + Rw : T);
+    count_visits<ST>(a, lane == 0 ? end - beg : 0u);
+    const uint32_t worst = Alg<A>::unreached;
+    uint32_t base = beg;
+    uint32_t cur = wave_search(a.rv_io, n, base);
+    uint32_t carry_v = kNone, carry_c = worst;
+    uint32_t nup = 0;
+    while (base < end) {
+        const uint32_t idx = cur + lane;
+        const uint32_t ii = idx < n ? idx : n - 1;
+        const uint32_t offl = a.rv_io[ii];
+        const uint32_t vl = a.rv_iv[ii];
+        const uint32_t off = idx < n ? offl : kNone;
+        const uint32_t next64 = cur + 64 < n ? a.rv_io[cur + 64] : T;  // start of the item after the window
+        const uint32_t t = base + lane;
+        const bool act = t < end;
+        const uint32_t tc = act ? t : base;
+        const uint32_t u = a.rv_src[tc];
+        const uint32_t w = a.rv_w[tc];
+        const uint32_t x = a.R[u];
+        const int o = owner_lane(off, t);
+        const uint32_t v = __shfl(vl, o, 64);
+        const uint32_t voff = __shfl(off, o, 64);  // v's first in-edge
+        uint32_t vend = __shfl(off, (o + 1) & 63, 64);  // v's end: the next item's start
+        if (o == 63 || vend == kNone) vend = o == 63 ? next64 : T;
+        uint32_t c = act ? Alg<A>::extend(x, w) : worst;
+        if (lane == 0 && v == carry_v && Alg<A>::better(carry_c, c)) c = carry_c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t oc = __shfl_up(c, d, 64);
+            const int oo = __shfl_up(o, d, 64);
+            if (lane >= (uint32_t)d && oo == o && Alg<A>::better(oc, c)) c = oc;
+        }
+        const uint32_t nb = base + 64;
+        const int onext = __shfl_down(o, 1, 64);
+        const bool seg_end = lane == 63 || onext != o;
+        // the segment of lane 63 goes on into the next step of this slice
+        const bool carry = lane == 63 && vend > nb && nb < end;
+        const uint64_t cm = __ballot(carry);
+        if (seg_end && !carry) {
+            if (Alg<A>::better(c, a.R[v])) {
+                if (voff >= beg && vend <= end) a.R[v] = c;
+                else Alg<A>::improve_nr(&a.R[v], c);
+                mark(a.flags, v);
+                ++nup;
+            }
+        }
+        carry_v = cm ? __shfl(v, 63, 64) : kNone;
+        carry_c = cm ? __shfl(c, 63, 64) : worst;
+        // advance: the next step starts at the owner of base + 64
+        const uint32_t have = (uint32_t)__popcll(__ballot(off <= nb));
+        uint32_t adv = have - 1;
+        if (have == 64 && cur + 64 < n && next64 <= nb) adv = 64;
+        cur += adv;
+        base = nb;
+    }
+    if (ST) {
+        const uint32_t su = wave_sum(nup);
+        if (lane == 0 && su) atomicAdd(&a.stats[4], (unsigned long long)su);
+    }
+}
+
 template <int A, int MODE, int MW, bool ST>
 __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int p, uint32_t* slot) {
     constexpr int NW = kWalkers;
     const unsigned long long cx = expand_prologue(a.cnt, p, slot);
     const uint32_t n = items_of(cx), T = edges_of(cx);
     if (T == 0) return;
+    if (MODE == 0 && a.pull_frac != kNone) {
+        const uint32_t n_in = a.rv_cnt[1];
+        if (n_in && (uint64_t)T * 1024u >= (uint64_t)n_in * a.pull_frac) {
+            pull_walk<A, ST>(a, a.rv_cnt[0], n_in);
+            return;
+        }
+    }
     const uint32_t lane = lane_id();
     const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
     const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
@@ -324,6 +435,8 @@ SolveArgs make_args(const Graph& g, const Frontier& f, uint32_t* R) {
     a.cnt = f.cnt;
     a.stats = f.stats;
     a.V = g.V;
+    a.rv_src = a.rv_w = a.rv_io = a.rv_iv = a.rv_cnt = nullptr;
+    a.pull_frac = kNone;
     return a;
 }
 
@@ -333,7 +446,19 @@ uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t*
     fill_u32(R, g.V, Alg<A>::unreached, s);
     EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, f.delta, f.heavy, R, f.flags, source,
                Alg<A>::at_source);
-    if (W.full) return frontier_loop<A, 0, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
+    if (W.full) {
+        const uint32_t pf = f.delta == 0 && g.E ? pull_frac() : kNone;
+        if (pf != kNone) {
+            ensure_reverse(g, s);
+            a.rv_src = g.rv_src;
+            a.rv_w = g.rv_w;
+            a.rv_io = g.rv_io;
+            a.rv_iv = g.rv_iv;
+            a.rv_cnt = g.rv_cnt;
+            a.pull_frac = pf;
+        }
+        return frontier_loop<A, 0, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
+    }
     return frontier_loop<A, 1, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
 }
 

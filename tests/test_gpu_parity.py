@@ -294,6 +294,29 @@ def test_heavy_gating_many_blocks(evq, algo, monkeypatch):
         assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
 
 
+@pytest.mark.parametrize("frac", ["0", "0.3", "2"])
+@pytest.mark.parametrize("algo", ALGOS)
+def test_pull_step(evq, algo, frac, monkeypatch):
+    # full-window intersection solve pulling in every iteration (0), in the
+    # dense ones (0.3) or never (2): same values and bounds as the oracle, on
+    # small graphs and on one with hubs and many waves per slice
+    monkeypatch.setenv("EVQ_PULL_FRAC", frac)
+    cases = [(synth.config_instance("small", seed=s), 0) for s in (1, 2, 3)]
+    big = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=41)
+    cases.append((big, synth.pick_sources(big, 1, seed=3)[0]))
+    for ci, (inst, src) in enumerate(cases):
+        trip, bits = oracle.replay(inst)
+        want = oracle.window_values(inst, algo, src, 0, inst.K, replayed=(trip, bits))
+        rc_o, ru_o = oracle.bounds(inst.num_vertices, trip, bits, algo, src, 0, inst.K)
+        with _graph(evq, inst) as g:
+            got = gpu_values(g, algo, src, 0, inst.K)
+            rc, ru = gpu_bounds(g, algo, src, 0, inst.K)
+            again = gpu_values(g, algo, src, 0, inst.K)  # reverse CSR reused
+        assert_equal_values(got, want, f"pull {frac} case {ci}")
+        assert_equal_values(again, want, f"pull {frac} case {ci} second query")
+        assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
+
+
 @pytest.mark.parametrize("direct", ["0", "1000000000"])
 @pytest.mark.parametrize("algo", ALGOS)
 def test_relax_task_paths(evq, algo, direct, monkeypatch):
