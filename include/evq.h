@@ -42,8 +42,9 @@
  *                        all-present edges pulls (every vertex takes its best
  *                        all-present in-edge) instead of pushing; the graph's
  *                        reverse CSR (8 bytes per all-present edge) is built
- *                        by the first such query on a graph version
- *                        (default 0.5; above 1: never pull)
+ *                        by the second full-window query on a graph version
+ *                        (the first pushes only; default 0.5; above 1: never
+ *                        pull)
  *   EVQ_LAUNCH_DEPTH=d   frontier iterations kept in flight, 1..32 (default 3)
  *   EVQ_APPEND_REBUILD=1 evq_append rebuilds the versioned graph from all
  *                        held edges and the batch instead of updating it

@@ -39,9 +39,10 @@ Frontier make_frontier(const Graph& g, Workspace& ws, hipStream_t s);
 // all-present in-edges instead.  EVQ_PULL_FRAC (a fraction; above 1 turns the
 // pull step off) overrides the default.  Returns kNone when it is off.
 uint32_t pull_frac();
-// The graph's reverse CSR, built on s the first time (later callers' streams
-// wait for it).
-void ensure_reverse(const Graph& g, hipStream_t s);
+// The graph's reverse CSR if it is there or this is the second call asking
+// for it (then built on s); later callers' streams wait for it.  False: not
+// built yet, push only.
+bool reverse_ready(const Graph& g, hipStream_t s);
 
 // R := values on the window's intersection graph.  Returns the iteration count.
 uint64_t solve_cap(const Graph& g, uint32_t algo, const Window& W, uint32_t source, uint32_t* R, Frontier& f,

@@ -952,6 +952,79 @@ void append_incremental(const Graph& old, Graph* g, const uint32_t* d_ev, uint64
     EVQ_HIP(hipStreamSynchronize(s));
 }
 
+// ------------------------------------------------------------------ reverse CSR
+
+// Reverse CSR of the all-present edges (the pull step of the full-window
+// intersection solve): one radix sort of packed keys dst | src | w, with the
+// edges outside the all-present prefixes given the all-ones key so that they
+// sort last.  One wave per source row (grid-stride).
+template <typename KT>
+__global__ void __launch_bounds__(256) k_rv_keys(const uint32_t* __restrict__ row_ptr,
+                                                 const uint32_t* __restrict__ row_split,
+                                                 const uint32_t* __restrict__ col, const uint32_t* __restrict__ wgt,
+                                                 uint32_t V, int vb, int wb, KT* __restrict__ keys) {
+    const uint32_t lane = lane_id();
+    const uint64_t nw = (uint64_t)gridDim.x * 4;
+    for (uint64_t u = (blockIdx.x * 256ull + threadIdx.x) >> 6; u < V; u += nw) {
+        const uint32_t b = row_ptr[u], m = row_split[u], e = row_ptr[u + 1];
+        for (uint32_t i = b + lane; i < e; i += 64) {
+            KT k = ~(KT)0;
+            if (i < m) k = ((((KT)col[i] << vb) | (KT)u) << wb) | (KT)wgt[i];
+            keys[i] = k;
+        }
+    }
+}
+
+// Sorted keys -> source and weight per in-edge, a head flag where the
+// destination changes, and the in-edge count (written by the last real key).
+template <typename KT>
+__global__ void k_rv_decode(const KT* __restrict__ keys, uint64_t E, int vb, int wb, uint32_t* __restrict__ src,
+                            uint32_t* __restrict__ w, uint32_t* __restrict__ head, uint32_t* __restrict__ cnt) {
+    const KT none = ~(KT)0;
+    const KT vmask = ((KT)1 << vb) - 1, wmask = ((KT)1 << wb) - 1;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < E; i += (uint64_t)gridDim.x * blockDim.x) {
+        const KT k = keys[i];
+        uint32_t h = 0;
+        if (k != none) {
+            src[i] = (uint32_t)((k >> wb) & vmask);
+            w[i] = (uint32_t)(k & wmask);
+            h = (i == 0 || (keys[i - 1] >> (vb + wb)) != (k >> (vb + wb))) ? 1u : 0u;
+            if (i + 1 == E || keys[i + 1] == none) cnt[1] = (uint32_t)(i + 1);
+        }
+        head[i] = h;
+    }
+}
+
+// Heads -> items: first in-edge and destination of every vertex with in-edges.
+template <typename KT>
+__global__ void k_rv_items(const KT* __restrict__ keys, const uint32_t* __restrict__ head,
+                           const uint32_t* __restrict__ pos, uint64_t E, int vb, int wb, uint32_t* __restrict__ io,
+                           uint32_t* __restrict__ iv) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < E; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (head[i]) {
+            io[pos[i]] = (uint32_t)i;
+            iv[pos[i]] = (uint32_t)(keys[i] >> (vb + wb));
+        }
+    }
+}
+
+template <typename KT>
+void reverse_sorted(const Graph& g, int vb, int wb, hipStream_t s, Arena& ar) {
+    const uint64_t E = g.E;
+    KT* keys = ar.alloc<KT>(E);
+    KT* tmp = ar.alloc<KT>(E);
+    EVQ_LAUNCH("reverse_keys", k_rv_keys<KT>, grid_for((uint64_t)g.V * 64, 256, 8192), 256, s, g.row_ptr,
+               g.row_split, g.col, g.wgt, g.V, vb, wb, keys);
+    KT* sorted = radix_sort(keys, tmp, E, 2 * vb + wb + 1, s, ar);
+    uint32_t* head = ar.alloc<uint32_t>(E);
+    uint32_t* pos = ar.alloc<uint32_t>(E);
+    const uint32_t blocks = grid_for(E, 256, 65536);
+    EVQ_LAUNCH("reverse_decode", k_rv_decode<KT>, blocks, 256, s, sorted, E, vb, wb, g.rv_src, g.rv_w, head,
+               g.rv_cnt);
+    scan_exclusive(head, pos, E, g.rv_cnt, s, ar);
+    EVQ_LAUNCH("reverse_items", k_rv_items<KT>, blocks, 256, s, sorted, head, pos, E, vb, wb, g.rv_io, g.rv_iv);
+}
+
 }  // namespace
 
 void free_graph(Graph* g, hipStream_t s) {
@@ -963,6 +1036,15 @@ void free_graph(Graph* g, hipStream_t s) {
     if (g->rv_ready) (void)hipEventDestroy(g->rv_ready);
     for (hipEvent_t e : g->uses) (void)hipEventDestroy(e);
     delete g;
+}
+
+void build_reverse(const Graph& g, hipStream_t s) {
+    fill_u32(g.rv_cnt, 2, 0u, s);
+    if (g.V == 0 || g.E == 0) return;
+    Arena ar(s);
+    const int vb = bits_for(g.V - 1), wb = bits_for(g.maxw);
+    if (2 * vb + wb + 1 <= 64) reverse_sorted<uint64_t>(g, vb, wb, s, ar);
+    else reverse_sorted<u128>(g, vb, wb, s, ar);
 }
 
 Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_batch* batches, uint32_t K,

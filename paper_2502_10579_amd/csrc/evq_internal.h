@@ -60,8 +60,11 @@ struct Graph {
     mutable std::vector<hipEvent_t> uses;
     // Reverse CSR of the edges present in all K snapshots, grouped by
     // destination (the pull step of the full-window intersection solve).  It
-    // is built on first use; later users on other streams wait for rv_ready.
+    // is built by the second query that asks for it (a ring version that
+    // lives for one query or none never pays for it); later users on other
+    // streams wait for rv_ready.
     mutable std::mutex rv_mu;
+    mutable uint32_t rv_asks = 0;
     mutable bool rv_built = false;
     mutable hipEvent_t rv_ready = nullptr;
     mutable uint32_t* rv_src = nullptr;  // source of each in-edge (capacity E)
@@ -183,6 +186,9 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
 // The next version of a graph: snapshot first+K (old newest with batch b
 // applied) replaces snapshot `first` in its mask bit.  `old` is not changed.
 Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s);
+// Fills g's reverse CSR arrays (allocated by the caller: rv_src and rv_w with
+// E entries, rv_io and rv_iv with V, rv_cnt with 2) on s.
+void build_reverse(const Graph& g, hipStream_t s);
 // Releases g's device arrays, ordered on s, and deletes g.
 void free_graph(Graph* g, hipStream_t s);
 // A retired version: its arrays are released on a private stream once every

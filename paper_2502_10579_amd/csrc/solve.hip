@@ -448,8 +448,7 @@ uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t*
                Alg<A>::at_source);
     if (W.full) {
         const uint32_t pf = f.delta == 0 && g.E ? pull_frac() : kNone;
-        if (pf != kNone) {
-            ensure_reverse(g, s);
+        if (pf != kNone && reverse_ready(g, s)) {
             a.rv_src = g.rv_src;
             a.rv_w = g.rv_w;
             a.rv_io = g.rv_io;
