@@ -116,7 +116,7 @@ typedef struct {
     uint32_t reserved;
     uint64_t num_edges;      /* distinct (src, dst, w) triples present in >= 1 snapshot */
     uint64_t num_partial;    /* of those, triples absent from >= 1 snapshot */
-    uint64_t device_bytes;   /* device memory held by the handle */
+    uint64_t device_bytes;   /* device memory held by the handle (with the pull step's reverse CSR once built) */
     double build_ms;         /* wall time of evq_build (or of the last evq_append), host validation included */
     uint64_t first_snapshot; /* global id of the oldest snapshot held (0 until the first evq_append) */
 } evq_graph_info;

@@ -309,9 +309,13 @@ def test_pull_step(evq, algo, frac, monkeypatch):
         want = oracle.window_values(inst, algo, src, 0, inst.K, replayed=(trip, bits))
         rc_o, ru_o = oracle.bounds(inst.num_vertices, trip, bits, algo, src, 0, inst.K)
         with _graph(evq, inst) as g:
-            got = gpu_values(g, algo, src, 0, inst.K)
-            rc, ru = gpu_bounds(g, algo, src, 0, inst.K)
+            got = gpu_values(g, algo, src, 0, inst.K)  # pushes only: the reverse CSR is not built yet
+            held = g.info["device_bytes"]
+            rc, ru = gpu_bounds(g, algo, src, 0, inst.K)  # builds it (unless the pull step is off)
+            grown = g.info["device_bytes"] - held
             again = gpu_values(g, algo, src, 0, inst.K)  # reverse CSR reused
+            assert g.info["device_bytes"] - held == grown
+        assert (grown > 0) == (frac != "2"), (frac, grown)
         assert_equal_values(got, want, f"pull {frac} case {ci}")
         assert_equal_values(again, want, f"pull {frac} case {ci} second query")
         assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
