@@ -13,7 +13,9 @@
 //               into equal contiguous slices, one per wave; a wave finds its
 //               first vertex with a 64-ary search over fo[] and then walks 64
 //               edges per step, each lane locating its edge's vertex with a
-//               binary search over 64 offsets held in registers.
+//               binary search over 64 offsets held in registers.  In the
+//               dense iterations of the full-window intersection solve the
+//               expansion pulls instead (every vertex over its in-edges).
 // Values improve with fire-and-forget uint32 atomicMin/atomicMax after a plain
 // read shows the candidate is better; improved vertices set their bit.
 #include "bounds.h"
@@ -170,8 +172,9 @@ __device__ __forceinline__ int owner_lane(uint32_t off, uint32_t t) {
 // Pull step of the full-window intersection solve.  When most of the graph
 // is in the frontier, pushing costs one atomic per improving edge; instead
 // every vertex takes the best candidate over its all-present in-edges from
-// the current values of their sources (a valid Bellman-Ford step: it only
-// ever lowers a value to that of a real path) and writes it once.  The
+// the current values of their sources (a valid Bellman-Ford step: a value
+// only ever moves to that of a real path, and only when that is better) and
+// writes it once.  The
 // in-edges, grouped by destination, are one range [0, n_in) cut into equal
 // slices per wave as in the push walk; the lanes of a step holding one
 // destination reduce their candidates (segmented scan), and a destination
