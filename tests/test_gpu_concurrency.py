@@ -3,6 +3,8 @@
 * Single queries from several host threads, each on its own stream, equal
   the oracle (frontier loops on different threads and streams share nothing;
   iterations issued past the end of one loop never end the next one early).
+* Full-window queries from several threads racing to build the pull step's
+  reverse CSR equal the oracle.
 * Appends while other threads run single and batched queries: every result
   equals the oracle for the window it was answered on (a query keeps the
   graph version it started on).
@@ -121,3 +123,40 @@ def test_appends_while_querying(evq):
     assert len(results) > 20
     for (a, s, b, L, got) in results:
         assert_equal_values(got, oracle.window_values(inst, a, s, b, L, replayed=rep), f"{(a, s, b, L)}")
+
+
+def test_threads_share_the_reverse_build(evq, monkeypatch):
+    # full-window queries from four threads and streams released together on a
+    # fresh graph, pulling whenever they can: the reverse CSR is built once by
+    # whichever query asks second, the others' streams wait for it
+    import torch
+    monkeypatch.setenv("EVQ_PULL_FRAC", "0")
+    inst = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=41)
+    srcs = synth.pick_sources(inst, 4, seed=3)
+    rep = oracle.replay(inst)
+    V, K = inst.num_vertices, inst.K
+    keys = [(a, s) for a in (oracle.SSSP, oracle.SSWP) for s in srcs]
+    want = {k: oracle.window_values(inst, k[0], k[1], 0, K, replayed=rep) for k in keys}
+    bad = []
+    with evq.Graph.from_instance(inst) as g:
+        start = threading.Barrier(4)
+
+        def worker(tid):
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                start.wait()
+                for r in range(3):
+                    for j in range(len(keys)):
+                        a, s = keys[(j + tid) % len(keys)]
+                        out = g.query(a, s, 0, K, stream=st.cuda_stream)
+                        st.synchronize()
+                        if not np.array_equal(evq.to_u32(out).reshape(V, K), want[(a, s)]):
+                            bad.append((tid, r, a, s))
+        th = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        grown = g.info["device_bytes"]
+    assert not bad, f"wrong results on (thread, round, algo, source): {bad[:5]}"
+    assert grown > 0
