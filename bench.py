@@ -454,6 +454,7 @@ def main():
 
     plain_ms = None
     seq_ms = None
+    push_ms = None
     if not args.no_plain:
         outp = torch.empty_like(out)
         g.query_plain(algo, source, b, L, out=outp)
@@ -475,6 +476,22 @@ def main():
         seq_ms = (time.perf_counter() - t) * 1000.0 / n_plain
         same_seq = bool(torch.equal(out, outp))
         log(f"[bench] sequential per-snapshot evaluation: {seq_ms:.3f} ms/query, identical={same_seq}")
+        # the method with its pull step off (pushes only), against which the plain evaluation, whose kernel
+        # has no pull step, compares on the analysis alone
+        prev = os.environ.get("EVQ_PULL_FRAC")
+        os.environ["EVQ_PULL_FRAC"] = "2"
+        g.query(algo, source, b, L, out=outp)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n_plain):
+            g.query(algo, source, b, L, out=outp)
+        torch.cuda.synchronize()
+        push_ms = (time.perf_counter() - t) * 1000.0 / n_plain
+        if prev is None:
+            del os.environ["EVQ_PULL_FRAC"]
+        else:
+            os.environ["EVQ_PULL_FRAC"] = prev
+        log(f"[bench] method without its pull step: {push_ms:.3f} ms/query, identical={bool(torch.equal(out, outp))}")
 
     # batching leg on the same graph: 64 mixed queries of the batched recipe (algorithm uniform, random
     # source, start in [0, K - 25], length in [25, K] clamped), one call against one at a time
@@ -647,6 +664,8 @@ def main():
         "speedup_vs_plain": (plain_ms / ms) if plain_ms else None,
         "sequential_ms_per_query": seq_ms,
         "speedup_vs_sequential": (seq_ms / ms) if seq_ms else None,
+        "push_only_ms_per_query": push_ms,
+        "speedup_vs_plain_push_only": (plain_ms / push_ms) if (plain_ms and push_ms) else None,
         "build_ms": info["build_ms"],
         "batch_leg": batch_leg,
         "query_stats": st,
