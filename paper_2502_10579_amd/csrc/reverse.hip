@@ -10,7 +10,11 @@ namespace evq {
 uint32_t pull_frac() {
     const char* e = getenv("EVQ_PULL_FRAC");
     double f = 0.5;
-    if (e && *e) f = strtod(e, nullptr);
+    if (e && *e) {
+        char* endp = nullptr;
+        const double v = strtod(e, &endp);
+        if (endp != e) f = v;  // an unreadable value keeps the default
+    }
     if (!(f >= 0.0) || f > 1.0) return kNone;
     return (uint32_t)(f * 1024.0 + 0.5);
 }
