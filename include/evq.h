@@ -27,29 +27,12 @@
  *     ownership.  Device pointers belong to the caller unless stated.
  *   - Edge weights are uint32 >= 1; vertex ids are uint32 < num_vertices.
  *
- * Environment switches (none changes a value, only how the work is
- * scheduled; defaults are the measured best):
- *   EVQ_SPLIT_FRAC, EVQ_SPLIT_MIN   sub-window splitting (see evq_query)
- *   EVQ_DELTA[_ALGO], EVQ_HEAVY[_ALGO]  near/far scheduling of the bound
- *                                   solves (see evq_query)
- *   EVQ_BATCH_LANES/CHUNK/BLOCKS/GROUP/WORKERS  batched execution choices
- *                                   (see evq_batch_config)
- *   EVQ_DIRECT_TASKS=n   reduced subgraphs of at most n relaxation tasks
- *                        have them written by the frontier compaction, larger
- *                        ones by a kernel of their own (default 262144)
- *   EVQ_PULL_FRAC=f      full-window intersection solves: an iteration whose
- *                        frontier holds at least this share of the
- *                        all-present edges pulls (every vertex takes its best
- *                        all-present in-edge) instead of pushing; the graph's
- *                        reverse CSR (8 bytes per all-present edge) is built
- *                        by the second full-window query on a graph version
- *                        (the first pushes only; default 0.5; above 1: never
- *                        pull)
- *   EVQ_LAUNCH_DEPTH=d   frontier iterations kept in flight, 1..32 (default 3)
- *   EVQ_APPEND_REBUILD=1 evq_append rebuilds the versioned graph from all
- *                        held edges and the batch instead of updating it
- *                        incrementally (same result)
- *   EVQ_TRACE_LOOPS=1    print each frontier iteration's count to stderr
+ * Scheduling knobs (none changes a value, only how the work is scheduled;
+ * defaults are the measured best) are the fields of evq_tuning and
+ * evq_batch_config.  Their starting values are read once per process from
+ * the environment variables named beside each field; evq_tuning_set and
+ * evq_batch_config_set replace them for the calls that start afterwards, so
+ * no query reads the environment.
  *
  * Query values (Table 2 edge functions; sentinels are this library's reading
  * where the paper is silent):
@@ -84,6 +67,7 @@ typedef int32_t evq_status;
 #define EVQ_EDEVICE (-4)   /* a HIP runtime call failed */
 #define EVQ_ENOCONV (-5)   /* a frontier loop exceeded its iteration cap */
 #define EVQ_ECANCELED (-6) /* a served query was dropped when its server shut down */
+#define EVQ_EBUSY (-7)     /* a server's queue is full (evq_server_submit): poll, then submit again */
 
 #define EVQ_SSSP 0
 #define EVQ_BFS 1
@@ -108,6 +92,23 @@ typedef struct {
 
 /* Opaque handle; owns the device copy of the versioned graph. */
 typedef struct evq_graph evq_graph;
+
+/*
+ * A caller's device-memory allocator for a graph (evq_build).
+ *   alloc(bytes, ctx): device memory on the current device, at least `bytes`
+ *     (a multiple of 256), 256-byte aligned, or NULL when none is available.
+ *   free(p, ctx): returns a block alloc gave.  The library calls it exactly
+ *     once per block, from the host thread that releases the block, after
+ *     every device operation that uses the block has completed.
+ * The struct is copied; ctx must stay valid until every block is freed (after
+ * evq_free and once no call on the handle is running).  The callbacks must
+ * not call into this library.
+ */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* ctx);
+    void (*free)(void* p, void* ctx);
+    void* ctx;
+} evq_allocator;
 
 typedef struct {
     uint32_t num_vertices;
@@ -148,13 +149,23 @@ typedef struct {
  * the edges present in all K snapshots come first.
  *   num_vertices >= 1; 1 <= K <= 128; base may be NULL when n_base == 0,
  *   likewise del/add when their counts are 0.
+ *   alloc: NULL, or the allocator every device array of the graph comes
+ *   from: the arrays of this version and of every version evq_append makes,
+ *   the pull step's reverse CSR, and the temporaries of the build and of the
+ *   appends.  (Query workspaces and batched results are not graph memory;
+ *   they come from the device's stream-ordered pool either way.)  With NULL
+ *   the graph's arrays come from that pool too.
  * Errors: EVQ_EINVAL (NULL out/batches, id >= num_vertices, w == 0, K out of
- * range), EVQ_ERANGE (more than 2^32 - 2 events or union edges),
- * EVQ_ENOMEM, EVQ_EDEVICE.  On success *out owns its device memory until
- * evq_free.  The call synchronises `stream`.
+ * range), EVQ_ERANGE (more than 2^32 - 2 events or union edges), EVQ_ENOMEM
+ * (the allocator returned NULL, or the pool is exhausted), EVQ_EDEVICE.  On
+ * failure *out is NULL and every block taken from `alloc` has been returned
+ * to it.  With `alloc`, its first request (the event buffer) comes before any
+ * device call.  On success *out owns its device memory until evq_free.  The
+ * call synchronises `stream`.
  */
 evq_status evq_build(uint32_t num_vertices, const evq_edge* base, uint64_t n_base,
-                     const evq_batch* batches, uint32_t K, void* stream, evq_graph** out);
+                     const evq_batch* batches, uint32_t K, const evq_allocator* alloc, void* stream,
+                     evq_graph** out);
 
 /* Sizes of a built graph.  EVQ_EINVAL on NULL arguments. */
 evq_status evq_graph_info_get(const evq_graph* g, evq_graph_info* info);
@@ -289,6 +300,10 @@ evq_status evq_query_batch(const evq_graph* g, const evq_query_desc* q, uint32_t
  */
 evq_status evq_result_expand(const evq_result* r, uint32_t* d_values, void* stream);
 
+/* The same call as evq_result_expand, under the name the problem statement's
+ * interface gives it (compact result -> dense values). */
+evq_status evq_expand(const evq_result* r, uint32_t* d_values, void* stream);
+
 /*
  * Release a result's device memory, ordered on `stream` (work already queued
  * there that reads the result completes first; work on other streams must be
@@ -297,9 +312,61 @@ evq_status evq_result_expand(const evq_result* r, uint32_t* d_values, void* stre
  */
 evq_status evq_result_free(evq_result* r, void* stream);
 
-/* Read / replace the execution choices used by evq_query_batch on this process. */
+/* Read / replace the execution choices used by evq_query_batch on this
+ * process (starting values: EVQ_BATCH_LANES, _CHUNK, _BLOCKS, _GROUP; the
+ * worker count, EVQ_BATCH_WORKERS, is read once when the pool starts). */
 evq_status evq_batch_config_get(evq_batch_config* c);
 evq_status evq_batch_config_set(const evq_batch_config* c);
+
+/*
+ * Scheduling of single queries, appends and frontier loops.
+ *   pull_frac     EVQ_PULL_FRAC: full-window intersection solves: an
+ *                 iteration whose frontier holds at least this share of the
+ *                 all-present edges pulls (every vertex takes its best
+ *                 all-present in-edge) instead of pushing; the graph's
+ *                 reverse CSR (8 bytes per all-present edge) is built by the
+ *                 second full-window query on a graph version (the first
+ *                 pushes only).  Default 0.5; above 1 (or negative): never.
+ *   split_frac    EVQ_SPLIT_FRAC: a window with more than split_frac * V
+ *                 unstable vertices is answered as two halves, each with its
+ *                 own bounds, to depth 4 (default 0: off).
+ *   split_min     EVQ_SPLIT_MIN: smallest half (default 8, >= 1).
+ *   launch_depth  EVQ_LAUNCH_DEPTH: frontier iterations kept in flight, 1..32
+ *                 (default 3).
+ *   direct_tasks  EVQ_DIRECT_TASKS: reduced subgraphs of at most this many
+ *                 relaxation tasks have them written by the frontier
+ *                 compaction, larger ones by a kernel of their own (default
+ *                 262144).
+ *   append_rebuild EVQ_APPEND_REBUILD: nonzero makes evq_append rebuild the
+ *                 versioned graph from all held edges and the batch instead
+ *                 of updating it incrementally (same result).
+ *   trace_loops   EVQ_TRACE_LOOPS: nonzero prints each frontier iteration's
+ *                 count to stderr.
+ *   delta[a], heavy[a]  EVQ_DELTA_<ALGO> (else EVQ_DELTA), EVQ_HEAVY_<ALGO>
+ *                 (else EVQ_HEAVY), per algorithm EVQ_SSSP .. EVQ_VITERBI:
+ *                 with delta > 0 the bound solves defer vertices whose order
+ *                 key is not below a threshold that steps by delta
+ *                 (near/far); with heavy > 0 as well only vertices with at
+ *                 least heavy edges are deferred and the threshold follows
+ *                 the frontier's best key plus delta (default 0: off).
+ * evq_tuning_set: EVQ_EINVAL on NULL, launch_depth outside 1..32 or
+ * split_min == 0; calls already running keep the values they started with.
+ */
+typedef struct {
+    double pull_frac;
+    double split_frac;
+    uint32_t split_min;
+    uint32_t launch_depth;
+    uint32_t direct_tasks;
+    uint32_t append_rebuild;
+    uint32_t trace_loops;
+    uint32_t delta[5];
+    uint32_t heavy[5];
+    uint32_t reserved;
+} evq_tuning;
+
+evq_status evq_tuning_get(evq_tuning* t);
+evq_status evq_tuning_set(const evq_tuning* t);
 
 /*
  * Autotune: run evq_query_batch on the caller's n queries once to warm up,
@@ -353,6 +420,8 @@ typedef struct {
     uint32_t max_inflight;   /* admitted and not completed (0: 256) */
     uint32_t max_groups;     /* group bound solves running at once (0: 2) */
     uint64_t mem_budget;     /* device bytes, by estimate (0: a quarter of the free memory at creation) */
+    uint32_t max_queued;     /* queries waiting for admission; submit returns EVQ_EBUSY beyond (0: 65536) */
+    uint32_t reserved;
 } evq_server_config;
 
 typedef struct {
@@ -372,7 +441,8 @@ typedef struct {
 evq_status evq_server_create(evq_graph* g, const evq_server_config* c, evq_server** out);
 
 /* Queue a query; *ticket identifies its completion.  EVQ_EINVAL / EVQ_ERANGE
- * on a bad algorithm, source >= V or win_len == 0. */
+ * on a bad algorithm, source >= V or win_len == 0; EVQ_EBUSY when max_queued
+ * queries already wait (nothing is queued then). */
 evq_status evq_server_submit(evq_server* s, uint32_t algo, uint32_t source, uint32_t win_len, uint64_t* ticket);
 
 /* Move up to cap completions to out (waiting up to wait_ms for the first); returns their number. */

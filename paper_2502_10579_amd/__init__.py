@@ -18,8 +18,9 @@ ALGOS = {"sssp": SSSP, "bfs": BFS, "sswp": SSWP, "ssnp": SSNP, "viterbi": VITERB
 INF = 0xFFFFFFFF
 
 EVQ_OK, EVQ_EINVAL, EVQ_ERANGE, EVQ_ENOMEM, EVQ_EDEVICE, EVQ_ENOCONV = 0, -1, -2, -3, -4, -5
+EVQ_ECANCELED, EVQ_EBUSY = -6, -7
 _STATUS = {EVQ_EINVAL: "EINVAL", EVQ_ERANGE: "ERANGE", EVQ_ENOMEM: "ENOMEM", EVQ_EDEVICE: "EDEVICE",
-           EVQ_ENOCONV: "ENOCONV"}
+           EVQ_ENOCONV: "ENOCONV", EVQ_ECANCELED: "ECANCELED", EVQ_EBUSY: "EBUSY"}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first (python paper_2502_10579_amd/_build.py)")
@@ -32,6 +33,15 @@ class Edge(ctypes.Structure):
 class Batch(ctypes.Structure):
     _fields_ = [("dels", ctypes.POINTER(Edge)), ("n_del", ctypes.c_uint64),
                 ("adds", ctypes.POINTER(Edge)), ("n_add", ctypes.c_uint64)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """evq_allocator: the caller's device allocator for a graph's arrays."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -74,7 +84,8 @@ class BatchConfig(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
-                ("max_groups", ctypes.c_uint32), ("mem_budget", ctypes.c_uint64)]
+                ("max_groups", ctypes.c_uint32), ("mem_budget", ctypes.c_uint64), ("max_queued", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class Completion(ctypes.Structure):
@@ -82,6 +93,13 @@ class Completion(ctypes.Structure):
                 ("t_arrival_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double), ("t_bounds_ms", ctypes.c_double),
                 ("t_done_ms", ctypes.c_double),
                 ("n_unstable", ctypes.c_uint64), ("iters_relax", ctypes.c_uint64), ("result", ResultC)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("pull_frac", ctypes.c_double), ("split_frac", ctypes.c_double), ("split_min", ctypes.c_uint32),
+                ("launch_depth", ctypes.c_uint32), ("direct_tasks", ctypes.c_uint32),
+                ("append_rebuild", ctypes.c_uint32), ("trace_loops", ctypes.c_uint32),
+                ("delta", ctypes.c_uint32 * 5), ("heavy", ctypes.c_uint32 * 5), ("reserved", ctypes.c_uint32)]
 
 
 class KernelTime(ctypes.Structure):
@@ -92,7 +110,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 _P = ctypes.c_void_p
 _lib.evq_build.restype = ctypes.c_int32
 _lib.evq_build.argtypes = [ctypes.c_uint32, ctypes.POINTER(Edge), ctypes.c_uint64, ctypes.POINTER(Batch),
-                           ctypes.c_uint32, _P, ctypes.POINTER(_P)]
+                           ctypes.c_uint32, ctypes.POINTER(Allocator), _P, ctypes.POINTER(_P)]
 _lib.evq_graph_info_get.restype = ctypes.c_int32
 _lib.evq_graph_info_get.argtypes = [_P, ctypes.POINTER(GraphInfo)]
 _lib.evq_graph_export.restype = ctypes.c_int32
@@ -107,8 +125,9 @@ _lib.evq_query_bounds.argtypes = [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c
 _lib.evq_query_batch.restype = ctypes.c_int32
 _lib.evq_query_batch.argtypes = [_P, ctypes.POINTER(QueryDesc), ctypes.c_uint32, ctypes.POINTER(ResultC),
                                  ctypes.POINTER(QueryStats), _P]
-_lib.evq_result_expand.restype = ctypes.c_int32
-_lib.evq_result_expand.argtypes = [ctypes.POINTER(ResultC), _P, _P]
+for _name in ("evq_result_expand", "evq_expand"):
+    getattr(_lib, _name).restype = ctypes.c_int32
+    getattr(_lib, _name).argtypes = [ctypes.POINTER(ResultC), _P, _P]
 _lib.evq_result_free.restype = ctypes.c_int32
 _lib.evq_result_free.argtypes = [ctypes.POINTER(ResultC), _P]
 _lib.evq_batch_config_get.restype = ctypes.c_int32
@@ -141,14 +160,18 @@ _lib.evq_timing_reset.restype = None
 _lib.evq_timing_reset.argtypes = []
 _lib.evq_timing_report.restype = ctypes.c_int
 _lib.evq_timing_report.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int]
+_lib.evq_tuning_get.restype = ctypes.c_int32
+_lib.evq_tuning_get.argtypes = [ctypes.POINTER(Tuning)]
+_lib.evq_tuning_set.restype = ctypes.c_int32
+_lib.evq_tuning_set.argtypes = [ctypes.POINTER(Tuning)]
 _lib.evq_gather_ceiling.restype = ctypes.c_int32
 _lib.evq_gather_ceiling.argtypes = [_P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), _P]
 
 EXPORTED = ["evq_build", "evq_graph_info_get", "evq_graph_export", "evq_query", "evq_query_bounds",
             "evq_query_plain", "evq_query_sequential", "evq_query_batch", "evq_result_expand", "evq_result_free",
-            "evq_batch_config_get", "evq_batch_config_set", "evq_batch_autotune", "evq_append", "evq_server_create",
+            "evq_batch_config_get", "evq_batch_config_set", "evq_batch_autotune", "evq_expand", "evq_append", "evq_server_create",
             "evq_server_submit", "evq_server_poll", "evq_server_pending", "evq_server_destroy", "evq_free", "evq_last_error", "evq_timing_enable",
-            "evq_timing_reset", "evq_timing_report", "evq_gather_ceiling"]
+            "evq_timing_reset", "evq_timing_report", "evq_gather_ceiling", "evq_tuning_get", "evq_tuning_set"]
 
 
 class EvqError(RuntimeError):
@@ -187,7 +210,9 @@ def _ptr(t):
 class Graph:
     """Versioned graph of K snapshots resident on the current device (evq_build)."""
 
-    def __init__(self, num_vertices, base, dels, adds, stream=None):
+    def __init__(self, num_vertices, base, dels, adds, stream=None, allocator=None):
+        """allocator: None, or an Allocator whose callbacks stay referenced by the caller for the
+        graph's whole life (evq_build's `alloc`)."""
         if len(dels) != len(adds):
             raise ValueError("dels and adds must have one entry per batch")
         keep = []
@@ -200,8 +225,11 @@ class Graph:
             keep += [d, a]
             batches[i] = Batch(dp, len(d), ap, len(a))
         h = ctypes.c_void_p()
-        _check(_lib.evq_build(num_vertices, bp, len(b), batches, len(dels), _stream(stream), ctypes.byref(h)))
+        _check(_lib.evq_build(num_vertices, bp, len(b), batches, len(dels),
+                              ctypes.byref(allocator) if allocator is not None else None, _stream(stream),
+                              ctypes.byref(h)))
         self._h = h
+        self._allocator = allocator
         self.num_vertices = num_vertices
         self.K = len(dels)
 
@@ -365,7 +393,7 @@ class Result:
             out = torch.empty((V, L), dtype=torch.int32, device="cuda")
         if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous() or out.numel() != V * L:
             raise ValueError("out must be a contiguous int32 CUDA tensor of V * L elements")
-        _check(_lib.evq_result_expand(ctypes.byref(self._c), _ptr(out), _stream(stream)))
+        _check(_lib.evq_expand(ctypes.byref(self._c), _ptr(out), _stream(stream)))
         return out
 
     def free(self, stream=None):
@@ -382,8 +410,9 @@ class Result:
 class Server:
     """Query server over a graph (evq_server_*): mode "batch" (continuous batching) or "plain" (one at a time)."""
 
-    def __init__(self, graph, mode="batch", max_batch=0, max_inflight=0, max_groups=0, mem_budget=0):
-        cfg = ServerConfig({"batch": 0, "plain": 1}[mode], max_batch, max_inflight, max_groups, mem_budget)
+    def __init__(self, graph, mode="batch", max_batch=0, max_inflight=0, max_groups=0, mem_budget=0, max_queued=0):
+        cfg = ServerConfig({"batch": 0, "plain": 1}[mode], max_batch, max_inflight, max_groups, mem_budget,
+                           max_queued, 0)
         h = ctypes.c_void_p()
         _check(_lib.evq_server_create(graph._h, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -442,6 +471,49 @@ def batch_config() -> dict:
 def set_batch_config(lanes=0, chunk=0, blocks=0, group=0):
     """Execution choices of query_batch (0 keeps the current value)."""
     _check(_lib.evq_batch_config_set(ctypes.byref(BatchConfig(lanes, chunk, blocks, group))))
+
+
+def get_tuning() -> dict:
+    """Scheduling knobs of single queries, appends and frontier loops (evq_tuning_get)."""
+    t = Tuning()
+    _check(_lib.evq_tuning_get(ctypes.byref(t)))
+    d = {k: getattr(t, k) for k, _ in Tuning._fields_ if k != "reserved"}
+    d["delta"], d["heavy"] = list(t.delta), list(t.heavy)
+    return d
+
+
+def set_tuning(**kw):
+    """Replace some scheduling knobs (evq_tuning_set); the others keep their values.
+    delta / heavy may be one number (every algorithm) or five."""
+    cur = get_tuning()
+    for k, v in kw.items():
+        if k not in cur:
+            raise KeyError(k)
+        if k in ("delta", "heavy") and not isinstance(v, (list, tuple)):
+            v = [v] * 5
+        cur[k] = v
+    t = Tuning()
+    for k, v in cur.items():
+        if k in ("delta", "heavy"):
+            getattr(t, k)[:] = [int(x) for x in v]
+        else:
+            setattr(t, k, v)
+    _check(_lib.evq_tuning_set(ctypes.byref(t)))
+
+
+class tuning:
+    """Context manager: set scheduling knobs for the block, restore them after."""
+
+    def __init__(self, **kw):
+        self.kw = kw
+
+    def __enter__(self):
+        self.prev = get_tuning()
+        set_tuning(**self.kw)
+        return self
+
+    def __exit__(self, *a):
+        set_tuning(**self.prev)
 
 
 def to_u32(t) -> np.ndarray:

@@ -64,7 +64,7 @@ evq_status make_window(const evq::Graph& g, uint32_t algo, uint32_t source, uint
 extern "C" {
 
 evq_status evq_build(uint32_t num_vertices, const evq_edge* base, uint64_t n_base, const evq_batch* batches,
-                     uint32_t K, void* stream, evq_graph** out) {
+                     uint32_t K, const evq_allocator* alloc, void* stream, evq_graph** out) {
     g_last_error.clear();
     if (!out) return bad(EVQ_EINVAL, "out is NULL");
     *out = nullptr;
@@ -72,8 +72,9 @@ evq_status evq_build(uint32_t num_vertices, const evq_edge* base, uint64_t n_bas
     if (K == 0 || K > EVQ_MAX_SNAPSHOTS) return bad(EVQ_EINVAL, "K must be in [1, 128]");
     if (!batches) return bad(EVQ_EINVAL, "batches is NULL");
     if (n_base && !base) return bad(EVQ_EINVAL, "base is NULL with n_base > 0");
+    if (alloc && (!alloc->alloc || !alloc->free)) return bad(EVQ_EINVAL, "allocator without alloc or free");
     try {
-        evq::Graph* g = evq::build_graph(num_vertices, base, n_base, batches, K, (hipStream_t)stream);
+        evq::Graph* g = evq::build_graph(num_vertices, base, n_base, batches, K, alloc, (hipStream_t)stream);
         std::shared_ptr<const evq::Graph> sp;
         try {
             sp = std::shared_ptr<const evq::Graph>(g, evq::release_graph);
@@ -285,6 +286,28 @@ evq_status evq_result_expand(const evq_result* r, uint32_t* d_values, void* stre
     } catch (...) {
         return guard_exc();
     }
+}
+
+evq_status evq_tuning_get(evq_tuning* t) {
+    g_last_error.clear();
+    if (!t) return bad(EVQ_EINVAL, "NULL argument");
+    *t = evq::tuning();
+    return EVQ_OK;
+}
+
+evq_status evq_tuning_set(const evq_tuning* t) {
+    g_last_error.clear();
+    if (!t) return bad(EVQ_EINVAL, "NULL argument");
+    try {
+        evq::set_tuning(*t);
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
+evq_status evq_expand(const evq_result* r, uint32_t* d_values, void* stream) {
+    return evq_result_expand(r, d_values, stream);
 }
 
 evq_status evq_result_free(evq_result* r, void* stream) {

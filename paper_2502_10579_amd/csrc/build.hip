@@ -331,11 +331,11 @@ void finish_build(Graph* g, KT* sorted, uint64_t N, KeyLayout L, uint64_t* mtmp,
     ar.release(pos);
     ar.release(sorted);
 
-    g->row_ptr = (uint32_t*)stream_alloc(((uint64_t)g->V + 1) * 4, s);
-    g->row_split = (uint32_t*)stream_alloc((uint64_t)g->V * 4, s);
-    g->col = (uint32_t*)stream_alloc(E * 4, s);
-    g->wgt = (uint32_t*)stream_alloc(E * 4, s);
-    g->mask = (uint64_t*)stream_alloc(E * 8 * MW, s);
+    g->row_ptr = (uint32_t*)graph_alloc(*g, ((uint64_t)g->V + 1) * 4, s);
+    g->row_split = (uint32_t*)graph_alloc(*g, (uint64_t)g->V * 4, s);
+    g->col = (uint32_t*)graph_alloc(*g, E * 4, s);
+    g->wgt = (uint32_t*)graph_alloc(*g, E * 4, s);
+    g->mask = (uint64_t*)graph_alloc(*g, E * 8 * MW, s);
     g->bytes = ((uint64_t)g->V + 1) * 4 + (uint64_t)g->V * 4 + E * (8 + 8 * MW);
 
     EVQ_LAUNCH("build_row_ptr", k_row_ptr, grid_for(E + 1, 256), 256, s, c_src, E, g->V, g->row_ptr);
@@ -344,10 +344,10 @@ void finish_build(Graph* g, KT* sorted, uint64_t N, KeyLayout L, uint64_t* mtmp,
     EVQ_HIP(hipStreamSynchronize(s));
     const uint64_t n_full = mb.h[0];
     g->n_partial = E - n_full;
-    g->p_src = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
-    g->p_dst = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
-    g->p_w = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
-    g->p_mask = (uint64_t*)stream_alloc(g->n_partial * 8 * MW + 16, s);
+    g->p_src = (uint32_t*)graph_alloc(*g, g->n_partial * 4 + 4, s);
+    g->p_dst = (uint32_t*)graph_alloc(*g, g->n_partial * 4 + 4, s);
+    g->p_w = (uint32_t*)graph_alloc(*g, g->n_partial * 4 + 4, s);
+    g->p_mask = (uint64_t*)graph_alloc(*g, g->n_partial * 8 * MW + 16, s);
     g->bytes += g->n_partial * (12 + 8 * MW);
     if (E > 0)
         EVQ_LAUNCH("build_partition", k_partition<MW>, grid_for(E, 256), 256, s, c_src, c_dst, c_w, c_mask, c_full, fb,
@@ -906,11 +906,10 @@ void append_incremental(const Graph& old, Graph* g, const uint32_t* d_ev, uint64
 
     // new row lengths and starts
     NewCsr<MW> o;
-    o.rp = (uint32_t*)stream_alloc(((uint64_t)V + 1) * 4, s);
+    g->row_ptr = o.rp = (uint32_t*)graph_alloc(*g, ((uint64_t)V + 1) * 4, s);
     o.nf = ar.alloc<uint32_t>((uint64_t)V + 1);
     o.fx = ar.alloc<uint32_t>((uint64_t)V + 1);
     uint32_t* len = ar.alloc<uint32_t>((uint64_t)V + 1);
-    g->row_ptr = o.rp;
     EVQ_LAUNCH("append_rows_new", k_new_rows, grid_for(V, 256), 256, s, old.row_ptr, old.row_split, cS, icnt, V, len,
                o.nf);
     scan_exclusive(len, o.rp, V, o.rp + V, s, ar);
@@ -921,14 +920,14 @@ void append_incremental(const Graph& old, Graph* g, const uint32_t* d_ev, uint64
     const uint64_t E2 = mb.h[0], NF = mb.h[1];
     g->E = E2;
     g->n_partial = E2 - NF;
-    g->row_split = (uint32_t*)stream_alloc((uint64_t)V * 4, s);
-    g->col = o.col = (uint32_t*)stream_alloc(E2 * 4 + 4, s);
-    g->wgt = o.wgt = (uint32_t*)stream_alloc(E2 * 4 + 4, s);
-    g->mask = o.mask = (uint64_t*)stream_alloc(E2 * 8 * MW + 16, s);
-    g->p_src = o.p_src = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
-    g->p_dst = o.p_dst = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
-    g->p_w = o.p_w = (uint32_t*)stream_alloc(g->n_partial * 4 + 4, s);
-    g->p_mask = o.p_mask = (uint64_t*)stream_alloc(g->n_partial * 8 * MW + 16, s);
+    g->row_split = (uint32_t*)graph_alloc(*g, (uint64_t)V * 4, s);
+    g->col = o.col = (uint32_t*)graph_alloc(*g, E2 * 4 + 4, s);
+    g->wgt = o.wgt = (uint32_t*)graph_alloc(*g, E2 * 4 + 4, s);
+    g->mask = o.mask = (uint64_t*)graph_alloc(*g, E2 * 8 * MW + 16, s);
+    g->p_src = o.p_src = (uint32_t*)graph_alloc(*g, g->n_partial * 4 + 4, s);
+    g->p_dst = o.p_dst = (uint32_t*)graph_alloc(*g, g->n_partial * 4 + 4, s);
+    g->p_w = o.p_w = (uint32_t*)graph_alloc(*g, g->n_partial * 4 + 4, s);
+    g->p_mask = o.p_mask = (uint64_t*)graph_alloc(*g, g->n_partial * 8 * MW + 16, s);
     g->bytes = ((uint64_t)V + 1) * 4 + (uint64_t)V * 4 + E2 * (8 + 8 * MW) + g->n_partial * (12 + 8 * MW);
 
     // 5. placement
@@ -1031,8 +1030,15 @@ void free_graph(Graph* g, hipStream_t s) {
     if (!g) return;
     void* arrays[14] = {g->row_ptr, g->row_split, g->col,   g->wgt,   g->mask,  g->p_src, g->p_dst,
                         g->p_w,     g->p_mask,    g->rv_src, g->rv_w, g->rv_io, g->rv_iv, g->rv_cnt};
-    for (void* p : arrays)
-        if (p) (void)hipFreeAsync(p, s);
+    if (g->has_ua) {
+        // the caller's allocator frees on the host: the work on s that uses the arrays completes first
+        if (s) (void)hipStreamSynchronize(s);
+        for (void* p : arrays)
+            if (p) g->ua.free(p, g->ua.ctx);
+    } else {
+        for (void* p : arrays)
+            if (p) (void)hipFreeAsync(p, s);
+    }
     if (g->rv_ready) (void)hipEventDestroy(g->rv_ready);
     for (hipEvent_t e : g->uses) (void)hipEventDestroy(e);
     delete g;
@@ -1041,14 +1047,14 @@ void free_graph(Graph* g, hipStream_t s) {
 void build_reverse(const Graph& g, hipStream_t s) {
     fill_u32(g.rv_cnt, 2, 0u, s);
     if (g.V == 0 || g.E == 0) return;
-    Arena ar(s);
+    Arena ar(s, g.has_ua ? &g.ua : nullptr);
     const int vb = bits_for(g.V - 1), wb = bits_for(g.maxw);
     if (2 * vb + wb + 1 <= 64) reverse_sorted<uint64_t>(g, vb, wb, s, ar);
     else reverse_sorted<u128>(g, vb, wb, s, ar);
 }
 
 Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_batch* batches, uint32_t K,
-                   hipStream_t s) {
+                   const evq_allocator* ua, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     // ---- validation (host, before any device work)
     uint64_t maxw = 1;
@@ -1070,21 +1076,27 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
     }
     if (N >= 0xFFFFFFFEull) fail(EVQ_ERANGE, "more than 2^32 - 2 edge events");
 
-    int dev = 0;
-    EVQ_HIP(hipGetDevice(&dev));
-    init_mempool(dev);
     Graph* g = new Graph();
     g->V = V;
     g->K = K;
     g->MW = K > 64 ? 2 : 1;
     g->maxw = (uint32_t)maxw;
-    g->device = dev;
+    if (ua) {
+        g->ua = *ua;
+        g->has_ua = true;
+    }
     try {
-        Arena ar(s);
+        Arena ar(s, g->has_ua ? &g->ua : nullptr);
+        // A caller's allocator is asked for the event buffer before any device call.
+        uint32_t* d_ev = g->has_ua ? ar.alloc<uint32_t>(3 * (N + 1)) : nullptr;
+        int dev = 0;
+        EVQ_HIP(hipGetDevice(&dev));
+        init_mempool(dev);
+        g->device = dev;
         // ---- events to the device: [base | del_0 | add_0 | del_1 | add_1 | ...]
         const int nseg = 2 * (int)K + 2;
         std::vector<uint64_t> seg(nseg);
-        uint32_t* d_ev = ar.alloc<uint32_t>(3 * (N + 1));
+        if (!d_ev) d_ev = ar.alloc<uint32_t>(3 * (N + 1));
         uint64_t at = 0;
         auto put = [&](const evq_edge* e, uint64_t n) {
             if (n) EVQ_HIP(hipMemcpyAsync(d_ev + 3 * at, e, n * sizeof(evq_edge), hipMemcpyHostToDevice, s));
@@ -1109,17 +1121,17 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
         if (N == 0) {
             g->E = 0;
             g->n_partial = 0;
-            g->row_ptr = (uint32_t*)stream_alloc(((uint64_t)V + 1) * 4, s);
-            g->row_split = (uint32_t*)stream_alloc((uint64_t)V * 4, s);
+            g->row_ptr = (uint32_t*)graph_alloc(*g, ((uint64_t)V + 1) * 4, s);
+            g->row_split = (uint32_t*)graph_alloc(*g, (uint64_t)V * 4, s);
             fill_u32(g->row_ptr, (uint64_t)V + 1, 0u, s);
             fill_u32(g->row_split, V, 0u, s);
-            g->col = (uint32_t*)stream_alloc(4, s);
-            g->wgt = (uint32_t*)stream_alloc(4, s);
-            g->mask = (uint64_t*)stream_alloc(16, s);
-            g->p_src = (uint32_t*)stream_alloc(4, s);
-            g->p_dst = (uint32_t*)stream_alloc(4, s);
-            g->p_w = (uint32_t*)stream_alloc(4, s);
-            g->p_mask = (uint64_t*)stream_alloc(16, s);
+            g->col = (uint32_t*)graph_alloc(*g, 4, s);
+            g->wgt = (uint32_t*)graph_alloc(*g, 4, s);
+            g->mask = (uint64_t*)graph_alloc(*g, 16, s);
+            g->p_src = (uint32_t*)graph_alloc(*g, 4, s);
+            g->p_dst = (uint32_t*)graph_alloc(*g, 4, s);
+            g->p_w = (uint32_t*)graph_alloc(*g, 4, s);
+            g->p_mask = (uint64_t*)graph_alloc(*g, 16, s);
             g->bytes = ((uint64_t)V + 1) * 8;
             EVQ_HIP(hipStreamSynchronize(s));
         } else if (L.total() <= 64) {
@@ -1140,12 +1152,9 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
     return g;
 }
 
-// EVQ_APPEND_REBUILD=1 rebuilds the versioned graph from all held edges and
-// the batch (one sort of everything) instead of the incremental append.
-bool append_rebuild() {
-    const char* e = getenv("EVQ_APPEND_REBUILD");
-    return e && *e && *e != '0';
-}
+// evq_tuning.append_rebuild rebuilds the versioned graph from all held edges
+// and the batch (one sort of everything) instead of the incremental append.
+bool append_rebuild() { return tuning().append_rebuild != 0; }
 
 Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
@@ -1172,8 +1181,10 @@ Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
     g->first = old.first + 1;
     g->maxw = (uint32_t)maxw;
     g->device = old.device;
+    g->ua = old.ua;
+    g->has_ua = old.has_ua;
     try {
-        Arena ar(s);
+        Arena ar(s, g->has_ua ? &g->ua : nullptr);
         uint32_t* d_ev = ar.alloc<uint32_t>(3 * (n_ev + 1));
         if (b.n_del) EVQ_HIP(hipMemcpyAsync(d_ev, b.del, b.n_del * sizeof(evq_edge), hipMemcpyHostToDevice, s));
         if (b.n_add)
@@ -1186,17 +1197,17 @@ Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
         if (old.E + n_ev == 0) {
             g->E = 0;
             g->n_partial = 0;
-            g->row_ptr = (uint32_t*)stream_alloc(((uint64_t)V + 1) * 4, s);
-            g->row_split = (uint32_t*)stream_alloc((uint64_t)V * 4, s);
+            g->row_ptr = (uint32_t*)graph_alloc(*g, ((uint64_t)V + 1) * 4, s);
+            g->row_split = (uint32_t*)graph_alloc(*g, (uint64_t)V * 4, s);
             fill_u32(g->row_ptr, (uint64_t)V + 1, 0u, s);
             fill_u32(g->row_split, V, 0u, s);
-            g->col = (uint32_t*)stream_alloc(4, s);
-            g->wgt = (uint32_t*)stream_alloc(4, s);
-            g->mask = (uint64_t*)stream_alloc(16, s);
-            g->p_src = (uint32_t*)stream_alloc(4, s);
-            g->p_dst = (uint32_t*)stream_alloc(4, s);
-            g->p_w = (uint32_t*)stream_alloc(4, s);
-            g->p_mask = (uint64_t*)stream_alloc(16, s);
+            g->col = (uint32_t*)graph_alloc(*g, 4, s);
+            g->wgt = (uint32_t*)graph_alloc(*g, 4, s);
+            g->mask = (uint64_t*)graph_alloc(*g, 16, s);
+            g->p_src = (uint32_t*)graph_alloc(*g, 4, s);
+            g->p_dst = (uint32_t*)graph_alloc(*g, 4, s);
+            g->p_w = (uint32_t*)graph_alloc(*g, 4, s);
+            g->p_mask = (uint64_t*)graph_alloc(*g, 16, s);
             g->bytes = ((uint64_t)V + 1) * 8;
         } else if (!append_rebuild()) {
             // incremental: event keys src | dst | w | tag

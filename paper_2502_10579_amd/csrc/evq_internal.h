@@ -54,6 +54,10 @@ struct Graph {
     int device = 0;
     uint64_t bytes = 0;
     double build_ms = 0.0;
+    // The caller's allocator (evq_build): every array of every version, the
+    // reverse CSR and the temporaries of builds and appends come from it.
+    evq_allocator ua{};
+    bool has_ua = false;
     // Events recorded on the streams of calls that read this version; its
     // arrays are released (stream-ordered, after all of them) when it retires.
     mutable std::mutex use_mu;
@@ -90,9 +94,11 @@ struct UseGuard {
 // ------------------------------------------------------------------ memory
 
 // Per-call device temporaries, stream-ordered (hipMallocAsync / hipFreeAsync).
+// With a caller's allocator, buffers come from it and are returned to it
+// once the work queued on the stream has completed.
 class Arena {
   public:
-    explicit Arena(hipStream_t s) : s_(s) {}
+    explicit Arena(hipStream_t s, const evq_allocator* ua = nullptr) : s_(s), ua_(ua) {}
     ~Arena();
     Arena(const Arena&) = delete;
     Arena& operator=(const Arena&) = delete;
@@ -106,9 +112,16 @@ class Arena {
 
   private:
     hipStream_t s_;
+    const evq_allocator* ua_;
     std::vector<void*> ptrs_;
     uint64_t bytes_ = 0;
 };
+
+// Device memory of a graph version: from the graph's caller allocator when it
+// has one (throws EVQ_ENOMEM when that returns NULL), else from the device's
+// stream-ordered pool.  graph_free returns one such array.
+void* graph_alloc(const Graph& g, uint64_t bytes, hipStream_t s);
+void graph_free(const Graph& g, void* p, hipStream_t s);
 
 // Query workspace: device buffers kept between queries on one host thread
 // and stream, grown on demand (growth waits for the stream).  Queries on one
@@ -147,6 +160,13 @@ struct Mailbox {
     static Mailbox& get();
 };
 
+// ------------------------------------------------------------------ tuning
+
+// Scheduling knobs: read from the environment once per process, replaced by
+// evq_tuning_set; each call takes a copy.
+evq_tuning tuning();
+void set_tuning(const evq_tuning& t);
+
 // ------------------------------------------------------------------ launches
 
 bool timing_on();
@@ -182,7 +202,7 @@ void scan_exclusive(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* d_t
 void fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 
 Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_batch* batches, uint32_t K,
-                   hipStream_t s);
+                   const evq_allocator* ua, hipStream_t s);
 // The next version of a graph: snapshot first+K (old newest with batch b
 // applied) replaces snapshot `first` in its mask bit.  `old` is not changed.
 Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s);

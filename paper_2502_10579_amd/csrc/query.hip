@@ -35,11 +35,8 @@ constexpr uint32_t kRowChunk = 1024;   // union-row edges per compaction task
 #endif
 constexpr uint32_t kRelaxChunk = EVQ_RELAX_CHUNK;  // reduced-subgraph edges per relaxation task
 // Largest task count (reduced edges / kRelaxChunk + vertices) whose tasks the
-// relax compaction writes itself: EVQ_DIRECT_TASKS overrides (read per query).
-uint64_t direct_tasks_limit() {
-    const char* e = getenv("EVQ_DIRECT_TASKS");
-    return e ? strtoull(e, nullptr, 10) : (1ull << 18);
-}
+// relax compaction writes itself (evq_tuning.direct_tasks).
+uint64_t direct_tasks_limit() { return tuning().direct_tasks; }
 
 
 template <int NLW>
@@ -967,23 +964,9 @@ void writeback(uint32_t LG, uint32_t V, uint32_t L, const uint32_t* cid_of, cons
 
 }  // namespace
 
-uint32_t choose_delta(uint32_t algo) {
-    static const char* names[5] = {"EVQ_DELTA_SSSP", "EVQ_DELTA_BFS", "EVQ_DELTA_SSWP", "EVQ_DELTA_SSNP",
-                                   "EVQ_DELTA_VITERBI"};
-    const char* e = getenv(names[algo <= EVQ_VITERBI ? algo : 0]);
-    if (!e) e = getenv("EVQ_DELTA");
-    if (e) return (uint32_t)strtoul(e, nullptr, 10);
-    return 0u;
-}
+uint32_t choose_delta(uint32_t algo) { return tuning().delta[algo <= EVQ_VITERBI ? algo : 0]; }
 
-uint32_t choose_heavy(uint32_t algo) {
-    static const char* names[5] = {"EVQ_HEAVY_SSSP", "EVQ_HEAVY_BFS", "EVQ_HEAVY_SSWP", "EVQ_HEAVY_SSNP",
-                                   "EVQ_HEAVY_VITERBI"};
-    const char* e = getenv(names[algo <= EVQ_VITERBI ? algo : 0]);
-    if (!e) e = getenv("EVQ_HEAVY");
-    if (e) return (uint32_t)strtoul(e, nullptr, 10);
-    return 0u;
-}
+uint32_t choose_heavy(uint32_t algo) { return tuning().heavy[algo <= EVQ_VITERBI ? algo : 0]; }
 
 namespace {
 
@@ -1077,10 +1060,10 @@ struct SplitRule {
     double frac = 0.0;
     uint32_t min_len = 8;
     static SplitRule get() {
+        const evq_tuning t = tuning();
         SplitRule r;
-        if (const char* e = getenv("EVQ_SPLIT_FRAC")) r.frac = atof(e);
-        if (const char* e = getenv("EVQ_SPLIT_MIN")) r.min_len = (uint32_t)strtoul(e, nullptr, 10);
-        if (r.min_len < 1) r.min_len = 1;
+        r.frac = t.split_frac;
+        r.min_len = t.split_min < 1 ? 1 : t.split_min;
         return r;
     }
 };

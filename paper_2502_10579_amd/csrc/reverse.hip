@@ -1,20 +1,12 @@
 // Choice of the pull step of the full-window intersection solve (Section 3,
 // Step 1 on the intersection graph), and the lazy build of the graph's
 // reverse CSR (its arrays are filled by build_reverse with one radix sort).
-#include <cstdlib>
-
 #include "bounds.h"
 
 namespace evq {
 
 uint32_t pull_frac() {
-    const char* e = getenv("EVQ_PULL_FRAC");
-    double f = 0.5;
-    if (e && *e) {
-        char* endp = nullptr;
-        const double v = strtod(e, &endp);
-        if (endp != e) f = v;  // an unreadable value keeps the default
-    }
+    const double f = tuning().pull_frac;
     if (!(f >= 0.0) || f > 1.0) return kNone;
     return (uint32_t)(f * 1024.0 + 0.5);
 }
@@ -29,16 +21,16 @@ bool reverse_ready(const Graph& g, hipStream_t s) {
     const uint32_t V = g.V;
     const uint64_t E = g.E ? g.E : 1;
     try {
-        g.rv_src = (uint32_t*)stream_alloc(E * 4, s);
-        g.rv_w = (uint32_t*)stream_alloc(E * 4, s);
-        g.rv_io = (uint32_t*)stream_alloc((uint64_t)V * 4 + 4, s);
-        g.rv_iv = (uint32_t*)stream_alloc((uint64_t)V * 4 + 4, s);
-        g.rv_cnt = (uint32_t*)stream_alloc(8, s);
+        g.rv_src = (uint32_t*)graph_alloc(g, E * 4, s);
+        g.rv_w = (uint32_t*)graph_alloc(g, E * 4, s);
+        g.rv_io = (uint32_t*)graph_alloc(g, (uint64_t)V * 4 + 4, s);
+        g.rv_iv = (uint32_t*)graph_alloc(g, (uint64_t)V * 4 + 4, s);
+        g.rv_cnt = (uint32_t*)graph_alloc(g, 8, s);
         build_reverse(g, s);
     } catch (...) {
         uint32_t** arrays[5] = {&g.rv_src, &g.rv_w, &g.rv_io, &g.rv_iv, &g.rv_cnt};
         for (uint32_t** p : arrays) {
-            stream_free(*p, s);
+            graph_free(g, *p, s);
             *p = nullptr;
         }
         throw;

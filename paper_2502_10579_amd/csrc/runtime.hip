@@ -65,6 +65,17 @@ void retire_graph(Graph* g) {
         std::lock_guard<std::mutex> lk(g->use_mu);
         uses.swap(g->uses);
     }
+    if (g->has_ua) {  // the caller's allocator frees on the host: wait for every use first
+        for (hipEvent_t e : uses) {
+            (void)hipEventSynchronize(e);
+            (void)hipEventDestroy(e);
+        }
+        try {
+            free_graph(g, nullptr);
+        } catch (...) {
+        }
+        return;
+    }
     if (!r) {  // no stream for ordered release: wait for everything instead
         (void)hipDeviceSynchronize();
         for (hipEvent_t e : uses) (void)hipEventDestroy(e);
@@ -97,6 +108,31 @@ void* stream_alloc(uint64_t bytes, hipStream_t s) {
 
 void stream_free(void* p, hipStream_t s) {
     if (p) EVQ_HIP(hipFreeAsync(p, s));
+}
+
+namespace {
+
+void* user_alloc(const evq_allocator& ua, uint64_t bytes) {
+    const uint64_t n = bytes ? (bytes + 255) & ~uint64_t(255) : 256;
+    void* p = ua.alloc((size_t)n, ua.ctx);
+    if (!p) fail(EVQ_ENOMEM, "the caller's allocator returned NULL for " + std::to_string(n) + " bytes");
+    return p;
+}
+
+}  // namespace
+
+void* graph_alloc(const Graph& g, uint64_t bytes, hipStream_t s) {
+    return g.has_ua ? user_alloc(g.ua, bytes) : stream_alloc(bytes, s);
+}
+
+void graph_free(const Graph& g, void* p, hipStream_t s) {
+    if (!p) return;
+    if (g.has_ua) {
+        (void)hipStreamSynchronize(s);
+        g.ua.free(p, g.ua.ctx);
+    } else {
+        stream_free(p, s);
+    }
 }
 
 void init_mempool(int device) {
@@ -145,10 +181,15 @@ void* Arena::raw(uint64_t bytes) {
     void* p = nullptr;
     uint64_t n = (bytes + 255) & ~uint64_t(255);
     if (n == 0) n = 256;
-    hipError_t e = hipMallocAsync(&p, n, s_);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(EVQ_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    ptrs_.reserve(ptrs_.size() + 1);  // so that recording p below cannot throw
+    if (ua_) {
+        p = user_alloc(*ua_, n);
+    } else {
+        hipError_t e = hipMallocAsync(&p, n, s_);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(EVQ_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
     }
     ptrs_.push_back(p);
     bytes_ += n;
@@ -158,11 +199,21 @@ void* Arena::raw(uint64_t bytes) {
 void Arena::release(void* p) {
     auto it = std::find(ptrs_.begin(), ptrs_.end(), p);
     if (it == ptrs_.end()) return;
-    (void)hipFreeAsync(p, s_);
+    if (ua_) {
+        (void)hipStreamSynchronize(s_);
+        ua_->free(p, ua_->ctx);
+    } else {
+        (void)hipFreeAsync(p, s_);
+    }
     ptrs_.erase(it);
 }
 
 Arena::~Arena() {
+    if (ua_) {
+        if (!ptrs_.empty()) (void)hipStreamSynchronize(s_);
+        for (void* p : ptrs_) ua_->free(p, ua_->ctx);
+        return;
+    }
     for (void* p : ptrs_) (void)hipFreeAsync(p, s_);
 }
 
@@ -200,22 +251,75 @@ HostSlots& HostSlots::get() {
     return *hs;
 }
 
-uint64_t launch_depth() {
-    static const uint64_t d = [] {
-        const char* e = getenv("EVQ_LAUNCH_DEPTH");
-        const unsigned long v = e ? strtoul(e, nullptr, 10) : 3ul;
-        return (uint64_t)(v < 1 ? 1 : (v > 32 ? 32 : v));
-    }();
-    return d;
+// ------------------------------------------------------------------ tuning
+
+namespace {
+
+std::mutex g_tuning_mu;
+bool g_tuning_init = false;
+evq_tuning g_tuning;
+
+double env_f64(const char* name, double dflt) {
+    const char* e = getenv(name);
+    if (!e || !*e) return dflt;
+    char* endp = nullptr;
+    const double v = strtod(e, &endp);
+    return endp != e ? v : dflt;  // an unreadable value keeps the default
 }
 
-bool trace_loops() {
-    static const bool t = [] {
-        const char* e = getenv("EVQ_TRACE_LOOPS");
-        return e && *e && *e != '0';
-    }();
+uint32_t env_u32(const char* name, uint32_t dflt) {
+    const char* e = getenv(name);
+    if (!e || !*e) return dflt;
+    char* endp = nullptr;
+    const unsigned long long v = strtoull(e, &endp, 10);
+    if (endp == e) return dflt;
+    return v > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)v;
+}
+
+evq_tuning tuning_from_env() {
+    evq_tuning t;
+    std::memset(&t, 0, sizeof(t));
+    t.pull_frac = env_f64("EVQ_PULL_FRAC", 0.5);
+    t.split_frac = env_f64("EVQ_SPLIT_FRAC", 0.0);
+    t.split_min = std::max<uint32_t>(1u, env_u32("EVQ_SPLIT_MIN", 8u));
+    t.launch_depth = std::min<uint32_t>(32u, std::max<uint32_t>(1u, env_u32("EVQ_LAUNCH_DEPTH", 3u)));
+    t.direct_tasks = env_u32("EVQ_DIRECT_TASKS", 1u << 18);
+    t.append_rebuild = env_u32("EVQ_APPEND_REBUILD", 0u) != 0;
+    t.trace_loops = env_u32("EVQ_TRACE_LOOPS", 0u) != 0;
+    static const char* delta_names[5] = {"EVQ_DELTA_SSSP", "EVQ_DELTA_BFS", "EVQ_DELTA_SSWP", "EVQ_DELTA_SSNP",
+                                         "EVQ_DELTA_VITERBI"};
+    static const char* heavy_names[5] = {"EVQ_HEAVY_SSSP", "EVQ_HEAVY_BFS", "EVQ_HEAVY_SSWP", "EVQ_HEAVY_SSNP",
+                                         "EVQ_HEAVY_VITERBI"};
+    const uint32_t delta_all = env_u32("EVQ_DELTA", 0u), heavy_all = env_u32("EVQ_HEAVY", 0u);
+    for (int a = 0; a < 5; ++a) {
+        t.delta[a] = env_u32(delta_names[a], delta_all);
+        t.heavy[a] = env_u32(heavy_names[a], heavy_all);
+    }
     return t;
 }
+
+}  // namespace
+
+evq_tuning tuning() {
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    if (!g_tuning_init) {
+        g_tuning = tuning_from_env();
+        g_tuning_init = true;
+    }
+    return g_tuning;
+}
+
+void set_tuning(const evq_tuning& t) {
+    if (t.launch_depth < 1 || t.launch_depth > 32) fail(EVQ_EINVAL, "tuning: launch_depth must be in [1, 32]");
+    if (t.split_min < 1) fail(EVQ_EINVAL, "tuning: split_min must be >= 1");
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    g_tuning = t;
+    g_tuning_init = true;
+}
+
+uint64_t launch_depth() { return tuning().launch_depth; }
+
+bool trace_loops() { return tuning().trace_loops != 0; }
 
 void wait_slot(volatile uint32_t* slot, hipStream_t s, const char* what) {
     if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) != HostSlots::kEmpty) return;

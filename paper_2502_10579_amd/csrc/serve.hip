@@ -349,6 +349,7 @@ evq_status evq_server_create(evq_graph* h, const evq_server_config* c, evq_serve
         if (cfg.max_batch > 64) return sbad(EVQ_EINVAL, "max_batch must be <= 64");
         if (cfg.max_inflight == 0) cfg.max_inflight = 256;
         if (cfg.max_groups == 0) cfg.max_groups = 2;
+        if (cfg.max_queued == 0) cfg.max_queued = 65536;
         if (cfg.mem_budget == 0) {
             size_t fr = 0, tot = 0;
             EVQ_HIP(hipMemGetInfo(&fr, &tot));
@@ -387,6 +388,10 @@ evq_status evq_server_submit(evq_server* sv, uint32_t algo, uint32_t source, uin
         if (sv->stop) {
             delete q;
             return sbad(EVQ_EINVAL, "server is shutting down");
+        }
+        if (sv->queue.size() >= sv->cfg.max_queued) {
+            delete q;
+            return sbad(EVQ_EBUSY, "the server's queue is full; submit again after polling");
         }
         q->ticket = sv->next_ticket++;
         q->t_arrival = sv->now();

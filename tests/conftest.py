@@ -19,3 +19,12 @@ def pytest_runtest_logstart(nodeid, location):
     # Name the case before it touches the GPU, so a fault still leaves its name behind.
     if os.environ.get("EVQ_ANNOUNCE"):
         print(f"\n[start] {nodeid}", flush=True)
+
+
+@pytest.fixture
+def tuned():
+    """Setter of the library's scheduling knobs (evq_tuning) for one test; restored after it."""
+    import paper_2502_10579_amd as evq
+    prev = evq.get_tuning()
+    yield evq.set_tuning
+    evq.set_tuning(**prev)

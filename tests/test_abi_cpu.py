@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol(evq):
     assert set(evq.EXPORTED) == set(names)
 
 
-def _build(evq, V, base, batches_np, K=None):
+def _build(evq, V, base, batches_np, K=None, allocator=None):
     b = np.ascontiguousarray(np.asarray(base, np.uint32).reshape(-1, 3))
     keep = [b]
     arr = (evq.Batch * max(len(batches_np), 1))()
@@ -43,7 +43,8 @@ def _build(evq, V, base, batches_np, K=None):
                            a.ctypes.data_as(ctypes.POINTER(evq.Edge)) if len(a) else None, len(a))
     h = ctypes.c_void_p()
     rc = evq.lib.evq_build(V, b.ctypes.data_as(ctypes.POINTER(evq.Edge)) if len(b) else None, len(b), arr,
-                           len(batches_np) if K is None else K, None, ctypes.byref(h))
+                           len(batches_np) if K is None else K,
+                           ctypes.byref(allocator) if allocator is not None else None, None, ctypes.byref(h))
     return rc, h
 
 
@@ -73,12 +74,12 @@ def test_build_rejects_bad_K_and_V(evq):
 
 def test_build_rejects_null_pointers(evq):
     h = ctypes.c_void_p()
-    assert evq.lib.evq_build(4, None, 3, None, 1, None, ctypes.byref(h)) == evq.EVQ_EINVAL
+    assert evq.lib.evq_build(4, None, 3, None, 1, None, None, ctypes.byref(h)) == evq.EVQ_EINVAL
     arr = (evq.Batch * 1)()
-    assert evq.lib.evq_build(4, None, 3, arr, 1, None, ctypes.byref(h)) == evq.EVQ_EINVAL
-    assert evq.lib.evq_build(4, None, 0, arr, 1, None, None) == evq.EVQ_EINVAL
+    assert evq.lib.evq_build(4, None, 3, arr, 1, None, None, ctypes.byref(h)) == evq.EVQ_EINVAL
+    assert evq.lib.evq_build(4, None, 0, arr, 1, None, None, None) == evq.EVQ_EINVAL
     arr[0] = evq.Batch(None, 2, None, 0)
-    assert evq.lib.evq_build(4, None, 0, arr, 1, None, ctypes.byref(h)) == evq.EVQ_EINVAL
+    assert evq.lib.evq_build(4, None, 0, arr, 1, None, None, ctypes.byref(h)) == evq.EVQ_EINVAL
 
 
 def test_query_rejects_null_graph(evq):
@@ -95,3 +96,54 @@ def test_query_rejects_null_graph(evq):
 def test_timing_report_empty(evq):
     evq.timing_reset()
     assert evq.timing_report() == {}
+
+
+class CountingAllocator:
+    """evq_allocator whose alloc fails from its `fail_at`-th request on (1-based; 0: never) and hands
+    out host blocks otherwise; counts what is outstanding."""
+
+    def __init__(self, evq, fail_at=0):
+        self.fail_at, self.requests, self.live = fail_at, 0, {}
+        self._a = evq.ALLOC_FN(self._alloc)
+        self._f = evq.FREE_FN(self._free)
+        self.c = evq.Allocator(self._a, self._f, None)
+
+    def _alloc(self, n, ctx):
+        self.requests += 1
+        if self.fail_at and self.requests >= self.fail_at:
+            return None
+        buf = ctypes.create_string_buffer(int(n))
+        self.live[ctypes.addressof(buf)] = buf
+        return ctypes.addressof(buf)
+
+    def _free(self, p, ctx):
+        assert p in self.live, "freed a block the allocator never gave (or twice)"
+        del self.live[p]
+
+
+def test_build_allocator_returning_null_gives_enomem(evq):
+    """The caller's allocator is asked for the event buffer before any device call: NULL from it is
+    EVQ_ENOMEM with no handle, and nothing stays allocated."""
+    a = CountingAllocator(evq, fail_at=1)
+    rc, h = _build(evq, 4, [[0, 1, 1], [1, 2, 3]], [([], [[2, 3, 1]])], allocator=a.c)
+    assert rc == evq.EVQ_ENOMEM and not h.value
+    assert "allocator returned NULL" in evq.last_error()
+    assert a.requests == 1 and not a.live
+
+
+def test_build_failure_after_allocating_returns_every_block(evq):
+    """Without a device the build fails after its first allocation succeeded: the block goes back
+    to the caller's allocator before the call returns, and no handle is left."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("needs a machine without a GPU")
+    a = CountingAllocator(evq)
+    rc, h = _build(evq, 4, [[0, 1, 1], [1, 2, 3]], [([], [[2, 3, 1]])], allocator=a.c)
+    assert rc != evq.EVQ_OK and not h.value
+    assert a.requests >= 1 and not a.live
+
+
+def test_build_rejects_incomplete_allocator(evq):
+    a = evq.Allocator(evq.ALLOC_FN(lambda n, c: None), evq.FREE_FN(), None)
+    rc, h = _build(evq, 4, [[0, 1, 1]], [([], [])], allocator=a)
+    assert rc == evq.EVQ_EINVAL and not h.value

@@ -125,12 +125,12 @@ def test_appends_while_querying(evq):
         assert_equal_values(got, oracle.window_values(inst, a, s, b, L, replayed=rep), f"{(a, s, b, L)}")
 
 
-def test_threads_share_the_reverse_build(evq, monkeypatch):
+def test_threads_share_the_reverse_build(evq, tuned):
     # full-window queries from four threads and streams released together on a
     # fresh graph, pulling whenever they can: the reverse CSR is built once by
     # whichever query asks second, the others' streams wait for it
     import torch
-    monkeypatch.setenv("EVQ_PULL_FRAC", "0")
+    tuned(pull_frac=0.0)
     inst = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=41)
     srcs = synth.pick_sources(inst, 4, seed=3)
     rep = oracle.replay(inst)
@@ -139,6 +139,8 @@ def test_threads_share_the_reverse_build(evq, monkeypatch):
     want = {k: oracle.window_values(inst, k[0], k[1], 0, K, replayed=rep) for k in keys}
     bad = []
     with evq.Graph.from_instance(inst) as g:
+        held = g.info["device_bytes"]
+        E = g.info["num_edges"]
         start = threading.Barrier(4)
 
         def worker(tid):
@@ -159,4 +161,6 @@ def test_threads_share_the_reverse_build(evq, monkeypatch):
             t.join()
         grown = g.info["device_bytes"]
     assert not bad, f"wrong results on (thread, round, algo, source): {bad[:5]}"
-    assert grown > 0
+    # built exactly once: the handle grew by one reverse CSR (8 bytes per edge, two arrays of V + 1
+    # entries, two counters)
+    assert grown - held == 8 * max(E, 1) + 2 * (4 * V + 4) + 8, (held, grown)

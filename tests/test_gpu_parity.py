@@ -256,11 +256,10 @@ def test_gather_ceiling_measurement(evq):
 
 @pytest.mark.parametrize("delta,heavy", [(1, 0), (7, 0), (60, 0), (3, 4), (20, 2)])
 @pytest.mark.parametrize("algo", ALGOS)
-def test_near_far_scheduling(evq, algo, delta, heavy, monkeypatch):
+def test_near_far_scheduling(evq, algo, delta, heavy, tuned):
     # near/far ordering of the bound solves (every vertex gated, or only those
     # with at least `heavy` edges) changes the schedule, never the values
-    monkeypatch.setenv("EVQ_DELTA", str(delta))
-    monkeypatch.setenv("EVQ_HEAVY", str(heavy))
+    tuned(delta=delta, heavy=heavy)
     for seed in (1, 2):
         inst = synth.config_instance("small", seed=seed)
         trip, bits = oracle.replay(inst)
@@ -276,14 +275,13 @@ def test_near_far_scheduling(evq, algo, delta, heavy, monkeypatch):
 
 
 @pytest.mark.parametrize("algo", ALGOS)
-def test_heavy_gating_many_blocks(evq, algo, monkeypatch):
+def test_heavy_gating_many_blocks(evq, algo, tuned):
     # only vertices with >= 16 edges deferred, threshold following the frontier
     inst = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=37)
     src = synth.pick_sources(inst, 1, seed=5)[0]
     trip, bits = oracle.replay(inst)
     delta = {oracle.BFS: 1, oracle.VITERBI: 1 << 23}.get(algo, 20)
-    monkeypatch.setenv("EVQ_DELTA", str(delta))
-    monkeypatch.setenv("EVQ_HEAVY", "16")
+    tuned(delta=delta, heavy=16)
     for (b, L) in [(0, 16), (5, 7)]:
         want = oracle.window_values(inst, algo, src, b, L, replayed=(trip, bits))
         rc_o, ru_o = oracle.bounds(inst.num_vertices, trip, bits, algo, src, b, L)
@@ -294,13 +292,13 @@ def test_heavy_gating_many_blocks(evq, algo, monkeypatch):
         assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
 
 
-@pytest.mark.parametrize("frac", ["0", "0.3", "2"])
+@pytest.mark.parametrize("frac", [0.0, 0.3, 2.0])
 @pytest.mark.parametrize("algo", ALGOS)
-def test_pull_step(evq, algo, frac, monkeypatch):
+def test_pull_step(evq, algo, frac, tuned):
     # full-window intersection solve pulling in every iteration (0), in the
     # dense ones (0.3) or never (2): same values and bounds as the oracle, on
     # small graphs and on one with hubs and many waves per slice
-    monkeypatch.setenv("EVQ_PULL_FRAC", frac)
+    tuned(pull_frac=frac)
     cases = [(synth.config_instance("small", seed=s), 0) for s in (1, 2, 3)]
     big = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=41)
     cases.append((big, synth.pick_sources(big, 1, seed=3)[0]))
@@ -315,18 +313,18 @@ def test_pull_step(evq, algo, frac, monkeypatch):
             grown = g.info["device_bytes"] - held
             again = gpu_values(g, algo, src, 0, inst.K)  # reverse CSR reused
             assert g.info["device_bytes"] - held == grown
-        assert (grown > 0) == (frac != "2"), (frac, grown)
+        assert (grown > 0) == (frac <= 1.0), (frac, grown)
         assert_equal_values(got, want, f"pull {frac} case {ci}")
         assert_equal_values(again, want, f"pull {frac} case {ci} second query")
         assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
 
 
-@pytest.mark.parametrize("direct", ["0", "1000000000"])
+@pytest.mark.parametrize("direct", [0, 1000000000])
 @pytest.mark.parametrize("algo", ALGOS)
-def test_relax_task_paths(evq, algo, direct, monkeypatch):
+def test_relax_task_paths(evq, algo, direct, tuned):
     # relaxation tasks written by a kernel of their own (limit 0) or by the
     # compaction (a limit above any task count): same values
-    monkeypatch.setenv("EVQ_DIRECT_TASKS", direct)
+    tuned(direct_tasks=direct)
     inst = synth.rmat_instance(15, 200000, 16, 2000, 2000, wmin=1, wmax=100, seed=41)
     src = synth.pick_sources(inst, 2, seed=9)
     trip, bits = oracle.replay(inst)
@@ -361,16 +359,15 @@ def test_query_many_blocks_method_plain_sequential(evq, algo):
 
 @pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("K,b,L,min_len", [(20, 3, 17, 2), (64, 0, 64, 8), (100, 13, 87, 3), (128, 0, 128, 1)])
-def test_split_subwindows_equal_oracle(evq, algo, K, b, L, min_len, monkeypatch):
+def test_split_subwindows_equal_oracle(evq, algo, K, b, L, min_len, tuned):
     # a threshold of 0 unstable vertices forces every window of 2 * min_len or more to split, to depth 4
     inst = synth.rmat_instance(11, 12000, K, 12, 12, wmin=1, wmax=30, seed=K + b + 7)
     src = synth.pick_sources(inst, 1, seed=K + 1)[0]
     want = oracle.window_values(inst, algo, src, b, L)
-    monkeypatch.setenv("EVQ_SPLIT_FRAC", "1e-9")
-    monkeypatch.setenv("EVQ_SPLIT_MIN", str(min_len))
+    tuned(split_frac=1e-9, split_min=min_len)
     with _graph(evq, inst) as g:
         got, st = gpu_values(g, algo, src, b, L, stats=True)
-        monkeypatch.setenv("EVQ_SPLIT_FRAC", "0")
+        tuned(split_frac=0.0)
         one, st1 = gpu_values(g, algo, src, b, L, stats=True)
     assert_equal_values(got, want, f"split algo {algo} K {K} [{b},{b + L})")
     assert_equal_values(one, want, f"unsplit algo {algo} K {K} [{b},{b + L})")

@@ -196,33 +196,31 @@ def test_ring_old_results_and_bad_append(evq):
             assert np.array_equal(before[k], after[k])
 
 
-def _appended_pair(evq, inst, K, batches, monkeypatch):
+def _appended_pair(evq, inst, K, batches):
     """Apply batches to two copies of the same ring, incrementally and by a full
-    rebuild (EVQ_APPEND_REBUILD=1); yield both exports after each append."""
+    rebuild (evq_tuning.append_rebuild); yield both exports after each append."""
     with evq.Graph.from_instance(head(inst, K)) as g1, evq.Graph.from_instance(head(inst, K)) as g2:
         for dels, adds in batches:
-            monkeypatch.delenv("EVQ_APPEND_REBUILD", raising=False)
             g1.append(dels, adds)
-            monkeypatch.setenv("EVQ_APPEND_REBUILD", "1")
-            g2.append(dels, adds)
-            monkeypatch.delenv("EVQ_APPEND_REBUILD", raising=False)
+            with evq.tuning(append_rebuild=1):
+                g2.append(dels, adds)
             yield g1, g2
 
 
 @pytest.mark.parametrize("K,A", [(8, 13), (64, 20), (100, 9), (128, 5)])
-def test_ring_incremental_equals_rebuild(evq, K, A, monkeypatch):
+def test_ring_incremental_equals_rebuild(evq, K, A):
     # the incremental append (events sorted and looked up, masks updated in one
     # pass, edges placed by rank) produces the same arrays as a full rebuild
     inst = synth.random_instance(90, 900, K + A, 6, 6, 9, 700 + K)
     batches = [(inst.dels[K + a], inst.adds[K + a]) for a in range(A)]
-    for i, (g1, g2) in enumerate(_appended_pair(evq, inst, K, batches, monkeypatch)):
+    for i, (g1, g2) in enumerate(_appended_pair(evq, inst, K, batches)):
         e1, e2 = g1.export(), g2.export()
         for k in e1:
             assert np.array_equal(e1[k], e2[k]), f"append {i}: {k} differs"
         assert g1.info["num_partial"] == g2.info["num_partial"]
 
 
-def test_ring_incremental_odd_batches(evq, monkeypatch):
+def test_ring_incremental_odd_batches(evq):
     # deletions of absent triples, additions of held ones, repeated events,
     # empty batches, a vertex's whole row deleted
     K = 6
@@ -244,7 +242,7 @@ def test_ring_incremental_odd_batches(evq, monkeypatch):
         d = [held[int(i)] for i in rng.integers(0, len(held), 3)]
         a = [(int(rng.integers(0, 40)), int(rng.integers(0, 40)), int(rng.integers(1, 10))) for _ in range(4)]
         batches.append((np.array(d, np.uint32), np.array(a, np.uint32)))
-    for i, (g1, g2) in enumerate(_appended_pair(evq, inst, K, batches, monkeypatch)):
+    for i, (g1, g2) in enumerate(_appended_pair(evq, inst, K, batches)):
         e1, e2 = g1.export(), g2.export()
         for k in e1:
             assert np.array_equal(e1[k], e2[k]), f"odd batch {i}: {k} differs"
