@@ -254,16 +254,15 @@ def bench_sweep(args):
             if name != "method":
                 res[name + "_identical"] = bool(torch.equal(out, ref))
         # the same query with sub-window splitting on (more than 35% unstable: two halves, recursively)
-        os.environ["EVQ_SPLIT_FRAC"] = "0.35"
-        g.query(0, src, 0, K, out=ref)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(3):
+        with evq.tuning(split_frac=0.35):
             g.query(0, src, 0, K, out=ref)
-        torch.cuda.synchronize()
-        res["split"] = (time.perf_counter() - t) * 1000.0 / 3
-        _, st = g.query(0, src, 0, K, out=ref, stats=True)
-        del os.environ["EVQ_SPLIT_FRAC"]
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                g.query(0, src, 0, K, out=ref)
+            torch.cuda.synchronize()
+            res["split"] = (time.perf_counter() - t) * 1000.0 / 3
+            _, st = g.query(0, src, 0, K, out=ref, stats=True)
         res["split_identical"] = bool(torch.equal(out, ref))
         _, st0 = g.query(0, src, 0, K, out=out, stats=True)
         row = {"K": K, "batch": nb, "union_edges": g.info["num_edges"], "n_unstable": st0["n_unstable"],
@@ -442,12 +441,36 @@ def main():
     for _ in range(args.warmup):
         g.query(algo, source, b, L, out=out)
     torch.cuda.synchronize()
+    # every query bracketed by HIP events on the stream it runs on (torch's current stream, which the
+    # binding passes to the library): per-query device time, median and p99 beside the wall-clock mean
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t = time.perf_counter()
-    for _ in range(args.steps):
+    for e0, e1 in evs:
+        e0.record()
         g.query(algo, source, b, L, out=out)
+        e1.record()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t) * 1000.0 / args.steps
-    log(f"[bench] method: {ms:.3f} ms/query over {args.steps} steps")
+    ev_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    q_ev = {"p50": float(np.median(ev_ms)), "p99": float(np.percentile(ev_ms, 99)), "mean": float(np.mean(ev_ms)),
+            "min": float(np.min(ev_ms))}
+    log(f"[bench] method: {ms:.3f} ms/query over {args.steps} steps (wall); HIP events p50 {q_ev['p50']:.3f} "
+        f"p99 {q_ev['p99']:.3f} ms")
+
+    # The paper's Fig. 11 split: QRS generation (both bound solves, then the unstable set and the reduced
+    # subgraph) against the whole query.  The bound solves alone (evq_query_bounds, uninstrumented, HIP events)
+    # give its lower part; the kernel-time share below adds the reduction kernels.
+    rc_buf = torch.empty(inst.num_vertices, dtype=torch.int32, device="cuda")
+    ru_buf = torch.empty_like(rc_buf)
+    bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in bev:
+        e0.record()
+        evq._check(evq.lib.evq_query_bounds(g._h, algo, source, b, L, evq._ptr(rc_buf), evq._ptr(ru_buf),
+                                            evq._stream(None)))
+        e1.record()
+    torch.cuda.synchronize()
+    bounds_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in bev]))
+    del rc_buf, ru_buf
 
     _, st = g.query(algo, source, b, L, out=out, stats=True)
     log(f"[bench] stats: {json.dumps({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()})}")
@@ -478,19 +501,14 @@ def main():
         log(f"[bench] sequential per-snapshot evaluation: {seq_ms:.3f} ms/query, identical={same_seq}")
         # the method with its pull step off (pushes only), against which the plain evaluation, whose kernel
         # has no pull step, compares on the analysis alone
-        prev = os.environ.get("EVQ_PULL_FRAC")
-        os.environ["EVQ_PULL_FRAC"] = "2"
-        g.query(algo, source, b, L, out=outp)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(n_plain):
+        with evq.tuning(pull_frac=2.0):
             g.query(algo, source, b, L, out=outp)
-        torch.cuda.synchronize()
-        push_ms = (time.perf_counter() - t) * 1000.0 / n_plain
-        if prev is None:
-            del os.environ["EVQ_PULL_FRAC"]
-        else:
-            os.environ["EVQ_PULL_FRAC"] = prev
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(n_plain):
+                g.query(algo, source, b, L, out=outp)
+            torch.cuda.synchronize()
+            push_ms = (time.perf_counter() - t) * 1000.0 / n_plain
         log(f"[bench] method without its pull step: {push_ms:.3f} ms/query, identical={bool(torch.equal(out, outp))}")
 
     # batching leg on the same graph: 64 mixed queries of the batched recipe (algorithm uniform, random
@@ -551,6 +569,15 @@ def main():
             if traffic:
                 roof["traffic_GBps"] = round(traffic / (avg_us * 1e-6) / 1e9, 2)
                 roof["traffic_frac"] = round(traffic / (avg_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
+            if dom == "solve_expand_cap_all":
+                # visits per edge of the window's intersection graph (over the whole window: the all-present
+                # edges), and the rate against one visit per such edge, the bound solve's lower bound
+                e_cap = info["num_edges"] - info["num_partial"]
+                lb = 12 * e_cap
+                roof["visits_per_intersection_edge"] = round(st["edges_cap"] / max(e_cap, 1), 3)
+                roof["one_visit_lower_bound"] = {"bytes_per_query": lb,
+                                                 "achieved": round(lb * reps / (tot_ms / 1000.0) / 1e9, 2),
+                                                 "frac": round(lb * reps / (tot_ms / 1000.0) / 1e9 / PEAK_HBM_GBS, 4)}
             if dom.startswith("solve_expand_"):
                 # the expansion's edge-visit rate against the same per-edge
                 # memory operations alone over this graph's edges
@@ -612,6 +639,15 @@ def main():
         log(f"[bench] relaxer on the heavy-churn mid graph: {ach:.1f} GB/s algorithmic "
             f"({hst['n_unstable'] / hv.num_vertices:.0%} unstable, query {hms:.2f} ms)")
 
+    # Fig. 11 analogue (QRS generation = bound solves + unstable set + reduced subgraph, share of the query)
+    qrs = {"bounds_only_ms_p50": round(bounds_ms, 4), "query_ms_p50": round(q_ev["p50"], 4),
+           "bounds_share_uninstrumented": round(bounds_ms / q_ev["p50"], 4), "paper_cqrs_share": 0.5601}
+    if kernels:
+        gen = sum(v[1] for k, v in kernels.items()
+                  if k.startswith("solve_") or k in ("compact_unstable", "compact_reduce", "copy_bound", "query_init"))
+        qrs["kernel_time_share"] = round(gen / sum(v[1] for v in kernels.values()), 4)
+    log(f"[bench] QRS generation: {qrs}")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -629,6 +665,14 @@ def main():
         one_s = time.perf_counter() - t
         got = evq.to_u32(out).reshape(inst.num_vertices, L)[:, :len(sample)]
         ok = bool(np.array_equal(got, want))
+        # the oracle against the paper's reported fractions (a sanity band: unchanged vertices 53.2-99.8%,
+        # unstable 0.3-42%, detection recall "nearly all")
+        san = oracle.window_sanity(inst.num_vertices, trip, bits, algo, source, b, L, values=want)
+        sanity = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in san.items()}
+        sanity["paper_unchanged_band"] = list(oracle.UNCHANGED_BAND)
+        sanity["paper_unstable_band"] = list(oracle.UNSTABLE_BAND)
+        sanity["warnings"] = oracle.sanity_warnings(san)
+        log(f"[bench] oracle sanity: {sanity}")
         cpu = {"value": float(counts[sample].sum() / cpu_s), "unit": "snapshot-edges/s", "cores": nthreads,
                "kind": "oracle",
                "sample": f"snapshots {sample[0]}..{sample[-1]} of the window ({len(sample)} of {L}), per-snapshot "
@@ -636,7 +680,8 @@ def main():
                          f"included",
                "matches_gpu": ok,
                "one_core": {"value": float(counts[sample[:2]].sum() / one_s), "unit": "snapshot-edges/s",
-                            "sample": f"snapshots {sample[0]}..{sample[1]} on 1 thread, {one_s:.2f}s"}}
+                            "sample": f"snapshots {sample[0]}..{sample[1]} on 1 thread, {one_s:.2f}s"},
+               "oracle_sanity": sanity}
         log(f"[bench] oracle sample: {cpu_s:.2f}s for {len(sample)} snapshots on {nthreads} threads, "
             f"matches GPU: {ok}")
 
@@ -660,6 +705,8 @@ def main():
                    "algo": args.algo, "snapshots": L, "snapshot_edges": snap_edges,
                    "union_edges": info["num_edges"], "partial_edges": info["num_partial"]},
         "ms_per_query": ms,
+        "ms_per_query_hip_events": q_ev,
+        "qrs_generation": qrs,
         "plain_ms_per_query": plain_ms,
         "speedup_vs_plain": (plain_ms / ms) if plain_ms else None,
         "sequential_ms_per_query": seq_ms,

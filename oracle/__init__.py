@@ -125,3 +125,51 @@ def window_values(inst, algo: int, source: int, b: int, L: int, snaps=None, repl
     trip, bits = replayed if replayed is not None else replay(inst)
     s = list(range(b, b + L)) if snaps is None else list(snaps)
     return query(inst.num_vertices, trip, bits, algo, source, s, nthreads)
+
+
+# Bands the paper reports for real graphs (sanity only, not exact pins):
+#  - vertices whose value is the same in every snapshot of a 25-100 snapshot window: 53.2%-99.8%
+#    (abstract, Section 1, Fig. 1);
+#  - vertices that need per-snapshot incremental work (bounds differ): 0.3%-42% (Section 6.2, Fig. 9);
+#  - the bounds detect "nearly all" unchanged vertices (Section 3 Step 2, Section 6.2, Fig. 10).
+UNCHANGED_BAND = (0.532, 0.998)
+UNSTABLE_BAND = (0.003, 0.42)
+
+
+def window_sanity(V: int, trip, bits, algo: int, source: int, b: int, L: int, values=None, nthreads: int = 0):
+    """Fractions of the window [b, b+L) to set beside the paper's bands, from the oracle's own
+    per-snapshot values and bounds:
+      unchanged_all        vertices with one value in every snapshot, over all V
+      unchanged_reachable  the same over vertices reachable in the union graph (R_cup not unreached)
+      unstable             vertices whose intersection and union bounds differ (|U| / V)
+      recall               detected-stable (equal bounds) / truly unchanged
+      detected_subset      Theorem 2: every detected-stable vertex is unchanged, at its bound's value
+    """
+    vals = values if values is not None else query(V, trip, bits, algo, source, list(range(b, b + L)), nthreads)
+    rcap, rcup = bounds(V, trip, bits, algo, source, b, L)
+    unreached = 0 if algo in (SSWP, VITERBI) else INF
+    constant = (vals == vals[:, :1]).all(axis=1)
+    detected = rcap == rcup
+    reach = rcup != unreached
+    n_const = int(constant.sum())
+    return {
+        "unchanged_all": float(constant.mean()),
+        "unchanged_reachable": float(constant[reach].mean()) if reach.any() else 1.0,
+        "reachable": float(reach.mean()),
+        "unstable": float((~detected).mean()),
+        "recall": float(int(detected.sum()) / n_const) if n_const else 1.0,
+        "detected_subset": bool((~detected | constant).all() and (vals[detected] == rcap[detected][:, None]).all()),
+    }
+
+
+def sanity_warnings(s: dict) -> list:
+    """Messages for the fractions that fall outside the paper's bands (warnings, not failures)."""
+    out = []
+    lo, hi = UNCHANGED_BAND
+    for k in ("unchanged_all", "unchanged_reachable"):
+        if not lo <= s[k] <= hi:
+            out.append(f"{k} {s[k]:.4f} outside the paper's {lo:.3f}-{hi:.3f}")
+    lo, hi = UNSTABLE_BAND
+    if not lo <= s["unstable"] <= hi:
+        out.append(f"unstable {s['unstable']:.4f} outside the paper's {lo:.3f}-{hi:.3f}")
+    return out

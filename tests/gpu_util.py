@@ -49,3 +49,39 @@ def oracle_triples(inst):
         if m:
             d[(int(r[0]), int(r[1]), int(r[2]))] = m
     return d
+
+
+def gpu_column_digests(t, chunk=16):
+    """Digests (tests/digest.py) of the columns of a (V, L) int32 device tensor of uint32 values."""
+    from digest import column_digests
+    L = t.shape[1]
+    out = []
+    for i in range(0, L, chunk):
+        part = t[:, i:i + chunk].t().contiguous().cpu().numpy().view(np.uint32)
+        out += column_digests(part)
+    return out
+
+
+def assert_digests(got, want, ctx, diagnose=None):
+    """Columns whose digests differ are named; diagnose(i) may add the first differing vertex."""
+    assert len(got) == len(want), f"{ctx}: {len(got)} columns, expected {len(want)}"
+    bad = [i for i, (a, b) in enumerate(zip(got, want)) if a != b]
+    if bad:
+        msg = f"{ctx}: {len(bad)} of {len(want)} snapshot columns differ from the oracle (first: column {bad[0]})"
+        if diagnose is not None:
+            msg += "; " + diagnose(bad[0])
+        raise AssertionError(msg)
+
+
+def golden_section(name, inst):
+    """A section of tests/golden/fullsize_digests.json, checked against the instance it was computed on."""
+    import json
+    import os
+    from digest import instance_fingerprint
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_digests.json")
+    with open(path) as f:
+        sec = json.load(f)[name]
+    fp = instance_fingerprint(inst)
+    assert sec["fingerprint"] == fp, (f"golden section {name} was computed on another instance "
+                                      f"(regenerate with tests/golden/make_fullsize_digests.py {name})")
+    return sec

@@ -7,19 +7,19 @@ newest len snapshots, len uniform in [16, 128].
 
 * Every served result equals the same query answered alone (compared on the
   device, element by element).
-* A 16-query sample equals the oracle on three snapshots of each window
-  (first, middle, last).  The oracle replays the history re-based at the
-  snapshot before the oldest one held.
+* A 16-query sample (every 4th query) equals the oracle on every snapshot of
+  its window, through per-snapshot digests that
+  tests/golden/make_fullsize_digests.py wrote from the oracle (whose history
+  is re-based at the snapshot before the oldest one held), and its unstable
+  count equals the oracle bounds'.
 Values are uint32: tolerance zero.
 """
-import concurrent.futures
-
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from gpu_util import assert_equal_values
+from gpu_util import assert_digests, golden_section, gpu_column_digests
 
 pytestmark = pytest.mark.gpu
 
@@ -77,28 +77,34 @@ def test_served_equal_alone(evq, served):
             raise AssertionError(f"served {(a, s, b, L)}: {int((got != one).sum())} values differ from alone")
 
 
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(600)
 def test_served_sample_vs_oracle(evq, served):
     inst, g, comps = served
     V = inst.num_vertices
-    # the oracle's history re-based so that its snapshot i is global snapshot A + i
-    trip, bits = oracle.replay(synth.Instance(V, inst.base, inst.dels[:A], inst.adds[:A]))
-    t = A - 1
-    keep = ((bits[:, t // 64] >> np.uint64(t % 64)) & np.uint64(1)).astype(bool)
-    reb = synth.Instance(V, trip[keep].copy(), inst.dels[A:], inst.adds[A:])
-    del trip, bits, keep
-    rtrip, rbits = oracle.replay(reb)
-    print("served: oracle history replayed", flush=True)
+    sec = golden_section("served", inst)
     sample = comps[::NQ // 16]
+    assert sorted(int(k) for k in sec["queries"]) == list(range(0, NQ, NQ // 16))
 
-    def solve(c):
-        b, L = c["win_begin"], c["win_len"]
-        snaps = sorted({b, b + L // 2, b + L - 1})
-        return c, snaps, oracle.query(V, rtrip, rbits, c["algo"], c["source"], [t - A for t in snaps], 3)
+    for k, c in zip(range(0, NQ, NQ // 16), sample):
+        want = sec["queries"][str(k)]
+        a, s, b, L = c["algo"], c["source"], c["win_begin"], c["win_len"]
+        assert want["query"] == [a, s, b, L]
+        out = c["result"].expand()
 
-    with concurrent.futures.ThreadPoolExecutor(5) as ex:
-        for c, snaps, want in ex.map(solve, sample):
-            b = c["win_begin"]
-            got = evq.to_u32(c["result"].expand()[:, [t - b for t in snaps]].contiguous())
-            assert_equal_values(got, want, f"served {(c['algo'], c['source'], b, c['win_len'])} snapshots {snaps}")
-            print(f"  served query {c['ticket']}: equal on snapshots {snaps}", flush=True)
+        def diagnose(col, a=a, s=s, b=b, out=out):
+            # the oracle's history re-based so that its snapshot i is global snapshot A + i
+            trip, bits = oracle.replay(synth.Instance(V, inst.base, inst.dels[:A], inst.adds[:A]))
+            t = A - 1
+            keep = ((bits[:, t // 64] >> np.uint64(t % 64)) & np.uint64(1)).astype(bool)
+            reb = synth.Instance(V, trip[keep].copy(), inst.dels[A:], inst.adds[A:])
+            del trip, bits, keep
+            rtrip, rbits = oracle.replay(reb)
+            w = oracle.query(V, rtrip, rbits, a, s, [b + col - A])[:, 0]
+            gc = evq.to_u32(out[:, col].contiguous())
+            v = int(np.flatnonzero(gc != w)[0])
+            return f"vertex {v}: gpu {gc[v]} oracle {w[v]}"
+
+        assert_digests(gpu_column_digests(out), want["columns"], f"served {(a, s, b, L)}", diagnose)
+        assert c["n_unstable"] == want["n_unstable"]
+        del out
+        print(f"  served query {c['ticket']} {(a, s, b, L)}: equal on all {L} snapshots", flush=True)
