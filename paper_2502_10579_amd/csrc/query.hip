@@ -442,14 +442,19 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
 // One iteration of Algorithm 2's loop over the snapshot-oblivious frontier.
 // Each LG-lane group takes one task (<= kRelaxChunk edges of one vertex);
 // the task's edge records and destination rows are loaded before any update.
+// The read-only arrays come as their own restrict-qualified arguments: with
+// one group per wave (LG >= 64) a task, its row bounds and its edge records
+// are wave-uniform, and the compiler may then fetch them with scalar loads,
+// since no store of the kernel can reach them.
 template <int A, int LG, bool ST>
-__global__ void __launch_bounds__(kBlock) k_relax(RelaxArgs r, int p, uint32_t* slot) {
+__global__ void __launch_bounds__(kBlock)
+    k_relax(RelaxArgs r, const uint64_t* __restrict__ tasks, const uint32_t* __restrict__ cuo,
+            const uint32_t* __restrict__ kc, const void* __restrict__ recs_v, int p, uint32_t* slot) {
     using T = Lanes<LG>;
     const unsigned long long cx = expand_prologue(r.cnt, p, slot);
     const uint32_t n = edges_of(cx);  // tasks (the items are their vertices)
     if (n == 0) return;
-    const uint64_t* __restrict__ tasks = r.tasks;
-    const Rec<T::NLW>* __restrict__ recs = static_cast<const Rec<T::NLW>*>(r.recs);
+    const Rec<T::NLW>* __restrict__ recs = static_cast<const Rec<T::NLW>*>(recs_v);
     const uint32_t lane = lane_id();
     const int g = LG >= 64 ? 0 : (int)lane / LG;
     const int i0 = LG >= 64 ? (int)lane : (int)lane % LG;
@@ -462,7 +467,7 @@ __global__ void __launch_bounds__(kBlock) k_relax(RelaxArgs r, int p, uint32_t* 
             uint64_t tk = tasks[ti];
             if (T::G == 1) tk = ((uint64_t)uniform((uint32_t)(tk >> 32)) << 32) | uniform((uint32_t)tk);
             c = (uint32_t)tk;
-            const uint32_t rb = r.cuo[c], re = rb + r.kc[c];
+            const uint32_t rb = cuo[c], re = rb + kc[c];
             e0 = rb + (uint32_t)(tk >> 32) * kRelaxChunk;
             ne = re - e0 < kRelaxChunk ? re - e0 : kRelaxChunk;
         }
@@ -902,7 +907,7 @@ void relax_phase(const Graph& g, const Window& W, const Window& PW, const uint32
             EVQ_LAUNCH("relax_compact", k_relax_compact<false>, cblocks, kCompactBlock, s, ra, p, first ? 1 : 0);
             EVQ_LAUNCH("relax_tasks", k_relax_tasks, tblocks, kBlock, s, ra, p);
         }
-        EVQ_LAUNCH("relax", (k_relax<A, LG, ST>), rblocks, kBlock, s, ra, p, slot);
+        EVQ_LAUNCH("relax", (k_relax<A, LG, ST>), rblocks, kBlock, s, ra, ra.tasks, ra.cuo, ra.kc, ra.recs, p, slot);
     };
     qo.st.iters_relax = drive_loop(issue, f.p, s, (uint64_t)g.V + 2, "snapshot relaxation");
 }
