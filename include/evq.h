@@ -209,6 +209,29 @@ evq_status evq_query(const evq_graph* g, uint32_t algo, uint32_t source, uint32_
                      uint32_t win_len, uint32_t* d_values, evq_query_stats* stats, void* stream);
 
 /*
+ * evq_query for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  Same arguments,
+ * output layout and values as evq_query (no stats).  It calls no device or
+ * pinned-host allocator: its device temporaries live in one 128 MiB array
+ * per GPU, held by the library until the process ends and shared by every
+ * call on that GPU (the first call on a device looks its address up).
+ * Differences from evq_query: it returns once the values are complete (it
+ * synchronises `stream`); the frontier loops read their counts back in
+ * batches with copies into host memory instead of mapped slots; the pull
+ * step is used only if an earlier evq_query built its reverse CSR, and no
+ * sub-window splitting is done.  `stream` must belong to the graph's device,
+ * which must be current.
+ * Errors: as evq_query, plus EVQ_ERANGE when the query's temporaries (about
+ * 45 bytes per vertex, plus the reduced subgraph and the unstable rows)
+ * exceed the array (nothing is left half-written that a later call depends
+ * on), EVQ_EBUSY when another call of this entry point is running on the
+ * device (calls that overlap on one GPU would race for the array: they are
+ * refused instead), EVQ_EDEVICE when the array cannot be looked up.
+ */
+evq_status evq_query_noalloc(const evq_graph* g, uint32_t algo, uint32_t source, uint32_t win_begin,
+                             uint32_t win_len, uint32_t* d_values, void* stream);
+
+/*
  * Only the bounds of Step 1: d_rcap[v] = value on the window's intersection
  * graph, d_rcup[v] = value on its union graph (device buffers of V uint32,
  * either may be NULL).  Same arguments and errors as evq_query.

@@ -119,6 +119,8 @@ for _name in ("evq_query", "evq_query_plain", "evq_query_sequential"):
     getattr(_lib, _name).restype = ctypes.c_int32
     getattr(_lib, _name).argtypes = [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _P,
                                      ctypes.POINTER(QueryStats), _P]
+_lib.evq_query_noalloc.restype = ctypes.c_int32
+_lib.evq_query_noalloc.argtypes = [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _P, _P]
 _lib.evq_query_bounds.restype = ctypes.c_int32
 _lib.evq_query_bounds.argtypes = [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _P, _P,
                                   _P]
@@ -171,7 +173,7 @@ EXPORTED = ["evq_build", "evq_graph_info_get", "evq_graph_export", "evq_query", 
             "evq_query_plain", "evq_query_sequential", "evq_query_batch", "evq_result_expand", "evq_result_free",
             "evq_batch_config_get", "evq_batch_config_set", "evq_batch_autotune", "evq_expand", "evq_append", "evq_server_create",
             "evq_server_submit", "evq_server_poll", "evq_server_pending", "evq_server_destroy", "evq_free", "evq_last_error", "evq_timing_enable",
-            "evq_timing_reset", "evq_timing_report", "evq_gather_ceiling", "evq_tuning_get", "evq_tuning_set"]
+            "evq_timing_reset", "evq_timing_report", "evq_gather_ceiling", "evq_tuning_get", "evq_tuning_set", "evq_query_noalloc"]
 
 
 class EvqError(RuntimeError):
@@ -314,6 +316,16 @@ class Graph:
         _check(_lib.evq_query(self._h, algo, source, win_begin, L, _ptr(out),
                               ctypes.byref(st) if st is not None else None, _stream(stream)))
         return (out, st.as_dict()) if stats else out
+
+    def query_noalloc(self, algo, source, win_begin=None, win_len=None, out=None, stream=None):
+        """Same output as query(), from a call that allocates nothing (evq_query_noalloc); it returns
+        once the values are complete.  `out` should be allocated beforehand by callers that cannot
+        allocate."""
+        algo = ALGOS.get(algo, algo)
+        win_begin, L = self._window(win_begin, win_len)
+        out = self._alloc(L, out)
+        _check(_lib.evq_query_noalloc(self._h, algo, source, win_begin, L, _ptr(out), _stream(stream)))
+        return out
 
     def query_plain(self, algo, source, win_begin=None, win_len=None, out=None, stats=False, stream=None):
         """Same output as query(), without the intersection-union analysis (evq_query_plain)."""

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libevq.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["runtime.hip", "build.hip", "solve.hip", "query.hip", "batch.hip", "serve.hip", "ceiling.hip", "reverse.hip", "api.hip"]
+SOURCES = ["runtime.hip", "build.hip", "solve.hip", "query.hip", "batch.hip", "serve.hip", "ceiling.hip", "reverse.hip", "noalloc.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

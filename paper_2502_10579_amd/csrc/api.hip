@@ -172,6 +172,48 @@ evq_status evq_query(const evq_graph* h, uint32_t algo, uint32_t source, uint32_
     }
 }
 
+evq_status evq_query_noalloc(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t win_begin,
+                             uint32_t win_len, uint32_t* d_values, void* stream) {
+    g_last_error.clear();
+    if (!h) return bad(EVQ_EINVAL, "graph handle is NULL");
+    auto gp = h->get();
+    evq::Window W;
+    evq_status rc = make_window(*gp, algo, source, win_begin, win_len, W);
+    if (rc != EVQ_OK) return rc;
+    if (!d_values) return bad(EVQ_EINVAL, "d_values is NULL");
+    try {
+        int dev = 0;
+        EVQ_HIP(hipGetDevice(&dev));
+        if (dev != gp->device) return bad(EVQ_EINVAL, "the graph is on another device than the current one");
+        uint64_t cap = 0;
+        char* base = evq::noalloc_scratch(dev, &cap);
+        static std::mutex busy_mu[64];  // one no-allocation call per device at a time
+        std::unique_lock<std::mutex> busy(busy_mu[dev & 63], std::try_to_lock);
+        if (!busy.owns_lock()) return bad(EVQ_EBUSY, "another evq_query_noalloc call is running on this device");
+        evq::NoAlloc na;
+        na.base = base;
+        na.cap = cap;
+        na.used = evq::kNoAllocSlotBytes;
+        struct Scope {
+            explicit Scope(evq::NoAlloc* p) { evq::noalloc_ctx() = p; }
+            ~Scope() { evq::noalloc_ctx() = nullptr; }
+        } scope(&na);
+        hipStream_t s = (hipStream_t)stream;
+        evq::Workspace::arena(s, na);
+        evq::QueryOut qo;
+        try {
+            evq::run_query(*gp, algo, source, W, d_values, nullptr, nullptr, false, qo, s);
+        } catch (...) {
+            (void)hipStreamSynchronize(s);  // nothing queued may still use the scratch or this version
+            throw;
+        }
+        EVQ_HIP(hipStreamSynchronize(s));
+        return EVQ_OK;
+    } catch (...) {
+        return guard_exc();
+    }
+}
+
 evq_status evq_query_bounds(const evq_graph* h, uint32_t algo, uint32_t source, uint32_t win_begin, uint32_t win_len,
                             uint32_t* d_rcap, uint32_t* d_rcup, void* stream) {
     g_last_error.clear();

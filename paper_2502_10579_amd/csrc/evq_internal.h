@@ -123,9 +123,25 @@ class Arena {
 void* graph_alloc(const Graph& g, uint64_t bytes, hipStream_t s);
 void graph_free(const Graph& g, void* p, hipStream_t s);
 
+// A call that must not allocate (evq_query_noalloc).  While it is set on a
+// thread, the query path takes its device buffers from `base` by bump
+// allocation (the first kNoAllocSlotBytes hold the frontier loops' published
+// counts, which the host reads back with a copy), reads counters into plain
+// host memory, launches untimed and never builds the pull step's reverse CSR.
+struct NoAlloc {
+    char* base = nullptr;
+    uint64_t cap = 0, used = 0;
+};
+constexpr uint64_t kNoAllocSlotBytes = 256;
+NoAlloc*& noalloc_ctx();  // thread-local; null outside such a call
+// Device address of this device's scratch array (looked up once per device)
+// and its size; throws EVQ_EDEVICE if the lookup fails.
+char* noalloc_scratch(int device, uint64_t* bytes);
+
 // Query workspace: device buffers kept between queries on one host thread
 // and stream, grown on demand (growth waits for the stream).  Queries on one
-// stream are ordered, so reuse is safe.
+// stream are ordered, so reuse is safe.  Inside a no-allocation call the
+// thread's arena workspace is used instead (reset by arena()).
 class Workspace {
   public:
     enum Slot {
@@ -133,6 +149,7 @@ class Workspace {
         kTasks, kX, kBatchCap, kBatchCup, kBatchTable, kSlots
     };
     static Workspace& get(hipStream_t s);
+    static Workspace& arena(hipStream_t s, NoAlloc& na);
     void* raw(Slot slot, uint64_t bytes);
     template <typename T>
     T* buf(Slot slot, uint64_t n) {
@@ -144,6 +161,7 @@ class Workspace {
   private:
     explicit Workspace(hipStream_t s) : s_(s) {}
     hipStream_t s_;
+    NoAlloc* na_ = nullptr;
     void* p_[kSlots] = {};
     uint64_t cap_[kSlots] = {};
 };
@@ -152,10 +170,13 @@ void* stream_alloc(uint64_t bytes, hipStream_t s);  // hipMallocAsync from the d
 void stream_free(void* p, hipStream_t s);          // hipFreeAsync (NULL allowed)
 void init_mempool(int device);
 
-// Small pinned host mailbox used to read counters back (one per host thread).
+// Small pinned host mailbox used to read counters back (one per host thread;
+// plain host memory inside a no-allocation call).
 struct Mailbox {
     uint32_t* h = nullptr;
+    bool pinned = true;
     explicit Mailbox(size_t n);
+    explicit Mailbox(uint32_t* plain) : h(plain), pinned(false) {}
     ~Mailbox();
     static Mailbox& get();
 };

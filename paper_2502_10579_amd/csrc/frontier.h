@@ -357,9 +357,37 @@ uint64_t launch_depth();
 // EVQ_TRACE_LOOPS=1: drive_loop prints each iteration's published count to stderr.
 bool trace_loops();
 
+// Inside a no-allocation call: the published counts go to the first words of
+// the scratch array; each batch of launch_depth() + 1 iterations is followed
+// by one copy of its counts to host memory and a stream synchronisation.
+template <typename IssueFn>
+uint64_t drive_loop_sync(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_iters, const char* what,
+                         uint64_t* items, NoAlloc& na) {
+    static_assert(kNoAllocSlotBytes >= 33 * 4, "slots of one batch");
+    uint32_t* dslots = reinterpret_cast<uint32_t*>(na.base);
+    const uint64_t batch = launch_depth() + 1;
+    uint32_t h[33];
+    uint64_t issued = 0, consumed = 0;
+    for (;;) {
+        for (uint64_t j = 0; j < batch; ++j, ++issued) {
+            issue(issued, f_parity, issued == 0, dslots + j);
+            f_parity ^= 1;
+        }
+        EVQ_HIP(hipMemcpyAsync(h, dslots, batch * 4, hipMemcpyDeviceToHost, s));
+        EVQ_HIP(hipStreamSynchronize(s));
+        for (uint64_t j = 0; j < batch; ++j) {
+            if (trace_loops()) fprintf(stderr, "[evq] %s iteration %llu: %u\n", what, (unsigned long long)consumed, h[j]);
+            if (h[j] == 0) return consumed;
+            if (items) *items += h[j];
+            if (++consumed > max_iters) fail(EVQ_ENOCONV, std::string(what) + " exceeded its iteration cap");
+        }
+    }
+}
+
 template <typename IssueFn>
 uint64_t drive_loop(IssueFn issue, int& f_parity, hipStream_t s, uint64_t max_iters, const char* what,
                     uint64_t* items) {
+    if (NoAlloc* na = noalloc_ctx()) return drive_loop_sync(issue, f_parity, s, max_iters, what, items, *na);
     const uint64_t kDepth = launch_depth();
     HostSlots& hs = HostSlots::get();
     uint64_t issued = 0, consumed = 0;

@@ -1110,7 +1110,7 @@ void answer(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uin
 void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values,
                uint32_t* d_rcap_out, uint32_t* d_rcup_out, bool bounds_only, QueryOut& qo, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
-    init_mempool(g.device);
+    if (!noalloc_ctx()) init_mempool(g.device);
     Workspace& ws = Workspace::get(s);
     const bool st = qo.want_stats;
     Timer tm(st, s);
@@ -1126,7 +1126,8 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
         ws.in_use = false;
         return;
     }
-    answer(g, algo, source, W, rcap, rcup, f, ws, d_values, W.L, qo, s, tm, 0, SplitRule::get());
+    answer(g, algo, source, W, rcap, rcup, f, ws, d_values, W.L, qo, s, tm, 0,
+           noalloc_ctx() ? SplitRule{} : SplitRule::get());
     ws.in_use = false;
     if (st) {
         qo.st.ms_cap = tm.ms(0, 1);
@@ -1154,7 +1155,7 @@ void run_bounds(const Graph& g, uint32_t algo, uint32_t source, const Window& W,
 void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Window& W, Compact& c, QueryOut& qo,
                        hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
-    init_mempool(g.device);
+    if (!noalloc_ctx()) init_mempool(g.device);
     Workspace& ws = Workspace::get(s);
     const bool st = qo.want_stats;
     Timer tm(st, s);
@@ -1179,7 +1180,7 @@ void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Win
 void run_tail_compact(const Graph& g, uint32_t algo, uint32_t source, const Window& W, const uint32_t* rcup,
                       Compact& c, QueryOut& qo, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
-    init_mempool(g.device);
+    if (!noalloc_ctx()) init_mempool(g.device);
     Workspace& ws = Workspace::get(s);
     const bool st = qo.want_stats;
     Timer tm(st, s);

@@ -17,6 +17,7 @@ bool reverse_ready(const Graph& g, hipStream_t s) {
         EVQ_HIP(hipStreamWaitEvent(s, g.rv_ready, 0));
         return true;
     }
+    if (noalloc_ctx()) return false;  // a call that must not allocate never builds it
     if (++g.rv_asks < 2) return false;
     const uint32_t V = g.V;
     const uint64_t E = g.E ? g.E : 1;

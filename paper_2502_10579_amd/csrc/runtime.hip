@@ -149,7 +149,31 @@ void init_mempool(int device) {
     done.push_back(device);
 }
 
+namespace {
+thread_local Workspace* t_arena = nullptr;
+}  // namespace
+
+NoAlloc*& noalloc_ctx() {
+    thread_local NoAlloc* p = nullptr;
+    return p;
+}
+
+Workspace& Workspace::arena(hipStream_t s, NoAlloc& na) {
+    if (!t_arena) t_arena = new Workspace(s);  // host object only, once per thread
+    Workspace& w = *t_arena;
+    w.s_ = s;
+    w.na_ = &na;
+    for (int i = 0; i < kSlots; ++i) {
+        w.p_[i] = nullptr;
+        w.cap_[i] = 0;
+    }
+    w.fresh_flags = true;  // the scratch holds whatever the last call left
+    w.in_use = false;
+    return w;
+}
+
 Workspace& Workspace::get(hipStream_t s) {
+    if (noalloc_ctx() && t_arena) return *t_arena;
     thread_local std::vector<std::pair<std::pair<int, hipStream_t>, Workspace*>> all;  // per thread
     int dev = 0;
     EVQ_HIP(hipGetDevice(&dev));
@@ -165,6 +189,18 @@ Workspace& Workspace::get(hipStream_t s) {
 void* Workspace::raw(Slot slot, uint64_t bytes) {
     if (bytes == 0) bytes = 16;
     if (cap_[slot] >= bytes) return p_[slot];
+    if (na_) {  // bump allocation in the caller-less scratch array
+        const uint64_t want = (bytes + 255) & ~uint64_t(255);
+        if (na_->used + want > na_->cap)
+            fail(EVQ_ERANGE, "the query needs more than the " + std::to_string(na_->cap >> 20) +
+                                 " MiB scratch of evq_query_noalloc (" + std::to_string((na_->used + want) >> 20) +
+                                 " MiB asked for so far); use evq_query");
+        p_[slot] = na_->base + na_->used;
+        cap_[slot] = want;
+        na_->used += want;
+        if (slot == kFlags) fresh_flags = true;
+        return p_[slot];
+    }
     if (p_[slot]) {
         stream_free(p_[slot], s_);
         p_[slot] = nullptr;
@@ -225,10 +261,15 @@ Mailbox::Mailbox(size_t n) {
 }
 
 Mailbox::~Mailbox() {
-    if (h) (void)hipHostFree(h);
+    if (h && pinned) (void)hipHostFree(h);
 }
 
 Mailbox& Mailbox::get() {
+    if (noalloc_ctx()) {
+        thread_local uint32_t plain[16];
+        thread_local Mailbox pmb(plain);
+        return pmb;
+    }
     thread_local Mailbox* mb = new Mailbox(16);  // lives as long as the thread
     return *mb;
 }
@@ -378,7 +419,7 @@ void drain_locked(TimingState& t) {
 bool timing_on() { return ts().on; }
 
 TimingScope::TimingScope(const char* n, hipStream_t st) : name(n), s(st) {
-    if (!ts().on) return;
+    if (!ts().on || noalloc_ctx()) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
         a = b = nullptr;
         return;
