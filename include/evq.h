@@ -222,7 +222,7 @@ evq_status evq_query(const evq_graph* g, uint32_t algo, uint32_t source, uint32_
  * sub-window splitting is done.  `stream` must belong to the graph's device,
  * which must be current.
  * Errors: as evq_query, plus EVQ_ERANGE when the query's temporaries (about
- * 45 bytes per vertex, plus the reduced subgraph and the unstable rows)
+ * 70 bytes per vertex, plus the reduced subgraph and the unstable rows)
  * exceed the array (nothing is left half-written that a later call depends
  * on), EVQ_EBUSY when another call of this entry point is running on the
  * device (calls that overlap on one GPU would race for the array: they are
@@ -372,8 +372,20 @@ evq_status evq_batch_config_set(const evq_batch_config* c);
  *                 (near/far); with heavy > 0 as well only vertices with at
  *                 least heavy edges are deferred and the threshold follows
  *                 the frontier's best key plus delta (default 0: off).
- * evq_tuning_set: EVQ_EINVAL on NULL, launch_depth outside 1..32 or
- * split_min == 0; calls already running keep the values they started with.
+ *   append_edges  EVQ_APPEND_EDGES: a bound-solve iteration whose frontier
+ *                 has at most this many edges lists the next frontier itself
+ *                 (each improved vertex once, by a per-vertex stamp) instead
+ *                 of marking flags for a compaction to scan (default 131072;
+ *                 0: never).
+ *   append_items  EVQ_APPEND_ITEMS: ... likewise an iteration whose frontier
+ *                 has at most this many vertices (default 0: never).
+ *   relax_staged  EVQ_RELAX_STAGED: the multi-snapshot relaxation stages each
+ *                 block's tasks and their edge records in LDS, 2 or 4 tasks
+ *                 per lane group (default 2; 0: each lane group loads its own
+ *                 task's records).
+ * evq_tuning_set: EVQ_EINVAL on NULL, launch_depth outside 1..32,
+ * split_min == 0 or relax_staged not 0, 2 or 4; calls already running keep
+ * the values they started with.
  */
 typedef struct {
     double pull_frac;
@@ -385,7 +397,9 @@ typedef struct {
     uint32_t trace_loops;
     uint32_t delta[5];
     uint32_t heavy[5];
-    uint32_t reserved;
+    uint32_t append_edges;
+    uint32_t relax_staged;
+    uint32_t append_items;
 } evq_tuning;
 
 evq_status evq_tuning_get(evq_tuning* t);

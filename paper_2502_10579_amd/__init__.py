@@ -99,7 +99,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("pull_frac", ctypes.c_double), ("split_frac", ctypes.c_double), ("split_min", ctypes.c_uint32),
                 ("launch_depth", ctypes.c_uint32), ("direct_tasks", ctypes.c_uint32),
                 ("append_rebuild", ctypes.c_uint32), ("trace_loops", ctypes.c_uint32),
-                ("delta", ctypes.c_uint32 * 5), ("heavy", ctypes.c_uint32 * 5), ("reserved", ctypes.c_uint32)]
+                ("delta", ctypes.c_uint32 * 5), ("heavy", ctypes.c_uint32 * 5), ("append_edges", ctypes.c_uint32),
+                ("relax_staged", ctypes.c_uint32), ("append_items", ctypes.c_uint32)]
 
 
 class KernelTime(ctypes.Structure):

@@ -105,7 +105,7 @@ evq_status evq_graph_info_get(const evq_graph* h, evq_graph_info* info) {
     info->device_bytes = g.bytes;
     {
         std::lock_guard<std::mutex> lk(g.rv_mu);  // reverse CSR of the pull step, once built
-        if (g.rv_built) info->device_bytes += (g.E ? g.E : 1) * 8 + ((uint64_t)g.V * 4 + 4) * 2 + 8;
+        if (g.rv_built) info->device_bytes += (g.E ? g.E : 1) * 12 + 8;
     }
     info->build_ms = g.build_ms;
     info->first_snapshot = g.first;

@@ -66,7 +66,7 @@ struct LaneGroup {
 // of a union row; the packed reservation counts vertices and tasks.  Union
 // rows of hubs have 10^4-10^5 tasks, so k_btasks writes them (write_tasks).
 __global__ void __launch_bounds__(kCompactBlock) k_bcompact(BatchArgs a, int p, int first) {
-    if (nothing_pending(a.cnt, p, first)) return;
+    if (compaction_skips(a.cnt, p, first)) return;
     compact_flags(
         a.flags, a.V, &a.cnt->packed[p], &a.cnt->far[p], &a.cnt->fmin[p],
         [&](uint32_t v, uint32_t& items, uint32_t& tasks, uint32_t&) {

@@ -15,6 +15,14 @@ struct Frontier {
     uint32_t* fd = nullptr;      //   row begin minus that offset,
     uint32_t* fs = nullptr;      //   end of the row's all-present prefix,
     uint32_t* fv = nullptr;      //   the vertex
+    uint32_t* fo1 = nullptr;     // the same four arrays for odd iterations (bound solves, appending expansions)
+    uint32_t* fd1 = nullptr;
+    uint32_t* fs1 = nullptr;
+    uint32_t* fv1 = nullptr;
+    uint32_t* stamp = nullptr;   // per vertex: epoch of the iteration that last appended it
+    uint32_t* epoch = nullptr;   // host: the workspace's epoch counter (one per issued iteration)
+    uint32_t append_edges = 0;   // appending expansions up to this many frontier edges (0: never)
+    uint32_t append_items = 0;   // ... or up to this many frontier vertices (0: never)
     FrontierCounters* cnt = nullptr;
     unsigned long long* stats = nullptr;  // [0] bound-solve edge visits, [1..] relaxer counters
     unsigned long long* aux = nullptr;    // 128 bytes of scratch counters for the reduction

@@ -974,35 +974,20 @@ __global__ void __launch_bounds__(256) k_rv_keys(const uint32_t* __restrict__ ro
     }
 }
 
-// Sorted keys -> source and weight per in-edge, a head flag where the
-// destination changes, and the in-edge count (written by the last real key).
+// Sorted keys -> source, weight and destination per in-edge, and the in-edge
+// count (written by the last real key).
 template <typename KT>
 __global__ void k_rv_decode(const KT* __restrict__ keys, uint64_t E, int vb, int wb, uint32_t* __restrict__ src,
-                            uint32_t* __restrict__ w, uint32_t* __restrict__ head, uint32_t* __restrict__ cnt) {
+                            uint32_t* __restrict__ w, uint32_t* __restrict__ dst, uint32_t* __restrict__ cnt) {
     const KT none = ~(KT)0;
     const KT vmask = ((KT)1 << vb) - 1, wmask = ((KT)1 << wb) - 1;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < E; i += (uint64_t)gridDim.x * blockDim.x) {
         const KT k = keys[i];
-        uint32_t h = 0;
         if (k != none) {
             src[i] = (uint32_t)((k >> wb) & vmask);
             w[i] = (uint32_t)(k & wmask);
-            h = (i == 0 || (keys[i - 1] >> (vb + wb)) != (k >> (vb + wb))) ? 1u : 0u;
+            dst[i] = (uint32_t)(k >> (vb + wb));
             if (i + 1 == E || keys[i + 1] == none) cnt[1] = (uint32_t)(i + 1);
-        }
-        head[i] = h;
-    }
-}
-
-// Heads -> items: first in-edge and destination of every vertex with in-edges.
-template <typename KT>
-__global__ void k_rv_items(const KT* __restrict__ keys, const uint32_t* __restrict__ head,
-                           const uint32_t* __restrict__ pos, uint64_t E, int vb, int wb, uint32_t* __restrict__ io,
-                           uint32_t* __restrict__ iv) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < E; i += (uint64_t)gridDim.x * blockDim.x) {
-        if (head[i]) {
-            io[pos[i]] = (uint32_t)i;
-            iv[pos[i]] = (uint32_t)(keys[i] >> (vb + wb));
         }
     }
 }
@@ -1015,21 +1000,17 @@ void reverse_sorted(const Graph& g, int vb, int wb, hipStream_t s, Arena& ar) {
     EVQ_LAUNCH("reverse_keys", k_rv_keys<KT>, grid_for((uint64_t)g.V * 64, 256, 8192), 256, s, g.row_ptr,
                g.row_split, g.col, g.wgt, g.V, vb, wb, keys);
     KT* sorted = radix_sort(keys, tmp, E, 2 * vb + wb + 1, s, ar);
-    uint32_t* head = ar.alloc<uint32_t>(E);
-    uint32_t* pos = ar.alloc<uint32_t>(E);
     const uint32_t blocks = grid_for(E, 256, 65536);
-    EVQ_LAUNCH("reverse_decode", k_rv_decode<KT>, blocks, 256, s, sorted, E, vb, wb, g.rv_src, g.rv_w, head,
+    EVQ_LAUNCH("reverse_decode", k_rv_decode<KT>, blocks, 256, s, sorted, E, vb, wb, g.rv_src, g.rv_w, g.rv_dst,
                g.rv_cnt);
-    scan_exclusive(head, pos, E, g.rv_cnt, s, ar);
-    EVQ_LAUNCH("reverse_items", k_rv_items<KT>, blocks, 256, s, sorted, head, pos, E, vb, wb, g.rv_io, g.rv_iv);
 }
 
 }  // namespace
 
 void free_graph(Graph* g, hipStream_t s) {
     if (!g) return;
-    void* arrays[14] = {g->row_ptr, g->row_split, g->col,   g->wgt,   g->mask,  g->p_src, g->p_dst,
-                        g->p_w,     g->p_mask,    g->rv_src, g->rv_w, g->rv_io, g->rv_iv, g->rv_cnt};
+    void* arrays[13] = {g->row_ptr, g->row_split, g->col,  g->wgt,   g->mask,   g->p_src, g->p_dst,
+                        g->p_w,     g->p_mask,    g->rv_src, g->rv_w, g->rv_dst, g->rv_cnt};
     if (g->has_ua) {
         // the caller's allocator frees on the host: the work on s that uses the arrays completes first
         if (s) (void)hipStreamSynchronize(s);

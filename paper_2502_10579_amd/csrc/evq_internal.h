@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -71,11 +72,10 @@ struct Graph {
     mutable uint32_t rv_asks = 0;
     mutable bool rv_built = false;
     mutable hipEvent_t rv_ready = nullptr;
-    mutable uint32_t* rv_src = nullptr;  // source of each in-edge (capacity E)
+    mutable uint32_t* rv_src = nullptr;  // source of each in-edge (capacity E), grouped by destination
     mutable uint32_t* rv_w = nullptr;    // its weight (capacity E)
-    mutable uint32_t* rv_io = nullptr;   // first in-edge of each destination with in-edges (capacity V)
-    mutable uint32_t* rv_iv = nullptr;   // that destination (capacity V)
-    mutable uint32_t* rv_cnt = nullptr;  // [0] destinations with in-edges, [1] in-edges (device)
+    mutable uint32_t* rv_dst = nullptr;  // its destination (capacity E), ascending
+    mutable uint32_t* rv_cnt = nullptr;  // [1] in-edges (device)
 };
 
 // Records that work reading g was queued on s (call after the last launch).
@@ -145,8 +145,8 @@ char* noalloc_scratch(int device, uint64_t* bytes);
 class Workspace {
   public:
     enum Slot {
-        kFlags, kFo, kFd, kFs, kFv, kControl, kRcap, kRcup, kCidOf, kUlist, kCuo, kRv, kRc, kRuo, kKc, kRecs,
-        kTasks, kX, kBatchCap, kBatchCup, kBatchTable, kSlots
+        kFlags, kFo, kFd, kFs, kFv, kFo1, kFd1, kFs1, kFv1, kStamp, kControl, kRcap, kRcup, kCidOf, kUlist, kCuo,
+        kRv, kRc, kRuo, kKc, kRecs, kTasks, kX, kBatchCap, kBatchCup, kBatchTable, kSlots
     };
     static Workspace& get(hipStream_t s);
     static Workspace& arena(hipStream_t s, NoAlloc& na);
@@ -157,6 +157,8 @@ class Workspace {
     }
     bool fresh_flags = true;  // flags must be cleared before use
     bool in_use = false;      // a query is running on it (a failed one leaves flags unknown)
+    uint32_t epoch = 0;               // last epoch handed to an expansion (appending iterations)
+    const void* stamp_seen = nullptr; // stamp buffer those epochs refer to (cleared when it changes)
 
   private:
     explicit Workspace(hipStream_t s) : s_(s) {}
@@ -227,8 +229,8 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
 // The next version of a graph: snapshot first+K (old newest with batch b
 // applied) replaces snapshot `first` in its mask bit.  `old` is not changed.
 Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s);
-// Fills g's reverse CSR arrays (allocated by the caller: rv_src and rv_w with
-// E entries, rv_io and rv_iv with V, rv_cnt with 2) on s.
+// Fills g's reverse CSR arrays (allocated by the caller: rv_src, rv_w and
+// rv_dst with E entries, rv_cnt with 2) on s.
 void build_reverse(const Graph& g, hipStream_t s);
 // Releases g's device arrays, ordered on s, and deletes g.
 void free_graph(Graph* g, hipStream_t s);
@@ -247,6 +249,7 @@ struct Window {
 struct QueryOut {
     evq_query_stats st{};
     bool want_stats = false;
+    std::chrono::steady_clock::time_point bounds_done{};  // host time the bound solves drained
 };
 
 void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* d_values,
@@ -266,9 +269,6 @@ struct Compact {
     uint32_t nU = 0, LG = 0;
 };
 
-// Both bounds of one query into device arrays of V values.
-void run_bounds(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* rcap, uint32_t* rcup,
-                QueryOut& qo, hipStream_t s);
 // Whole query with a compact result (bound solves into c.rcap).
 void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Window& W, Compact& c, QueryOut& qo,
                        hipStream_t s);

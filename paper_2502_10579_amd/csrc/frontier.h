@@ -9,11 +9,16 @@
 // same order.
 //
 // Counters are double-buffered by iteration parity p: the compaction of
-// iteration i adds into cnt[p]; the expansion of iteration i reads cnt[p],
-// zeroes cnt[p ^ 1] for the next compaction and publishes its item count to a
-// host-mapped slot, so the host never has to synchronise the stream to learn
-// when a loop has drained.  A compaction that finds the previous expansion
-// empty returns at once, so iterations issued past the end cost one launch.
+// iteration i zeroes cnt[p ^ 1] (the previous iteration's, whose readers have
+// finished) and adds into cnt[p]; the expansion of iteration i reads cnt[p],
+// tells the next compaction whether it produced work, and publishes its item
+// count to a host-mapped slot, so the host never has to synchronise the
+// stream to learn when a loop has drained.  A compaction that finds the
+// previous expansion empty returns at once, so iterations issued past the end
+// cost one launch.  In a sparse iteration the bound solves' expansion may
+// instead append its improved vertices to the next work list itself (into
+// cnt[p ^ 1], zeroed by the compaction before it); the next compaction then
+// skips its scan.
 #pragma once
 
 #include "evq_internal.h"
@@ -28,6 +33,8 @@ struct FrontierCounters {
     uint32_t delta;                // threshold step (0: every id is near)
     uint32_t heavy;                // with delta > 0: only ids with at least this many edges are gated (0: all)
     uint32_t kall[2];              // smallest order key over the compacted ids with edges, by parity (heavy > 0)
+    uint32_t status[2];            // for the compaction of parity q: bit 0 the expansion before it had work
+                                   // or deferred ids, bit 1 it appended the next list itself
 };
 
 __device__ __forceinline__ uint32_t items_of(unsigned long long x) { return (uint32_t)(x >> 32); }
@@ -40,15 +47,18 @@ __device__ __forceinline__ void mark(uint8_t* __restrict__ flags, uint32_t v) { 
 // Bytes of the flag array for n ids (a multiple of the 8 ids a lane reads).
 inline uint64_t flag_bytes(uint64_t n) { return (n + 7) & ~uint64_t(7); }
 
-// Expansion prologue: read this iteration's counts, clear the other parity,
-// publish the item count to the host slot.
+// Expansion prologue: read this iteration's counts, tell the next compaction
+// whether there was work and whether this expansion appends the next list
+// itself (`appends`, the same on every block), publish the item count to the
+// host slot.
 // When nothing was near but ids were deferred, the threshold moves to the
 // smallest deferred order key plus delta, so the next compaction releases the
 // best of them.  When only heavy ids are gated, the threshold also follows the
 // frontier: it rises to the smallest key of this iteration's ids plus delta,
 // so a heavy id is expanded once its value is within delta of the best one
 // still moving (and, with positive steps, close to final).
-__device__ __forceinline__ unsigned long long expand_prologue(FrontierCounters* c, int p, uint32_t* slot) {
+__device__ __forceinline__ unsigned long long expand_prologue(FrontierCounters* c, int p, uint32_t* slot,
+                                                              bool appends = false) {
     const unsigned long long x = c->packed[p];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const uint32_t f = c->far[p];
@@ -59,19 +69,25 @@ __device__ __forceinline__ unsigned long long expand_prologue(FrontierCounters* 
             t = u > t ? u : t;
         }
         c->thr = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
-        c->packed[p ^ 1] = 0ull;
-        c->far[p ^ 1] = 0u;
-        c->fmin[p ^ 1] = 0xFFFFFFFFu;
-        c->kall[p ^ 1] = 0xFFFFFFFFu;
+        c->status[p ^ 1] = (x != 0ull || f ? 1u : 0u) | (appends ? 2u : 0u);
         __hip_atomic_store(slot, items_of(x) + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     return x;
 }
 
-// A compaction may skip its scan when the previous iteration had no work and
-// deferred nothing: then no bit can be set.
-__device__ __forceinline__ bool nothing_pending(const FrontierCounters* c, int p, int first) {
-    return !first && c->packed[p ^ 1] == 0ull && c->far[p ^ 1] == 0u;
+// Compaction prologue: zero the other parity's counters (the previous
+// iteration's, read only by kernels that have finished) for the next
+// iteration, and say whether the scan can be skipped: the previous expansion
+// had no work and deferred nothing (no flag can be set), or it appended the
+// next list itself.  The first compaction of a loop always scans.
+__device__ __forceinline__ bool compaction_skips(FrontierCounters* c, int p, int first) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->packed[p ^ 1] = 0ull;
+        c->far[p ^ 1] = 0u;
+        c->fmin[p ^ 1] = 0xFFFFFFFFu;
+        c->kall[p ^ 1] = 0xFFFFFFFFu;
+    }
+    return !first && c->status[p] != 1u;
 }
 
 // Largest i in [0, n) with off[i] <= x (off ascending, off[0] == 0), found by

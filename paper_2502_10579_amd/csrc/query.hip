@@ -337,7 +337,7 @@ __device__ __forceinline__ void add_stat(unsigned long long* p, uint32_t v) {
 // most of an iteration's tasks alone, so k_relax_tasks writes them instead.
 template <bool DIRECT>
 __global__ void __launch_bounds__(kCompactBlock) k_relax_compact(RelaxArgs r, int p, int first) {
-    if (nothing_pending(r.cnt, p, first)) return;
+    if (compaction_skips(r.cnt, p, first)) return;
     __shared__ TaskList tl;
     if (DIRECT) task_list_init(tl);
     compact_flags(
@@ -517,6 +517,111 @@ __global__ void __launch_bounds__(kBlock)
             add_stat<true>(&r.stats[1], i0 == 0 ? ne : 0u);
             add_stat<true>(&r.stats[2], lanes_done);
         }
+    }
+}
+
+// The same iteration with the block staging its tasks in LDS: each round the
+// block takes (waves x lane groups x kStagePerWave) tasks, its threads load
+// their headers (task, row start and length) and then all their edge records
+// (one load each), and after a barrier every lane group takes kStagePerWave
+// (2 or 4) of the staged tasks and issues the source rows and the destination
+// rows of all of them before any update.  A task's records then cost one
+// coalesced load per thread of the block instead of a chain of dependent
+// loads per group, and each group keeps kStagePerWave * (1 + 8) row loads in
+// flight (Section 4.2: edge records and hot frontier chunks staged on chip,
+// values laid out snapshot-minor).
+template <int A, int LG, int kStagePerWave, bool ST>
+__global__ void __launch_bounds__(kBlock)
+    k_relax_staged(RelaxArgs r, const uint64_t* __restrict__ tasks, const uint32_t* __restrict__ cuo,
+                   const uint32_t* __restrict__ kc, const void* __restrict__ recs_v, int p, uint32_t* slot) {
+    using T = Lanes<LG>;
+    constexpr int kGroups = (kBlock / 64) * T::G;             // lane groups per block
+    constexpr int kStageTasks = kGroups * kStagePerWave;      // tasks per round
+    constexpr int kStageRecs = kStageTasks * (int)kRelaxChunk;
+    __shared__ uint32_t s_c[kStageTasks], s_e0[kStageTasks], s_ne[kStageTasks];
+    __shared__ Rec<T::NLW> s_rec[kStageTasks][kRelaxChunk];
+    const unsigned long long cx = expand_prologue(r.cnt, p, slot);
+    const uint32_t n = edges_of(cx);  // tasks
+    if (n == 0) return;
+    const Rec<T::NLW>* __restrict__ recs = static_cast<const Rec<T::NLW>*>(recs_v);
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const int g = LG >= 64 ? 0 : (int)lane / LG;
+    const int i0 = LG >= 64 ? (int)lane : (int)lane % LG;
+    const uint32_t grp = wave * T::G + g;  // this lane group's index in the block
+    for (uint32_t t0 = blockIdx.x * (uint32_t)kStageTasks; t0 < n; t0 += gridDim.x * (uint32_t)kStageTasks) {
+        for (uint32_t j = threadIdx.x; j < (uint32_t)kStageTasks; j += kBlock) {
+            const uint32_t ti = t0 + j;
+            uint32_t c = 0, e0 = 0, ne = 0;
+            if (ti < n) {
+                const uint64_t tk = tasks[ti];
+                c = (uint32_t)tk;
+                const uint32_t rb = cuo[c], re = rb + kc[c];
+                e0 = rb + (uint32_t)(tk >> 32) * kRelaxChunk;
+                ne = re - e0 < kRelaxChunk ? re - e0 : kRelaxChunk;
+            }
+            s_c[j] = c;
+            s_e0[j] = e0;
+            s_ne[j] = ne;
+        }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < (uint32_t)kStageRecs; j += kBlock) {
+            const uint32_t tt = j / kRelaxChunk, k = j % kRelaxChunk;
+            Rec<T::NLW> rc;
+            rc.dst = 0;
+            rc.w = 0;
+#pragma unroll
+            for (int q = 0; q < T::NLW; ++q) rc.lanes[q] = 0;
+            if (k < s_ne[tt]) rc = recs[s_e0[tt] + k];
+            s_rec[tt][k] = rc;
+        }
+        __syncthreads();
+        uint32_t xu[kStagePerWave][T::SPL];
+        uint32_t cur[kStagePerWave][kRelaxChunk][T::SPL];
+#pragma unroll
+        for (int q = 0; q < kStagePerWave; ++q) {
+            const uint32_t tt = grp * kStagePerWave + q;
+            const uint32_t c = s_c[tt], ne = s_ne[tt];
+#pragma unroll
+            for (int s = 0; s < T::SPL; ++s)
+                xu[q][s] = ne ? r.X[(uint64_t)c * T::S + i0 + 64 * s] : Alg<A>::unreached;
+#pragma unroll
+            for (uint32_t k = 0; k < kRelaxChunk; ++k)
+#pragma unroll
+                for (int s = 0; s < T::SPL; ++s) {
+                    const int i = i0 + 64 * s;
+                    const bool bit = (s_rec[tt][k].lanes[s] >> (i & 63)) & 1ull;
+                    cur[q][k][s] = bit ? r.X[(uint64_t)s_rec[tt][k].dst * T::S + i] : Alg<A>::unreached;
+                }
+        }
+        uint32_t lanes_done = 0, edges_done = 0;
+#pragma unroll
+        for (int q = 0; q < kStagePerWave; ++q) {
+            const uint32_t tt = grp * kStagePerWave + q;
+            edges_done += s_ne[tt];
+#pragma unroll
+            for (uint32_t k = 0; k < kRelaxChunk; ++k) {
+                const Rec<T::NLW> rc = s_rec[tt][k];
+                bool imp = false;
+#pragma unroll
+                for (int s = 0; s < T::SPL; ++s) {
+                    const int i = i0 + 64 * s;
+                    if ((rc.lanes[s] >> (i & 63)) & 1ull) {
+                        ++lanes_done;
+                        const uint32_t cand = Alg<A>::extend(xu[q][s], rc.w);
+                        if (Alg<A>::better(cand, cur[q][k][s])) {
+                            Alg<A>::improve_nr(&r.X[(uint64_t)rc.dst * T::S + i], cand);
+                            imp = true;
+                        }
+                    }
+                }
+                if (group_any<LG>(imp) && i0 == 0) mark(r.flags, rc.dst);
+            }
+        }
+        if (ST) {
+            add_stat<true>(&r.stats[1], i0 == 0 ? edges_done : 0u);
+            add_stat<true>(&r.stats[2], lanes_done);
+        }
+        __syncthreads();  // the staged tasks are read until here
     }
 }
 
@@ -900,6 +1005,11 @@ void relax_phase(const Graph& g, const Window& W, const Window& PW, const uint32
     const uint32_t tblocks = grid_for(((uint64_t)red.nU + red.TU / kRelaxChunk + 63) / 64, kBlock / 64, 2048);
     const uint32_t rblocks =
         grid_for(((uint64_t)red.nU + red.TU / kRelaxChunk + T::G - 1) / T::G, kBlock / 64, EVQ_RELAX_BLOCKS);
+    // the block stages its tasks in LDS, 2 or 4 per lane group (evq_tuning.relax_staged); the one-lane
+    // layout of the sequential ablation keeps the per-group kernel
+    const uint32_t staged = LG >= 8 ? tuning().relax_staged : 0u;
+    const uint32_t sblocks = grid_for((uint64_t)red.nU + red.TU / kRelaxChunk,
+                                      (kBlock / 64) * T::G * (staged ? staged : 1), EVQ_RELAX_BLOCKS);
     auto issue = [&](uint64_t, int p, bool first, uint32_t* slot) {
         if (direct) {
             EVQ_LAUNCH("relax_compact", k_relax_compact<true>, cblocks, kCompactBlock, s, ra, p, first ? 1 : 0);
@@ -907,7 +1017,14 @@ void relax_phase(const Graph& g, const Window& W, const Window& PW, const uint32
             EVQ_LAUNCH("relax_compact", k_relax_compact<false>, cblocks, kCompactBlock, s, ra, p, first ? 1 : 0);
             EVQ_LAUNCH("relax_tasks", k_relax_tasks, tblocks, kBlock, s, ra, p);
         }
-        EVQ_LAUNCH("relax", (k_relax<A, LG, ST>), rblocks, kBlock, s, ra, ra.tasks, ra.cuo, ra.kc, ra.recs, p, slot);
+        if (staged == 2)
+            EVQ_LAUNCH("relax", (k_relax_staged<A, (LG >= 8 ? LG : 8), 2, ST>), sblocks, kBlock, s, ra, ra.tasks,
+                       ra.cuo, ra.kc, ra.recs, p, slot);
+        else if (staged == 4)
+            EVQ_LAUNCH("relax", (k_relax_staged<A, (LG >= 8 ? LG : 8), 4, ST>), sblocks, kBlock, s, ra, ra.tasks,
+                       ra.cuo, ra.kc, ra.recs, p, slot);
+        else
+            EVQ_LAUNCH("relax", (k_relax<A, LG, ST>), rblocks, kBlock, s, ra, ra.tasks, ra.cuo, ra.kc, ra.recs, p, slot);
     };
     qo.st.iters_relax = drive_loop(issue, f.p, s, (uint64_t)g.V + 2, "snapshot relaxation");
 }
@@ -1140,18 +1257,6 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     }
 }
 
-void run_bounds(const Graph& g, uint32_t algo, uint32_t source, const Window& W, uint32_t* rcap, uint32_t* rcup,
-                QueryOut& qo, hipStream_t s) {
-    init_mempool(g.device);
-    Workspace& ws = Workspace::get(s);
-    Timer tm(false, s);
-    Frontier f = make_frontier(g, ws, s);
-    f.delta = choose_delta(algo);
-    f.heavy = choose_heavy(algo);
-    bounds_impl(g, algo, source, W, rcap, rcup, f, qo, s, tm);
-    ws.in_use = false;
-}
-
 void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Window& W, Compact& c, QueryOut& qo,
                        hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
@@ -1165,6 +1270,7 @@ void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Win
     f.heavy = choose_heavy(algo);
     uint32_t* rcup = ws.buf<uint32_t>(Workspace::kRcup, g.V);
     bounds_impl(g, algo, source, W, c.rcap, rcup, f, qo, s, tm);
+    qo.bounds_done = std::chrono::steady_clock::now();
     tail_impl(g, algo, source, W, c.rcap, rcup, f, ws, nullptr, &c, qo, s, tm);
     ws.in_use = false;
     if (st) {

@@ -19,17 +19,15 @@ bool reverse_ready(const Graph& g, hipStream_t s) {
     }
     if (noalloc_ctx()) return false;  // a call that must not allocate never builds it
     if (++g.rv_asks < 2) return false;
-    const uint32_t V = g.V;
     const uint64_t E = g.E ? g.E : 1;
     try {
         g.rv_src = (uint32_t*)graph_alloc(g, E * 4, s);
         g.rv_w = (uint32_t*)graph_alloc(g, E * 4, s);
-        g.rv_io = (uint32_t*)graph_alloc(g, (uint64_t)V * 4 + 4, s);
-        g.rv_iv = (uint32_t*)graph_alloc(g, (uint64_t)V * 4 + 4, s);
+        g.rv_dst = (uint32_t*)graph_alloc(g, E * 4, s);
         g.rv_cnt = (uint32_t*)graph_alloc(g, 8, s);
         build_reverse(g, s);
     } catch (...) {
-        uint32_t** arrays[5] = {&g.rv_src, &g.rv_w, &g.rv_io, &g.rv_iv, &g.rv_cnt};
+        uint32_t** arrays[4] = {&g.rv_src, &g.rv_w, &g.rv_dst, &g.rv_cnt};
         for (uint32_t** p : arrays) {
             graph_free(g, *p, s);
             *p = nullptr;

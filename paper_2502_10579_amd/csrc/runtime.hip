@@ -169,6 +169,8 @@ Workspace& Workspace::arena(hipStream_t s, NoAlloc& na) {
     }
     w.fresh_flags = true;  // the scratch holds whatever the last call left
     w.in_use = false;
+    w.stamp_seen = nullptr;
+    w.epoch = 0;
     return w;
 }
 
@@ -327,6 +329,9 @@ evq_tuning tuning_from_env() {
     t.direct_tasks = env_u32("EVQ_DIRECT_TASKS", 1u << 18);
     t.append_rebuild = env_u32("EVQ_APPEND_REBUILD", 0u) != 0;
     t.trace_loops = env_u32("EVQ_TRACE_LOOPS", 0u) != 0;
+    t.append_edges = env_u32("EVQ_APPEND_EDGES", 1u << 17);
+    t.append_items = env_u32("EVQ_APPEND_ITEMS", 0u);
+    t.relax_staged = env_u32("EVQ_RELAX_STAGED", 2u);
     static const char* delta_names[5] = {"EVQ_DELTA_SSSP", "EVQ_DELTA_BFS", "EVQ_DELTA_SSWP", "EVQ_DELTA_SSNP",
                                          "EVQ_DELTA_VITERBI"};
     static const char* heavy_names[5] = {"EVQ_HEAVY_SSSP", "EVQ_HEAVY_BFS", "EVQ_HEAVY_SSWP", "EVQ_HEAVY_SSNP",
@@ -353,6 +358,8 @@ evq_tuning tuning() {
 void set_tuning(const evq_tuning& t) {
     if (t.launch_depth < 1 || t.launch_depth > 32) fail(EVQ_EINVAL, "tuning: launch_depth must be in [1, 32]");
     if (t.split_min < 1) fail(EVQ_EINVAL, "tuning: split_min must be >= 1");
+    if (t.relax_staged != 0 && t.relax_staged != 2 && t.relax_staged != 4)
+        fail(EVQ_EINVAL, "tuning: relax_staged must be 0, 2 or 4");
     std::lock_guard<std::mutex> lk(g_tuning_mu);
     g_tuning = t;
     g_tuning_init = true;

@@ -141,42 +141,33 @@ Window window_of(const Graph& g, const SQuery* q) {
     return W;
 }
 
+// One query alone: bound solves and tail in one call (the per-query method),
+// its bounds-done time taken when the bound solves drain.
+void run_single(evq_server* sv, const Graph& g, SQuery* q, hipStream_t ws) {
+    try {
+        q->c.rcap = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
+        run_query_compact(g, q->algo, q->source, window_of(g, q), q->c, q->qo, ws);
+        q->t_bounds = std::chrono::duration<double, std::milli>(q->qo.bounds_done - sv->t0).count();
+    } catch (...) {
+        fail_query(q, current_error(), ws);
+        q->t_bounds = sv->now();
+    }
+}
+
 void launch_group(evq_server* sv, std::shared_ptr<const Graph> gp, std::vector<SQuery*> grp) {
     Pool& pool = Pool::get(sv->device);
     if (grp.size() == 1) {
-        // one query: its own bound solves (one value per vertex), then its tail
+        // one query: the single-query path, as the plain server runs it
         SQuery* q = grp[0];
         pool.submit([sv, gp, q](hipStream_t ws) {
             const Graph& g = *gp;
             UseGuard ug{g, ws};
-            const Window W = window_of(g, q);
-            bool ok = true;
-            try {
-                q->c.rcap = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
-                q->rcup = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
-                run_bounds(g, q->algo, q->source, W, q->c.rcap, q->rcup, q->qo, ws);
-                q->t_bounds = sv->now();
-            } catch (...) {
-                ok = false;
-                fail_query(q, current_error(), ws);
-            }
+            run_single(sv, g, q, ws);
             {
                 std::lock_guard<std::mutex> lk(sv->mu);
                 sv->groups -= 1;
             }
             sv->cv.notify_all();
-            if (ok) {
-                try {
-                    run_tail_compact(g, q->algo, q->source, W, q->rcup, q->c, q->qo, ws);
-                } catch (...) {
-                    fail_query(q, current_error(), ws);
-                }
-            }
-            try {
-                stream_free(q->rcup, ws);
-            } catch (...) {
-            }
-            q->rcup = nullptr;
             complete(sv, q, g, ws);
         });
         return;
@@ -275,14 +266,8 @@ void dispatch_loop(evq_server* sv) {
             lk.unlock();
             Pool::get(sv->device).submit([sv, gp, q](hipStream_t ws) {
                 const Graph& g = *gp;
-            UseGuard ug{g, ws};
-                try {
-                    q->c.rcap = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
-                    run_query_compact(g, q->algo, q->source, window_of(g, q), q->c, q->qo, ws);
-                } catch (...) {
-                    fail_query(q, current_error(), ws);
-                }
-                q->t_bounds = sv->now();
+                UseGuard ug{g, ws};
+                run_single(sv, g, q, ws);
                 complete(sv, q, g, ws);
             });
             lk.lock();

@@ -15,7 +15,9 @@
 //               edges per step, each lane locating its edge's vertex with a
 //               binary search over 64 offsets held in registers.  In the
 //               dense iterations of the full-window intersection solve the
-//               expansion pulls instead (every vertex over its in-edges).
+//               expansion pulls instead (every vertex over its in-edges); in
+//               sparse ones it lists the next frontier itself and the next
+//               compaction skips its scan.
 // Values improve with fire-and-forget uint32 atomicMin/atomicMax after a plain
 // read shows the candidate is better; improved vertices set their bit.
 #include "bounds.h"
@@ -56,10 +58,19 @@ struct SolveArgs {
     const uint64_t* mask;
     uint32_t* R;
     uint8_t* flags;
-    uint32_t* fo;  // frontier item: first edge offset in the frontier's edge range
-    uint32_t* fd;  // row begin minus that offset (edge id = frontier offset + fd)
-    uint32_t* fs;  // end of the row's all-present prefix
-    uint32_t* fv;  // the vertex (its value is read when expanded: fresher values save work)
+    // Frontier items, one set per iteration parity (a compaction writes its
+    // parity's set, an expansion reads it and, when it appends the next list
+    // itself, writes the other):
+    uint32_t* fo[2];  // first edge offset in the frontier's edge range
+    uint32_t* fd[2];  // row begin minus that offset (edge id = frontier offset + fd)
+    uint32_t* fs[2];  // end of the row's all-present prefix
+    uint32_t* fv[2];  // the vertex (its value is read when expanded: fresher values save work)
+    // Appending expansions: the iteration that last listed each vertex (an
+    // iteration's epoch is above every earlier one on this workspace), and the
+    // largest frontier edge count at which an expansion appends (0: never).
+    uint32_t* stamp;
+    uint32_t append_edges;
+    uint32_t append_items;  // ... or at most this many frontier vertices (0: never)
     FrontierCounters* cnt;
     unsigned long long* stats;
     uint32_t V;
@@ -67,8 +78,7 @@ struct SolveArgs {
     // the all-present edges from which an iteration pulls (kNone: never)
     const uint32_t* rv_src;
     const uint32_t* rv_w;
-    const uint32_t* rv_io;
-    const uint32_t* rv_iv;
+    const uint32_t* rv_dst;
     const uint32_t* rv_cnt;
     uint32_t pull_frac;
 };
@@ -128,7 +138,7 @@ __device__ __forceinline__ void count_visits(const SolveArgs& a, uint32_t n) {
 // vertices keep the iterations full.
 template <int A, int MODE>
 __global__ void __launch_bounds__(kCompactBlock) k_compact_frontier(SolveArgs a, int p, int first) {
-    if (nothing_pending(a.cnt, p, first)) return;
+    if (compaction_skips(a.cnt, p, first)) return;
     const uint32_t thr = a.cnt->thr;
     const bool nf = a.cnt->delta != 0;
     const uint32_t heavy = nf ? a.cnt->heavy : 0u;
@@ -142,10 +152,10 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact_frontier(SolveArgs a,
             return key < thr || edges < heavy;
         },
         [&](uint32_t v, uint32_t item, uint32_t edge, uint32_t, uint32_t) {
-            a.fo[item] = edge;
-            a.fd[item] = a.row_ptr[v] - edge;
-            if (MODE != 0) a.fs[item] = a.row_split[v];
-            a.fv[item] = v;
+            a.fo[p][item] = edge;
+            a.fd[p][item] = a.row_ptr[v] - edge;
+            if (MODE != 0) a.fs[p][item] = a.row_split[v];
+            a.fv[p][item] = v;
         },
         heavy ? &a.cnt->kall[p] : nullptr);
 }
@@ -157,33 +167,53 @@ struct Step {
     bool act, want;
 };
 
-// Lane of the 64 held items (first offsets `off`, ascending, all-ones past
-// the list) that owns range position t: the last one starting at or before t.
-__device__ __forceinline__ int owner_lane(uint32_t off, uint32_t t) {
-    int o = 0;
-#pragma unroll
-    for (int step = 32; step >= 1; step >>= 1) {
-        const uint32_t q = __shfl(off, o + step, 64);
-        if (q <= t) o += step;
-    }
-    return o;
-}
-
 // Pull step of the full-window intersection solve.  When most of the graph
 // is in the frontier, pushing costs one atomic per improving edge; instead
 // every vertex takes the best candidate over its all-present in-edges from
 // the current values of their sources (a valid Bellman-Ford step: a value
 // only ever moves to that of a real path, and only when that is better) and
-// writes it once.  The
-// in-edges, grouped by destination, are one range [0, n_in) cut into equal
-// slices per wave as in the push walk; the lanes of a step holding one
-// destination reduce their candidates (segmented scan), and a destination
-// running on into the next step carries its partial best.  A destination
-// whose in-edges all lie in this wave's slice is written with a plain store
-// (no other wave writes it); one cut by a slice boundary uses the atomic.
-// Every improved vertex is marked for the next frontier, as in the push.
+// writes it once.  The in-edges, sorted by destination, are one range
+// [0, n_in) cut into equal slices per wave, walked 64 at a time; each lane
+// holds one in-edge and its destination, the lanes of one destination take
+// their best by a segmented scan over the wave (DPP row shifts, then the row
+// broadcasts), and a destination running on into the next step carries its
+// partial best.  A destination whose in-edges all lie in this wave's slice is
+// written with a plain store (no other wave writes it); one cut by a slice
+// boundary uses the atomic.  Every improved vertex is marked for the next
+// frontier, as in the push.
+
+// DPP move of x from another lane (ctrl), rows outside row_mask and lanes
+// whose source lane is out of range keep `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, ROW_MASK, 0xF, false);
+}
+
+// One round of the segmented scan: take the candidate of the lane CTRL names
+// when it holds the same key (destination) and is better.
+template <int A, int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_round(uint32_t key, uint32_t& c) {
+    const uint32_t ok = dpp_mov<CTRL, ROW_MASK>(kNone, key);
+    const uint32_t oc = dpp_mov<CTRL, ROW_MASK>(Alg<A>::unreached, c);
+    if (ok == key && Alg<A>::better(oc, c)) c = oc;
+}
+
+// Inclusive segmented best-scan over the wave's 64 lanes, segments = runs of
+// equal keys (contiguous): row shifts by 1, 2, 4, 8 within rows of 16 lanes,
+// then lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and 3.
+template <int A>
+__device__ __forceinline__ uint32_t seg_scan(uint32_t key, uint32_t c) {
+    seg_round<A, 0x111, 0xF>(key, c);  // row_shr:1
+    seg_round<A, 0x112, 0xF>(key, c);  // row_shr:2
+    seg_round<A, 0x114, 0xF>(key, c);  // row_shr:4
+    seg_round<A, 0x118, 0xF>(key, c);  // row_shr:8
+    seg_round<A, 0x142, 0xA>(key, c);  // row_bcast:15
+    seg_round<A, 0x143, 0xC>(key, c);  // row_bcast:31
+    return c;
+}
+
 template <int A, bool ST>
-__device__ __forceinline__ void pull_walk(const SolveArgs& a, uint32_t n, uint32_t T) {
+__device__ __forceinline__ void pull_walk(const SolveArgs& a, uint32_t T) {
     const uint32_t lane = lane_id();
     const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
     const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
@@ -195,58 +225,64 @@ __device__ __forceinline__ void pull_walk(const SolveArgs& a, uint32_t n, uint32
     const uint32_t end = (uint32_t)(b0 + Rw < T ? b0 + Rw : T);
     count_visits<ST>(a, lane == 0 ? end - beg : 0u);
     const uint32_t worst = Alg<A>::unreached;
-    uint32_t base = beg;
-    uint32_t cur = wave_search(a.rv_io, n, base);
+    // destinations whose in-edges cross this slice's ends (other waves write them too)
+    const uint32_t v_lo = a.rv_dst[beg], v_hi = a.rv_dst[end - 1];
+    const bool cut_lo = beg > 0 && a.rv_dst[beg - 1] == v_lo;
+    const bool cut_hi = end < T && a.rv_dst[end] == v_hi;
     uint32_t carry_v = kNone, carry_c = worst;
     uint32_t nup = 0;
-    while (base < end) {
-        const uint32_t idx = cur + lane;
-        const uint32_t ii = idx < n ? idx : n - 1;
-        const uint32_t offl = a.rv_io[ii];
-        const uint32_t vl = a.rv_iv[ii];
-        const uint32_t off = idx < n ? offl : kNone;
-        const uint32_t next64 = cur + 64 < n ? a.rv_io[cur + 64] : T;  // start of the item after the window
-        const uint32_t t = base + lane;
-        const bool act = t < end;
-        const uint32_t tc = act ? t : base;
-        const uint32_t u = a.rv_src[tc];
-        const uint32_t w = a.rv_w[tc];
-        const uint32_t x = a.R[u];
-        const int o = owner_lane(off, t);
-        const uint32_t v = __shfl(vl, o, 64);
-        const uint32_t voff = __shfl(off, o, 64);  // v's first in-edge
-        uint32_t vend = __shfl(off, (o + 1) & 63, 64);  // v's end: the next item's start
-        if (o == 63 || vend == kNone) vend = o == 63 ? next64 : T;
-        uint32_t c = act ? Alg<A>::extend(x, w) : worst;
-        if (lane == 0 && v == carry_v && Alg<A>::better(carry_c, c)) c = carry_c;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t oc = __shfl_up(c, d, 64);
-            const int oo = __shfl_up(o, d, 64);
-            if (lane >= (uint32_t)d && oo == o && Alg<A>::better(oc, c)) c = oc;
+    // Two-deep pipeline: a step's in-edges are loaded two steps ahead and their
+    // sources' values one step ahead, so the step's own chain (scan, destination
+    // value, store) runs while the next steps' loads are in flight.
+    auto edge_at = [&](uint32_t b0, uint32_t& u, uint32_t& w, uint32_t& v) {
+        if (b0 < end) {
+            const uint32_t t = b0 + lane < end ? b0 + lane : b0;
+            u = a.rv_src[t];
+            w = a.rv_w[t];
+            v = a.rv_dst[t];
+        } else {
+            u = 0;
+            w = 0;
+            v = kNone;
         }
+    };
+    uint32_t u, w, v, un, wn, vn;
+    edge_at(beg, u, w, v);
+    edge_at(beg + 64, un, wn, vn);
+    uint32_t x = a.R[u];
+    for (uint32_t base = beg; base < end; base += 64) {
+        const bool act = base + lane < end;
+        const uint32_t key = act ? v : kNone;  // idle lanes form a segment of their own
         const uint32_t nb = base + 64;
-        const int onext = __shfl_down(o, 1, 64);
-        const bool seg_end = lane == 63 || onext != o;
-        // the segment of lane 63 goes on into the next step of this slice
-        const bool carry = lane == 63 && vend > nb && nb < end;
-        const uint64_t cm = __ballot(carry);
-        if (seg_end && !carry) {
-            if (Alg<A>::better(c, a.R[v])) {
-                if (voff >= beg && vend <= end) a.R[v] = c;
-                else Alg<A>::improve_nr(&a.R[v], c);
-                mark(a.flags, v);
-                ++nup;
-            }
+        const uint32_t xn = nb < end ? a.R[un] : 0u;
+        uint32_t unn, wnn, vnn;
+        edge_at(nb + 64, unn, wnn, vnn);
+        const uint32_t rv = a.R[v];  // read before the scan, used at the segment's end
+        uint32_t c = act ? Alg<A>::extend(x, w) : worst;
+        if (lane == 0 && key == carry_v && Alg<A>::better(carry_c, c)) c = carry_c;
+        c = seg_scan<A>(key, c);
+        const uint32_t knext = dpp_mov<0x130, 0xF>(kNone, key);  // wave_shl:1: the next lane's key
+        const bool seg_end = knext != key;                       // lane 63 keeps kNone: always an end
+        // the last segment of this step goes on into the next step of this slice
+        const uint32_t first_next = uniform(vn);
+        const bool carry = lane == 63 && act && nb < end && key == first_next;
+        if (seg_end && act && !carry && Alg<A>::better(c, rv)) {
+            const bool shared = (cut_lo && key == v_lo) || (cut_hi && key == v_hi);
+            if (!shared) a.R[key] = c;
+            else Alg<A>::improve_nr(&a.R[key], c);
+            mark(a.flags, key);
+            ++nup;
         }
-        carry_v = cm ? __shfl(v, 63, 64) : kNone;
-        carry_c = cm ? __shfl(c, 63, 64) : worst;
-        // advance: the next step starts at the owner of base + 64
-        const uint32_t have = (uint32_t)__popcll(__ballot(off <= nb));
-        uint32_t adv = have - 1;
-        if (have == 64 && cur + 64 < n && next64 <= nb) adv = 64;
-        cur += adv;
-        base = nb;
+        const uint64_t cm = __ballot(carry);
+        carry_v = cm ? uniform((uint32_t)__shfl((int)key, 63, 64)) : kNone;
+        carry_c = cm ? (uint32_t)__shfl((int)c, 63, 64) : worst;
+        u = un;
+        w = wn;
+        v = vn;
+        x = xn;
+        un = unn;
+        wn = wnn;
+        vn = vnn;
     }
     if (ST) {
         const uint32_t su = wave_sum(nup);
@@ -254,19 +290,65 @@ __device__ __forceinline__ void pull_walk(const SolveArgs& a, uint32_t n, uint32
     }
 }
 
+// An appending expansion's improved vertices: the first lane to improve a
+// vertex in this iteration (it moves the vertex's stamp to this iteration's
+// epoch) lists it for the next iteration, if it has edges in this solve's
+// graph.  The wave reserves its items and their edges with one packed atomic
+// on the next parity's counter, so the list's running edge offsets ascend
+// with the item index as a compaction's do.  Every lane of the wave calls it.
+template <int MODE>
+__device__ __forceinline__ void append_next(const SolveArgs& a, int p, bool improved, uint32_t v, uint32_t epoch) {
+    bool app = false;
+    uint32_t rb = 0, deg = 0, sp = 0;
+    if (improved && atomicMax(&a.stamp[v], epoch) != epoch) {
+        rb = a.row_ptr[v];
+        deg = row_end<MODE>(a, v) - rb;
+        if (MODE != 0) sp = a.row_split[v];
+        app = deg != 0;
+    }
+    const uint64_t bal = __ballot(app);
+    if (!bal) return;
+    if (!app) deg = 0;
+    const uint32_t incl = wave_incl_scan(deg);
+    const uint32_t tot = __shfl(incl, 63, 64);
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(&a.cnt->packed[p ^ 1], ((unsigned long long)__popcll(bal) << 32) | tot);
+    const uint32_t bi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), 0, 64);
+    const uint32_t be = (uint32_t)__shfl((int)(uint32_t)base, 0, 64);
+    if (app) {
+        const uint32_t item = bi + (uint32_t)__popcll(bal & lanemask_lt());
+        const uint32_t edge = be + incl - deg;
+        a.fo[p ^ 1][item] = edge;
+        a.fd[p ^ 1][item] = rb - edge;
+        if (MODE != 0) a.fs[p ^ 1][item] = sp;
+        a.fv[p ^ 1][item] = v;
+    }
+}
+
 template <int A, int MODE, int MW, bool ST>
-__global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int p, uint32_t* slot) {
+__global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int p, uint32_t epoch, uint32_t* slot) {
     constexpr int NW = kWalkers;
-    const unsigned long long cx = expand_prologue(a.cnt, p, slot);
-    const uint32_t n = items_of(cx), T = edges_of(cx);
-    if (T == 0) return;
+    const unsigned long long c0 = a.cnt->packed[p];
+    bool pull = false;
     if (MODE == 0 && a.pull_frac != kNone) {
         const uint32_t n_in = a.rv_cnt[1];
-        if (n_in && (uint64_t)T * 1024u >= (uint64_t)n_in * a.pull_frac) {
-            pull_walk<A, ST>(a, a.rv_cnt[0], n_in);
-            return;
-        }
+        pull = n_in && (uint64_t)edges_of(c0) * 1024u >= (uint64_t)n_in * a.pull_frac;
     }
+    // a sparse iteration (and no near/far schedule) lists the next frontier itself
+    const bool small = (a.append_edges && edges_of(c0) <= a.append_edges) ||
+                       (a.append_items && items_of(c0) <= a.append_items);
+    const bool appends = !pull && small && a.cnt->delta == 0;
+    const unsigned long long cx = expand_prologue(a.cnt, p, slot, appends);
+    const uint32_t n = items_of(cx), T = edges_of(cx);
+    if (T == 0) return;
+    if (pull) {
+        pull_walk<A, ST>(a, a.rv_cnt[1]);
+        return;
+    }
+    const uint32_t* __restrict__ fo = a.fo[p];
+    const uint32_t* __restrict__ fd = a.fd[p];
+    const uint32_t* __restrict__ fs = a.fs[p];
+    const uint32_t* __restrict__ fv = a.fv[p];
     const uint32_t lane = lane_id();
     const uint64_t gw = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) >> 6;
     const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
@@ -283,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int 
     if (base[0] >= end[0]) return;
     count_visits<ST>(a, lane == 0 ? end[NW - 1] - base[0] : 0u);
 #pragma unroll
-    for (int j = 0; j < NW; ++j) cur[j] = base[j] < end[j] ? wave_search(a.fo, n, base[j]) : 0u;
+    for (int j = 0; j < NW; ++j) cur[j] = base[j] < end[j] ? wave_search(fo, n, base[j]) : 0u;
     while (base[0] < end[0]) {
         Step st[NW];
         uint32_t off[NW];
@@ -295,12 +377,12 @@ __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int 
             off[j] = 0xFFFFFFFFu;
             if (base[j] >= end[j]) continue;
             const uint32_t idx = cur[j] + lane;
-            off[j] = idx < n ? stream_load(a.fo + idx) : 0xFFFFFFFFu;
+            off[j] = idx < n ? stream_load(fo + idx) : 0xFFFFFFFFu;
             uint32_t dl = 0, sp = 0, xv = 0;
             if (off[j] <= base[j] + 63) {
-                dl = stream_load(a.fd + idx);
-                if (MODE != 0) sp = stream_load(a.fs + idx);
-                xv = a.R[stream_load(a.fv + idx)];
+                dl = stream_load(fd + idx);
+                if (MODE != 0) sp = stream_load(fs + idx);
+                xv = a.R[stream_load(fv + idx)];
             }
             const uint32_t t = base[j] + lane;
             int o = 0;
@@ -329,10 +411,12 @@ __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int 
         uint32_t nup = 0;
 #pragma unroll
         for (int j = 0; j < NW; ++j) {
-            if (!st[j].want) continue;
-            Alg<A>::improve_nr(&a.R[st[j].v], st[j].cand);
-            mark(a.flags, st[j].v);
-            ++nup;
+            if (st[j].want) {
+                Alg<A>::improve_nr(&a.R[st[j].v], st[j].cand);
+                if (!appends) mark(a.flags, st[j].v);
+                ++nup;
+            }
+            if (appends) append_next<MODE>(a, p, st[j].want, st[j].v, epoch);
         }
         if (ST) {
             const uint32_t su = wave_sum(nup);
@@ -345,7 +429,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int 
             const uint32_t nb = base[j] + 64;
             const uint32_t have = (uint32_t)__popcll(__ballot(off[j] <= nb));
             uint32_t adv = have - 1;
-            if (have == 64 && cur[j] + 64 < n && a.fo[cur[j] + 64] <= nb) adv = 64;
+            if (have == 64 && cur[j] + 64 < n && fo[cur[j] + 64] <= nb) adv = 64;
             cur[j] += adv;
             base[j] = nb;
         }
@@ -409,8 +493,9 @@ uint64_t frontier_loop(SolveArgs a, const Mask<MW>& W, Frontier& f, hipStream_t 
     const uint32_t cblocks = grid_for(a.V, kCompactIds, 4096);
     static const char* names[3] = {"solve_expand_cap_all", "solve_expand_cap", "solve_expand_cup"};
     auto issue = [&](uint64_t, int p, bool first, uint32_t* slot) {
+        const uint32_t epoch = ++*f.epoch;
         EVQ_LAUNCH("solve_compact", (k_compact_frontier<A, MODE>), cblocks, kCompactBlock, s, a, p, first ? 1 : 0);
-        EVQ_LAUNCH(names[MODE], (k_expand<A, MODE, MW, ST>), kExpandBlocks, kBlock, s, a, W, p, slot);
+        EVQ_LAUNCH(names[MODE], (k_expand<A, MODE, MW, ST>), kExpandBlocks, kBlock, s, a, W, p, epoch, slot);
     };
     return drive_loop(issue, f.p, s, max_iters, "bound solve", &f.items);
 }
@@ -431,14 +516,21 @@ SolveArgs make_args(const Graph& g, const Frontier& f, uint32_t* R) {
     a.mask = g.mask;
     a.R = R;
     a.flags = f.flags;
-    a.fo = f.fo;
-    a.fd = f.fd;
-    a.fs = f.fs;
-    a.fv = f.fv;
+    a.fo[0] = f.fo;
+    a.fd[0] = f.fd;
+    a.fs[0] = f.fs;
+    a.fv[0] = f.fv;
+    a.fo[1] = f.fo1;
+    a.fd[1] = f.fd1;
+    a.fs[1] = f.fs1;
+    a.fv[1] = f.fv1;
+    a.stamp = f.stamp;
+    a.append_edges = f.append_edges;
+    a.append_items = f.append_items;
     a.cnt = f.cnt;
     a.stats = f.stats;
     a.V = g.V;
-    a.rv_src = a.rv_w = a.rv_io = a.rv_iv = a.rv_cnt = nullptr;
+    a.rv_src = a.rv_w = a.rv_dst = a.rv_cnt = nullptr;
     a.pull_frac = kNone;
     return a;
 }
@@ -454,8 +546,7 @@ uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t*
         if (pf != kNone && reverse_ready(g, s)) {
             a.rv_src = g.rv_src;
             a.rv_w = g.rv_w;
-            a.rv_io = g.rv_io;
-            a.rv_iv = g.rv_iv;
+            a.rv_dst = g.rv_dst;
             a.rv_cnt = g.rv_cnt;
             a.pull_frac = pf;
         }
@@ -501,6 +592,7 @@ uint64_t dispatch_cup(uint32_t algo, const Graph& g, const Window& W, uint32_t* 
 __global__ void k_init_frontier(FrontierCounters* c, unsigned long long* st, int n) {
     if (threadIdx.x == 0) {
         c->packed[0] = c->packed[1] = 0ull;
+        c->status[0] = c->status[1] = 0u;
         c->far[0] = c->far[1] = 0u;
         c->fmin[0] = c->fmin[1] = 0xFFFFFFFFu;
         c->thr = 0xFFFFFFFFu;
@@ -521,6 +613,24 @@ Frontier make_frontier(const Graph& g, Workspace& ws, hipStream_t s) {
     f.fd = ws.buf<uint32_t>(Workspace::kFd, g.V);
     f.fs = ws.buf<uint32_t>(Workspace::kFs, g.V);
     f.fv = ws.buf<uint32_t>(Workspace::kFv, g.V);
+    f.fo1 = ws.buf<uint32_t>(Workspace::kFo1, g.V);
+    f.fd1 = ws.buf<uint32_t>(Workspace::kFd1, g.V);
+    f.fs1 = ws.buf<uint32_t>(Workspace::kFs1, g.V);
+    f.fv1 = ws.buf<uint32_t>(Workspace::kFv1, g.V);
+    f.stamp = ws.buf<uint32_t>(Workspace::kStamp, g.V);
+    // stamps below every epoch to come: cleared when the buffer is new (or after a no-allocation
+    // call, whose scratch another call may have used) and before the epoch counter wraps
+    if (f.stamp != ws.stamp_seen || ws.epoch > 0xFFFF0000u) {
+        fill_u32(f.stamp, g.V, 0u, s);
+        ws.stamp_seen = f.stamp;
+        ws.epoch = 0;
+    }
+    f.epoch = &ws.epoch;
+    {
+        const evq_tuning tn = tuning();
+        f.append_edges = tn.append_edges;
+        f.append_items = tn.append_items;
+    }
     char* ctl = ws.buf<char>(Workspace::kControl, 512);
     f.cnt = reinterpret_cast<FrontierCounters*>(ctl);
     f.stats = reinterpret_cast<unsigned long long*>(ctl + 128);

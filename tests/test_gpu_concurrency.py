@@ -161,6 +161,6 @@ def test_threads_share_the_reverse_build(evq, tuned):
             t.join()
         grown = g.info["device_bytes"]
     assert not bad, f"wrong results on (thread, round, algo, source): {bad[:5]}"
-    # built exactly once: the handle grew by one reverse CSR (8 bytes per edge, two arrays of V + 1
-    # entries, two counters)
-    assert grown - held == 8 * max(E, 1) + 2 * (4 * V + 4) + 8, (held, grown)
+    # built exactly once: the handle grew by one reverse CSR (source, weight and destination per
+    # edge, two counters)
+    assert grown - held == 12 * max(E, 1) + 8, (held, grown)

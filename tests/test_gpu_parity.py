@@ -319,6 +319,48 @@ def test_pull_step(evq, algo, frac, tuned):
         assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
 
 
+@pytest.mark.parametrize("staged", [0, 2, 4])
+@pytest.mark.parametrize("algo", ALGOS)
+def test_relax_staged_tasks(evq, algo, staged, tuned):
+    # the relaxation with the block's tasks staged in LDS (2 or 4 per lane group) or each
+    # lane group loading its own (0), for every lane layout (8 to 128 lanes per group);
+    # heavy churn so that the reduced subgraph spans many blocks, two-word masks at K = 100
+    tuned(relax_staged=staged)
+    inst = synth.rmat_instance(14, 120000, 100, 400, 400, wmin=1, wmax=100, seed=53)
+    src = synth.pick_sources(inst, 2, seed=8)
+    trip, bits = oracle.replay(inst)
+    with _graph(evq, inst) as g:
+        for s_ in src:
+            for (b, L) in [(0, 100), (3, 64), (30, 70), (50, 7), (5, 9), (10, 16), (20, 32), (40, 40)]:
+                want = oracle.window_values(inst, algo, s_, b, L, replayed=(trip, bits))
+                got, st = gpu_values(g, algo, s_, b, L, stats=True)
+                assert_equal_values(got, want, f"staged {staged} algo {algo} [{b},{b + L})")
+                assert st["n_unstable"] > 0
+
+
+@pytest.mark.parametrize("append_edges", [0, 64, 1 << 30])
+@pytest.mark.parametrize("algo", ALGOS)
+def test_appending_expansions(evq, algo, append_edges, tuned):
+    # the bound solves' sparse iterations list the next frontier themselves (every
+    # iteration, those of at most 64 frontier edges, or none): same values and bounds,
+    # for the full window (with and without the pull step) and a sub-window
+    tuned(append_edges=append_edges)
+    big = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=47)
+    cases = [(synth.config_instance("small", seed=4), 0), (big, synth.pick_sources(big, 1, seed=6)[0])]
+    for ci, (inst, src) in enumerate(cases):
+        trip, bits = oracle.replay(inst)
+        rc_o, ru_o = oracle.bounds(inst.num_vertices, trip, bits, algo, src, 0, inst.K)
+        want = oracle.window_values(inst, algo, src, 0, inst.K, replayed=(trip, bits))
+        with _graph(evq, inst) as g:
+            for rep in range(3):  # the second full-window query builds the reverse CSR of the pull step
+                got = gpu_values(g, algo, src, 0, inst.K)
+                assert_equal_values(got, want, f"append {append_edges} case {ci} query {rep}")
+            rc, ru = gpu_bounds(g, algo, src, 0, inst.K)
+            sub = gpu_values(g, algo, src, 1, inst.K - 3)
+        assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
+        assert_equal_values(sub, want[:, 1:inst.K - 2], f"append {append_edges} case {ci} sub-window")
+
+
 @pytest.mark.parametrize("direct", [0, 1000000000])
 @pytest.mark.parametrize("algo", ALGOS)
 def test_relax_task_paths(evq, algo, direct, tuned):
