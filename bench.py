@@ -133,7 +133,8 @@ def bench_served(args):
         lev = {"qps": qps, "queries": len(qs)}
         for mode in ("batch", "plain"):
             g = evq.Graph(V, inst.base, inst.dels[:K], inst.adds[:K])
-            with evq.Server(g, mode=mode, max_groups=args.max_groups, max_batch=args.max_batch) as srv:
+            with evq.Server(g, mode=mode, max_groups=args.max_groups, max_batch=args.max_batch,
+                            queue_hi=args.queue_hi) as srv:
                 # warm-up: the worker pool's buffers and the kernels' first launches
                 for i in range(16):
                     srv.submit(i % 4, int(src_pool[i]), 128)
@@ -400,6 +401,8 @@ def main():
     ap.add_argument("--qps", default="4,16,64", help="served: arrival rates")
     ap.add_argument("--duration", type=float, default=6.0, help="served: seconds of arrivals per rate")
     ap.add_argument("--max-groups", type=int, default=0, help="served: group solves at once (0: server default)")
+    ap.add_argument("--queue-hi", type=int, default=0,
+                    help="served: waiting queries from which groups start beside running ones (0: server default)")
     ap.add_argument("--max-batch", type=int, default=0, help="served: queries per group (0: server default)")
     ap.add_argument("--no-appends", action="store_true", help="served: no appends during the run")
     args = ap.parse_args()

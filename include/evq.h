@@ -438,7 +438,10 @@ evq_status evq_append(evq_graph* g, const evq_batch* b, void* stream);
  * (len clamped to K), recorded in the result's win_begin / win_len.
  *   mode 0, continuous batching: a dispatcher admits queued queries while
  *     the estimated device footprint of all queries in flight stays within
- *     mem_budget (one query is always admitted when nothing is in flight),
+ *     mem_budget (one query is always admitted when nothing is in flight);
+ *     at light load (fewer than queue_hi waiting) it starts a query only when
+ *     nothing is in flight, as the plain server does, so that queries do not
+ *     share the device when no queue has formed,
  *     and forms groups of up to max_batch queued queries of the algorithm of
  *     the oldest waiting query; a group's bound solves run together (one
  *     query per lane), then each query's reduction and relaxation complete
@@ -458,7 +461,8 @@ typedef struct {
     uint32_t max_groups;     /* group bound solves running at once (0: 2) */
     uint64_t mem_budget;     /* device bytes, by estimate (0: a quarter of the free memory at creation) */
     uint32_t max_queued;     /* queries waiting for admission; submit returns EVQ_EBUSY beyond (0: 65536) */
-    uint32_t reserved;
+    uint32_t queue_hi;       /* mode 0: while queries are in flight, a new group starts only once this many
+                                wait (0: 4); with nothing in flight the oldest query starts at once */
 } evq_server_config;
 
 typedef struct {

@@ -85,7 +85,7 @@ class BatchConfig(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
                 ("max_groups", ctypes.c_uint32), ("mem_budget", ctypes.c_uint64), ("max_queued", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("queue_hi", ctypes.c_uint32)]
 
 
 class Completion(ctypes.Structure):
@@ -423,9 +423,10 @@ class Result:
 class Server:
     """Query server over a graph (evq_server_*): mode "batch" (continuous batching) or "plain" (one at a time)."""
 
-    def __init__(self, graph, mode="batch", max_batch=0, max_inflight=0, max_groups=0, mem_budget=0, max_queued=0):
+    def __init__(self, graph, mode="batch", max_batch=0, max_inflight=0, max_groups=0, mem_budget=0, max_queued=0,
+                 queue_hi=0):
         cfg = ServerConfig({"batch": 0, "plain": 1}[mode], max_batch, max_inflight, max_groups, mem_budget,
-                           max_queued, 0)
+                           max_queued, queue_hi)
         h = ctypes.c_void_p()
         _check(_lib.evq_server_create(graph._h, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -370,8 +370,12 @@ __global__ void __launch_bounds__(kBlock) k_relax_tasks(RelaxArgs r, int p) {
 
 // Seeding pass (the parfor over the reduced addition batches in Algorithm 2):
 // each window-partial edge u -> v with v in U improves v's lanes from R_cap[u].
-// Lanes first test one partial edge each; the survivors are then applied with
-// one LG-lane group per edge.
+// Lanes first test one partial edge each; the wave lists its survivors in LDS
+// (compact id, candidate, lane bits), and each lane group then applies them
+// eight at a time, issuing the eight destination rows before any update, so
+// a survivor costs no chain of dependent loads of its own.
+constexpr int kSeedChunk = 8;
+
 template <int A, int MW, int LG, bool ST>
 __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32_t* __restrict__ p_src,
                                                        const uint32_t* __restrict__ p_dst,
@@ -381,7 +385,9 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
                                                        const uint32_t* __restrict__ rcap, uint32_t b, uint32_t L,
                                                        uint32_t K, uint32_t pb, uint32_t pL) {
     using T = Lanes<LG>;
-    const uint32_t lane = lane_id();
+    __shared__ uint32_t s_cv[kBlock / 64][64], s_cand[kBlock / 64][64];
+    __shared__ uint64_t s_lanes[kBlock / 64][64][T::NLW];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const int g = LG >= 64 ? 0 : (int)lane / LG;
     const int i0 = LG >= 64 ? (int)lane : (int)lane % LG;
     const uint32_t gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
@@ -409,33 +415,49 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
                 if (act) cand = Alg<A>::extend(rcap[p_src[q]], p_w[q]);
             }
         }
-        uint64_t bal = __ballot(act);
+        const uint64_t bal = __ballot(act);
         add_stat<ST>(&r.stats[3], lane == 0 ? (uint32_t)__popcll(bal) : 0u);
-        while (bal) {
-            // group g takes the g-th remaining survivor
-            uint64_t rest = bal;
-            for (int k = 0; k < g && rest; ++k) rest &= rest - 1;
-            const bool has = rest != 0;
-            const int src = has ? __ffsll((unsigned long long)rest) - 1 : 0;
-            const uint32_t gcv = (uint32_t)__shfl((int)cv, src, 64);
-            const uint32_t gcand = (uint32_t)__shfl((int)cand, src, 64);
-            bool imp = false;
+        if (!bal) continue;
+        if (act) {
+            const uint32_t k = (uint32_t)__popcll(bal & lanemask_lt());
+            s_cv[wave][k] = cv;
+            s_cand[wave][k] = cand;
 #pragma unroll
-            for (int s = 0; s < T::SPL; ++s) {
-                const uint64_t lw = ((uint64_t)(uint32_t)__shfl((int)(lanes[s] >> 32), src, 64) << 32) |
-                                    (uint32_t)__shfl((int)(uint32_t)lanes[s], src, 64);
-                const int i = i0 + 64 * s;
-                if (has && ((lw >> (i & 63)) & 1ull)) {
-                    uint32_t* px = &r.X[(uint64_t)gcv * T::S + i];
-                    if (Alg<A>::better(gcand, *px)) {
-                        Alg<A>::improve_nr(px, gcand);
+            for (int j = 0; j < T::NLW; ++j) s_lanes[wave][k][j] = lanes[j];
+        }
+        wave_lds_sync();
+        const uint32_t ns = (uint32_t)__popcll(bal);
+        for (uint32_t j0 = 0; j0 < ns; j0 += T::G * kSeedChunk) {
+            uint32_t cur[kSeedChunk][T::SPL];
+#pragma unroll
+            for (int k = 0; k < kSeedChunk; ++k) {
+                const uint32_t j = j0 + (uint32_t)g + (uint32_t)(T::G * k);
+#pragma unroll
+                for (int s = 0; s < T::SPL; ++s) {
+                    const int i = i0 + 64 * s;
+                    const bool bit = j < ns && ((s_lanes[wave][j < ns ? j : 0][s] >> (i & 63)) & 1ull);
+                    cur[k][s] = bit ? r.X[(uint64_t)s_cv[wave][j] * T::S + i] : Alg<A>::unreached;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kSeedChunk; ++k) {
+                const uint32_t j = j0 + (uint32_t)g + (uint32_t)(T::G * k);
+                const bool has = j < ns;
+                const uint32_t jj = has ? j : 0;
+                const uint32_t gcv = s_cv[wave][jj], gcand = s_cand[wave][jj];
+                bool imp = false;
+#pragma unroll
+                for (int s = 0; s < T::SPL; ++s) {
+                    const int i = i0 + 64 * s;
+                    if (has && ((s_lanes[wave][jj][s] >> (i & 63)) & 1ull) && Alg<A>::better(gcand, cur[k][s])) {
+                        Alg<A>::improve_nr(&r.X[(uint64_t)gcv * T::S + i], gcand);
                         imp = true;
                     }
                 }
+                if (group_any<LG>(imp) && i0 == 0) mark(r.flags, gcv);
             }
-            if (group_any<LG>(imp) && i0 == 0) mark(r.flags, gcv);
-            for (int k = 0; k < T::G && bal; ++k) bal &= bal - 1;
         }
+        wave_lds_sync();  // the list is read until here
     }
 }
 

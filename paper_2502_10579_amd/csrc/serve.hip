@@ -249,9 +249,11 @@ void dispatch_loop(evq_server* sv) {
     (void)hipSetDevice(sv->device);
     std::unique_lock<std::mutex> lk(sv->mu);
     for (;;) {
+        // continuous batching starts a group beside running queries only once a queue has formed
         sv->cv.wait(lk, [sv] {
             return sv->stop || (!sv->queue.empty() && sv->groups < sv->cfg.max_groups &&
-                                sv->inflight < sv->cfg.max_inflight);
+                                sv->inflight < sv->cfg.max_inflight &&
+                                (sv->cfg.mode == 1 || sv->inflight == 0 || sv->queue.size() >= sv->cfg.queue_hi));
         });
         if (sv->stop) return;
         std::shared_ptr<const Graph> gp = sv->h->get();
@@ -335,6 +337,7 @@ evq_status evq_server_create(evq_graph* h, const evq_server_config* c, evq_serve
         if (cfg.max_inflight == 0) cfg.max_inflight = 256;
         if (cfg.max_groups == 0) cfg.max_groups = 2;
         if (cfg.max_queued == 0) cfg.max_queued = 65536;
+        if (cfg.queue_hi == 0) cfg.queue_hi = 4;
         if (cfg.mem_budget == 0) {
             size_t fr = 0, tot = 0;
             EVQ_HIP(hipMemGetInfo(&fr, &tot));

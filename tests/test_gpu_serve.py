@@ -137,3 +137,51 @@ def test_serve_destroy_with_queued_queries(evq):
         srv.close()  # queued ones are dropped, running ones finish, uncollected results released
         with pytest.raises(evq.EvqError):
             evq.Server(g, mode="batch", max_batch=65)
+
+
+def test_serve_light_load_runs_one_at_a_time(evq):
+    # continuous batching at light load: below queue_hi waiting queries, a query starts only when
+    # nothing is in flight (as the plain server does); results stay exact
+    K = 8
+    inst = synth.random_instance(60, 500, K, 4, 4, 9, 59)
+    rep = oracle.replay(inst)
+    src = synth.pick_sources(inst, 10, seed=6)
+    with evq.Graph.from_instance(inst) as g:
+        with evq.Server(g, mode="batch", queue_hi=1000) as srv:
+            for i in range(10):
+                srv.submit(ALGOS[i % 5], src[i], 1 + i % K)
+            comps = sorted(collect(srv, 10), key=lambda c: c["t_admit_ms"])
+            # a group's queries are admitted together (one dispatch, contiguous in admission order);
+            # the next group starts only after everything admitted before it has completed
+            i = 0
+            while i < len(comps):
+                grp = comps[i:i + comps[i]["group_size"]]
+                assert len({c["algo"] for c in grp}) == 1
+                done_before = max((c["t_done_ms"] for c in comps[:i]), default=0.0)
+                assert grp[0]["t_admit_ms"] >= done_before - 1e-3, "a group started beside running queries"
+                i += len(grp)
+            check(evq, g, inst, rep, comps)
+
+
+def test_serve_full_queue_is_busy(evq):
+    # admission back-off: beyond max_queued waiting queries, submit answers EVQ_EBUSY and queues
+    # nothing; the accepted queries complete exactly, and submitting works again after polling
+    K = 8
+    inst = synth.random_instance(60, 500, K, 4, 4, 9, 61)
+    rep = oracle.replay(inst)
+    src = synth.pick_sources(inst, 64, seed=8)
+    with evq.Graph.from_instance(inst) as g:
+        with evq.Server(g, mode="plain", max_queued=2) as srv:
+            accepted, busy = 0, 0
+            for i in range(64):
+                try:
+                    srv.submit(ALGOS[i % 5], src[i], 1 + i % K)
+                    accepted += 1
+                except evq.EvqError as e:
+                    assert e.status == evq.EVQ_EBUSY
+                    busy += 1
+            assert busy > 0 and accepted >= 2
+            comps = collect(srv, accepted)
+            srv.submit(ALGOS[0], src[0], K)
+            comps += collect(srv, 1)
+            check(evq, g, inst, rep, comps)
