@@ -295,14 +295,22 @@ __device__ __forceinline__ T uniform(T x) {
     return (T)__builtin_amdgcn_readfirstlane((int)x);
 }
 
-// Wave-wide inclusive prefix sum (64 lanes).
+// Wave-wide inclusive prefix sum (64 lanes) with DPP moves, no LDS permutes:
+// row shifts by 1, 2, 4 and 8 sum within each row of 16 lanes (a lane whose
+// source is outside its row adds 0), then lane 15 of rows 0 and 2 is added
+// into rows 1 and 3, then lane 31 into rows 2 and 3.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_or_zero(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (l >= d) v += t;
-    }
+    v += dpp_or_zero<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_or_zero<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_or_zero<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_or_zero<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_or_zero<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+    v += dpp_or_zero<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
     return v;
 }
 
