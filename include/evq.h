@@ -383,6 +383,17 @@ evq_status evq_batch_config_set(const evq_batch_config* c);
  *                 block's tasks and their edge records in LDS, 2 or 4 tasks
  *                 per lane group (default 2; 0: each lane group loads its own
  *                 task's records).
+ *   bucket_width  EVQ_BUCKET_WIDTH: SSSP intersection solves run delta-
+ *                 stepping (buckets of this many distance units; the edges
+ *                 of a row heavier than the width are expanded once, when
+ *                 the row's bucket is done) instead of plain frontier
+ *                 iterations, and neither pull nor defer by delta[].  The
+ *                 graph keeps a weight-ordered copy of its rows per width in
+ *                 use (8 bytes per edge + 4 per vertex, at most 4 widths,
+ *                 built by the first query that asks for it).  0 (default):
+ *                 off, since on R-MAT graphs the extra iterations cost more
+ *                 than the edge visits saved; 0xFFFFFFFF: a width from the
+ *                 graph's largest weight and mean out-degree.
  * evq_tuning_set: EVQ_EINVAL on NULL, launch_depth outside 1..32,
  * split_min == 0 or relax_staged not 0, 2 or 4; calls already running keep
  * the values they started with.
@@ -400,6 +411,7 @@ typedef struct {
     uint32_t append_edges;
     uint32_t relax_staged;
     uint32_t append_items;
+    uint32_t bucket_width;
 } evq_tuning;
 
 evq_status evq_tuning_get(evq_tuning* t);

@@ -16,6 +16,7 @@ LIB_PATH = os.environ.get("EVQ_LIBRARY") or os.path.join(_HERE, "libevq.so")
 SSSP, BFS, SSWP, SSNP, VITERBI = 0, 1, 2, 3, 4
 ALGOS = {"sssp": SSSP, "bfs": BFS, "sswp": SSWP, "ssnp": SSNP, "viterbi": VITERBI}
 INF = 0xFFFFFFFF
+BUCKET_WIDTH_AUTO = 0xFFFFFFFF  # evq_tuning.bucket_width: derived from the graph
 
 EVQ_OK, EVQ_EINVAL, EVQ_ERANGE, EVQ_ENOMEM, EVQ_EDEVICE, EVQ_ENOCONV = 0, -1, -2, -3, -4, -5
 EVQ_ECANCELED, EVQ_EBUSY = -6, -7
@@ -100,7 +101,8 @@ class Tuning(ctypes.Structure):
                 ("launch_depth", ctypes.c_uint32), ("direct_tasks", ctypes.c_uint32),
                 ("append_rebuild", ctypes.c_uint32), ("trace_loops", ctypes.c_uint32),
                 ("delta", ctypes.c_uint32 * 5), ("heavy", ctypes.c_uint32 * 5), ("append_edges", ctypes.c_uint32),
-                ("relax_staged", ctypes.c_uint32), ("append_items", ctypes.c_uint32)]
+                ("relax_staged", ctypes.c_uint32), ("append_items", ctypes.c_uint32),
+                ("bucket_width", ctypes.c_uint32)]
 
 
 class KernelTime(ctypes.Structure):

@@ -107,6 +107,10 @@ evq_status evq_graph_info_get(const evq_graph* h, evq_graph_info* info) {
         std::lock_guard<std::mutex> lk(g.rv_mu);  // reverse CSR of the pull step, once built
         if (g.rv_built) info->device_bytes += (g.E ? g.E : 1) * 12 + 8;
     }
+    {
+        std::lock_guard<std::mutex> lk(g.wo_mu);  // weight-ordered rows of the bucketed solve
+        info->device_bytes += (uint64_t)g.n_wo * ((g.E ? g.E : 1) * 8 + (uint64_t)(g.V ? g.V : 1) * 4);
+    }
     info->build_ms = g.build_ms;
     info->first_snapshot = g.first;
     return EVQ_OK;

@@ -69,12 +69,12 @@ __global__ void __launch_bounds__(kCompactBlock) k_bcompact(BatchArgs a, int p, 
     if (compaction_skips(a.cnt, p, first)) return;
     compact_flags(
         a.flags, a.V, &a.cnt->packed[p], &a.cnt->far[p], &a.cnt->fmin[p],
-        [&](uint32_t v, uint32_t& items, uint32_t& tasks, uint32_t&) {
+        [&](uint32_t v, uint32_t, uint32_t& items, uint32_t& tasks, uint32_t&, uint2&) {
             tasks = (a.row_ptr[v + 1] - a.row_ptr[v] + a.chunk - 1) / a.chunk;
             items = tasks ? 1u : 0u;
-            return true;
+            return 0u;
         },
-        [&](uint32_t v, uint32_t item, uint32_t task, uint32_t, uint32_t) {
+        [&](uint32_t v, uint32_t item, uint32_t task, uint32_t, uint32_t, uint2) {
             a.fo[item] = task;
             a.fv[item] = v;
         });

@@ -29,6 +29,7 @@ struct Frontier {
     int p = 0;                            // parity of the next compaction (continues across phases)
     uint32_t delta = 0;                   // near/far step of the bound solves (0: off)
     uint32_t heavy = 0;                   // with delta: gate only vertices with this many edges (0: all)
+    uint32_t bdelta = 0;                  // bucket width of the SSSP intersection solve (0: off)
     uint64_t items = 0;                   // frontier items processed so far (published counts)
 };
 
@@ -38,6 +39,13 @@ uint32_t choose_delta(uint32_t algo);
 // per-algorithm default (0: every vertex is gated).
 uint32_t choose_heavy(uint32_t algo);
 
+
+// Bucket width of the intersection solve of a query of algo on g (0: off).
+uint32_t choose_bucket_width(uint32_t algo, const Graph& g);
+// g's rows ordered for the bucket width, built on s on first use (later users
+// on other streams wait for it); null when it cannot be had (a call that must
+// not allocate, or all kWeightOrders slots hold other widths).
+const WeightOrder* weight_order_ready(const Graph& g, uint32_t width, hipStream_t s);
 
 Frontier make_frontier(const Graph& g, Workspace& ws, hipStream_t s);
 

@@ -1009,8 +1009,13 @@ void reverse_sorted(const Graph& g, int vb, int wb, hipStream_t s, Arena& ar) {
 
 void free_graph(Graph* g, hipStream_t s) {
     if (!g) return;
-    void* arrays[13] = {g->row_ptr, g->row_split, g->col,  g->wgt,   g->mask,   g->p_src, g->p_dst,
-                        g->p_w,     g->p_mask,    g->rv_src, g->rv_w, g->rv_dst, g->rv_cnt};
+    std::vector<void*> arrays = {g->row_ptr, g->row_split, g->col,  g->wgt,   g->mask,   g->p_src, g->p_dst,
+                                 g->p_w,     g->p_mask,    g->rv_src, g->rv_w, g->rv_dst, g->rv_cnt};
+    for (uint32_t i = 0; i < g->n_wo; ++i) {
+        arrays.push_back(g->wo[i].col);
+        arrays.push_back(g->wo[i].w);
+        arrays.push_back(g->wo[i].nheavy);
+    }
     if (g->has_ua) {
         // the caller's allocator frees on the host: the work on s that uses the arrays completes first
         if (s) (void)hipStreamSynchronize(s);
@@ -1021,6 +1026,8 @@ void free_graph(Graph* g, hipStream_t s) {
             if (p) (void)hipFreeAsync(p, s);
     }
     if (g->rv_ready) (void)hipEventDestroy(g->rv_ready);
+    for (uint32_t i = 0; i < kWeightOrders; ++i)
+        if (g->wo[i].ready) (void)hipEventDestroy(g->wo[i].ready);
     for (hipEvent_t e : g->uses) (void)hipEventDestroy(e);
     delete g;
 }

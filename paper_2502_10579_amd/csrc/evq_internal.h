@@ -34,6 +34,18 @@ constexpr uint32_t kSat = 0xFFFFFFFEu;
 
 // ------------------------------------------------------------------ graph
 
+// A graph's rows with each all-present prefix reordered for a bucket width:
+// the edges heavier than the width first (nheavy of them), the lighter ones
+// after; the other edges keep their places (so masks still index them).
+struct WeightOrder {
+    uint32_t width = 0;
+    uint32_t* col = nullptr;     // E
+    uint32_t* w = nullptr;       // E
+    uint32_t* nheavy = nullptr;  // V
+    hipEvent_t ready = nullptr;  // recorded after the copy was written
+};
+constexpr uint32_t kWeightOrders = 4;  // widths kept per graph version
+
 // Snapshot t (a global id, counted from the first snapshot ever built) is
 // held in mask bit (t mod K); the graph holds snapshots first .. first+K-1.
 struct Graph {
@@ -76,6 +88,11 @@ struct Graph {
     mutable uint32_t* rv_w = nullptr;    // its weight (capacity E)
     mutable uint32_t* rv_dst = nullptr;  // its destination (capacity E), ascending
     mutable uint32_t* rv_cnt = nullptr;  // [1] in-edges (device)
+    // Weight-ordered copies of the rows for the bucketed SSSP intersection
+    // solve, one per width in use, built by the first query that asks.
+    mutable std::mutex wo_mu;
+    mutable WeightOrder wo[kWeightOrders];
+    mutable uint32_t n_wo = 0;
 };
 
 // Records that work reading g was queued on s (call after the last launch).
@@ -189,6 +206,7 @@ struct Mailbox {
 // evq_tuning_set; each call takes a copy.
 evq_tuning tuning();
 void set_tuning(const evq_tuning& t);
+constexpr uint32_t kAutoWidth = 0xFFFFFFFFu;  // evq_tuning::bucket_width: derived from the graph
 
 // ------------------------------------------------------------------ launches
 
@@ -314,10 +332,35 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+// Lane l's value of v (l a constant or wave-uniform), read into a scalar register.
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// Wave-wide sum and minimum, wave-uniform results: the row shifts leave each
+// row's total in its lane 15, and the four row totals are combined in scalar
+// registers.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+    v += dpp_or_zero<0x111, 0xF>(v);
+    v += dpp_or_zero<0x112, 0xF>(v);
+    v += dpp_or_zero<0x114, 0xF>(v);
+    v += dpp_or_zero<0x118, 0xF>(v);
+    return lane_value(v, 15) + lane_value(v, 31) + lane_value(v, 47) + lane_value(v, 63);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_or_max(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    v = umin32(v, dpp_or_max<0x111>(v));
+    v = umin32(v, dpp_or_max<0x112>(v));
+    v = umin32(v, dpp_or_max<0x114>(v));
+    v = umin32(v, dpp_or_max<0x118>(v));
+    return umin32(umin32(lane_value(v, 15), lane_value(v, 31)), umin32(lane_value(v, 47), lane_value(v, 63)));
 }
 
 // Query value algebra (Table 2).  `better(a, b)`: a strictly improves on b.

@@ -9,8 +9,10 @@
 // same order.
 //
 // Counters are double-buffered by iteration parity p: the compaction of
-// iteration i zeroes cnt[p ^ 1] (the previous iteration's, whose readers have
-// finished) and adds into cnt[p]; the expansion of iteration i reads cnt[p],
+// iteration i zeroes the item counter of parity p ^ 1 (the previous
+// iteration's, whose readers have finished) and adds into parity p, whose
+// deferral counters the expansion before it has reset; the expansion of
+// iteration i reads cnt[p],
 // tells the next compaction whether it produced work, and publishes its item
 // count to a host-mapped slot, so the host never has to synchronise the
 // stream to learn when a loop has drained.  A compaction that finds the
@@ -27,15 +29,21 @@ namespace evq {
 
 struct FrontierCounters {
     unsigned long long packed[2];  // (items << 32) | edges, by parity
-    uint32_t far[2];               // ids left for a later threshold, by parity
-    uint32_t fmin[2];              // smallest order key among those ids, by parity
+    uint32_t far[2];               // ids left flagged (for a later threshold or bucket), by parity
+    uint32_t fmin[2];              // smallest order key among the ids left for a later threshold, by parity
     uint32_t thr;                  // near/far threshold of the bound solves (order keys below it are near)
     uint32_t delta;                // threshold step (0: every id is near)
     uint32_t heavy;                // with delta > 0: only ids with at least this many edges are gated (0: all)
     uint32_t kall[2];              // smallest order key over the compacted ids with edges, by parity (heavy > 0)
     uint32_t status[2];            // for the compaction of parity q: bit 0 the expansion before it had work
                                    // or deferred ids, bit 1 it appended the next list itself
+    // Bucketed schedule with light and heavy edges (bound solves of SSSP):
+    uint32_t bdelta;               // bucket width (0: off)
+    uint32_t bthr[2];              // the bucket's upper key bound set by the compaction of parity q
+    uint32_t near[2];              // the expansion of parity q improved a vertex below bthr[q]
+    uint32_t nmin[2];              // smallest value it wrote at or above bthr[q]
 };
+static_assert(sizeof(FrontierCounters) <= 128, "frontier counters share a 128-byte control slot");
 
 __device__ __forceinline__ uint32_t items_of(unsigned long long x) { return (uint32_t)(x >> 32); }
 __device__ __forceinline__ uint32_t edges_of(unsigned long long x) { return (uint32_t)x; }
@@ -70,22 +78,27 @@ __device__ __forceinline__ unsigned long long expand_prologue(FrontierCounters* 
         }
         c->thr = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
         c->status[p ^ 1] = (x != 0ull || f ? 1u : 0u) | (appends ? 2u : 0u);
+        // the other parity's deferral counters, last read by the compaction
+        // before this expansion, start afresh for the next compaction
+        c->far[p ^ 1] = 0u;
+        c->fmin[p ^ 1] = 0xFFFFFFFFu;
+        c->kall[p ^ 1] = 0xFFFFFFFFu;
         __hip_atomic_store(slot, items_of(x) + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     return x;
 }
 
-// Compaction prologue: zero the other parity's counters (the previous
+// Compaction prologue: zero the other parity's item counters (the previous
 // iteration's, read only by kernels that have finished) for the next
-// iteration, and say whether the scan can be skipped: the previous expansion
+// iteration, clear this parity's bucket reports for the expansion that
+// follows, and say whether the scan can be skipped: the previous expansion
 // had no work and deferred nothing (no flag can be set), or it appended the
 // next list itself.  The first compaction of a loop always scans.
 __device__ __forceinline__ bool compaction_skips(FrontierCounters* c, int p, int first) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         c->packed[p ^ 1] = 0ull;
-        c->far[p ^ 1] = 0u;
-        c->fmin[p ^ 1] = 0xFFFFFFFFu;
-        c->kall[p ^ 1] = 0xFFFFFFFFu;
+        c->near[p] = 0u;
+        c->nmin[p] = 0xFFFFFFFFu;
     }
     return !first && c->status[p] != 1u;
 }
@@ -119,17 +132,20 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Flag compaction shared by the frontier loops.  A block of kCompactBlock
-// threads takes kCompactIds consecutive ids (8 flag bytes per lane), clears
-// their flags, stages the set ids in LDS, reads every id's work size with all
-// loads in flight at once, and reserves (items, edges) for the whole block
-// with one packed atomic.  size_of(id, items, edges, key) gives an id's work
-// and returns false to defer the id: its flag stays set, it is counted in
-// *far and its order key enters the minimum *fmin.  emit(id, item, edge,
-// items, edges) writes an id's work.  Ids appear in ascending order within a
-// block.  With kall non-null, size_of gives every id with edges its order key
-// and the smallest of them enters the minimum *kall.  post() runs on every
-// thread of the block after each group of ids has been emitted (and the block
-// synchronised), before the next group is compacted.
+// threads takes kCompactIds consecutive ids (8 flag bytes per lane), stages
+// the flagged ids and their flag bytes in LDS, reads every id's work size with
+// all loads in flight at once, rewrites the flag bytes, and reserves (items,
+// edges) for the whole block with one packed atomic.
+// size_of(id, flag, items, edges, key, aux) gives an id's work (items and
+// edges, zero for none), may keep two words of what it read in aux for emit,
+// and returns the flag byte the id keeps: 0 clears it; an id left flagged is
+// counted in *far and, unless size_of leaves key at 0xFFFFFFFF, its order key
+// enters the minimum *fmin.  emit(id, item, edge, items, edges, aux) writes an
+// id's work.  Ids appear in ascending order within a block.  With kall
+// non-null, size_of gives every id with edges its order key and the smallest
+// of them enters the minimum *kall.  post() runs on every thread of the block
+// after each group of ids has been emitted (and the block synchronised),
+// before the next group is compacted.
 struct NoPost {
     __device__ void operator()() const {}
 };
@@ -144,11 +160,13 @@ __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint3
                                               uint32_t* far, uint32_t* fmin, SizeFn size_of, EmitFn emit,
                                               uint32_t* kall = nullptr, PostFn post = PostFn()) {
     __shared__ uint32_t ids[kCompactWaves][kIdsPerWave];
-    __shared__ uint32_t keep[kCompactWaves][64];
+    __shared__ uint8_t fbyte[kCompactWaves][kIdsPerWave];  // flag byte of each listed id
+    __shared__ uint2 nflag[kCompactWaves][64];             // the wave's new flag bytes, in id order
     __shared__ uint32_t wtot[kCompactWaves][5];
     __shared__ unsigned long long bbase;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     uint2* __restrict__ f8 = reinterpret_cast<uint2*>(flags);
+    uint8_t* const nf8 = reinterpret_cast<uint8_t*>(nflag[wave]);
     for (uint64_t b0 = (uint64_t)blockIdx.x * kCompactIds; b0 < n; b0 += (uint64_t)gridDim.x * kCompactIds) {
         const uint32_t w0 = (uint32_t)b0 + wave * kIdsPerWave;  // first id of this wave
         const uint32_t g0 = w0 + lane * 8;                       // first id of this lane
@@ -162,69 +180,57 @@ __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint3
         }
         const uint32_t pc = (uint32_t)__popc(word);
         const uint32_t incl = wave_incl_scan(pc);
-        const uint32_t tot = __shfl(incl, 63, 64);
+        const uint32_t tot = lane_value(incl, 63);
         uint32_t id[kIdSteps], ni[kIdSteps], ne[kIdSteps], pi[kIdSteps], pe[kIdSteps];
+        uint2 aux[kIdSteps];
+#pragma unroll
+        for (int s = 0; s < kIdSteps; ++s) {
+            id[s] = ni[s] = ne[s] = pi[s] = pe[s] = 0;
+            aux[s] = make_uint2(0u, 0u);
+        }
         uint32_t ti = 0, te = 0, tf = 0, tk = 0xFFFFFFFFu, ta = 0xFFFFFFFFu;
         if (tot) {
-            keep[wave][lane] = 0;
+            nflag[wave][lane] = make_uint2(0u, 0u);
             uint32_t k = incl - pc;
-            for (uint32_t m = word; m; m &= m - 1) ids[wave][k++] = g0 + (uint32_t)__builtin_ctz(m);
+            for (uint32_t m = word; m; m &= m - 1) {
+                const uint32_t b = (uint32_t)__builtin_ctz(m);
+                ids[wave][k] = g0 + b;
+                fbyte[wave][k] = (uint8_t)(((b < 4 ? fl.x : fl.y) >> (8 * (b & 3))) & 0xFFu);
+                ++k;
+            }
             wave_lds_sync();
             uint32_t nf = 0, kmin = 0xFFFFFFFFu, amin = 0xFFFFFFFFu;
+            // the steps past the wave's count (tot, wave-uniform) are skipped
 #pragma unroll
             for (int s = 0; s < kIdSteps; ++s) {
+                if (s * 64u >= tot) break;
                 const uint32_t j = s * 64 + lane;
-                id[s] = 0;
-                ni[s] = 0;
-                ne[s] = 0;
                 if (j < tot) {
                     id[s] = ids[wave][j];
                     uint32_t key = 0xFFFFFFFFu;
-                    const bool near = size_of(id[s], ni[s], ne[s], key);
+                    const uint32_t kept = size_of(id[s], (uint32_t)fbyte[wave][j], ni[s], ne[s], key, aux[s]);
                     amin = key < amin ? key : amin;
-                    if (!near) {  // deferred: its flag stays set
-                        ni[s] = ne[s] = 0;
+                    if (kept) {  // its flag stays set
                         ++nf;
                         kmin = key < kmin ? key : kmin;
-                        const uint32_t r = id[s] - w0;
-                        atomicOr(&keep[wave][r >> 3], 1u << (r & 7));
+                        nf8[id[s] - w0] = (uint8_t)kept;
                     }
                 }
             }
 #pragma unroll
             for (int s = 0; s < kIdSteps; ++s) {
+                if (s * 64u >= tot) break;
                 const uint32_t a = wave_incl_scan(ni[s]), b = wave_incl_scan(ne[s]);
                 pi[s] = ti + a - ni[s];
                 pe[s] = te + b - ne[s];
-                ti += __shfl(a, 63, 64);
-                te += __shfl(b, 63, 64);
+                ti += lane_value(a, 63);
+                te += lane_value(b, 63);
             }
             tf = wave_sum(nf);
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                const uint32_t o = __shfl_xor(kmin, d, 64);
-                kmin = o < kmin ? o : kmin;
-            }
-            tk = kmin;
-            if (kall) {
-#pragma unroll
-                for (int d = 32; d >= 1; d >>= 1) {
-                    const uint32_t o = __shfl_xor(amin, d, 64);
-                    amin = o < amin ? o : amin;
-                }
-                ta = amin;
-            }
+            tk = wave_min(kmin);
+            if (kall) ta = wave_min(amin);
             wave_lds_sync();
-            if (word) {
-                const uint32_t kb = keep[wave][lane];
-                uint2 out = make_uint2(0u, 0u);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    out.x |= ((kb >> k) & 1u) << (8 * k);
-                    out.y |= ((kb >> (k + 4)) & 1u) << (8 * k);
-                }
-                f8[g0 >> 3] = out;
-            }
+            if (word) f8[g0 >> 3] = nflag[wave][lane];
         }
         if (lane == 0) {
             wtot[wave][0] = ti;
@@ -260,7 +266,7 @@ __device__ __forceinline__ void compact_flags(uint8_t* __restrict__ flags, uint3
             }
 #pragma unroll
             for (int s = 0; s < kIdSteps; ++s)
-                if (ni[s]) emit(id[s], bi + pi[s], be + pe[s], ni[s], ne[s]);
+                if (ni[s]) emit(id[s], bi + pi[s], be + pe[s], ni[s], ne[s], aux[s]);
         }
         __syncthreads();
         post();

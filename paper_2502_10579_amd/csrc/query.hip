@@ -342,12 +342,12 @@ __global__ void __launch_bounds__(kCompactBlock) k_relax_compact(RelaxArgs r, in
     if (DIRECT) task_list_init(tl);
     compact_flags(
         r.flags, r.nU, &r.cnt->packed[p], &r.cnt->far[p], &r.cnt->fmin[p],
-        [&](uint32_t c, uint32_t& items, uint32_t& tasks, uint32_t&) {
+        [&](uint32_t c, uint32_t, uint32_t& items, uint32_t& tasks, uint32_t&, uint2&) {
             tasks = (r.kc[c] + kRelaxChunk - 1) / kRelaxChunk;
             items = tasks ? 1u : 0u;
-            return true;
+            return 0u;
         },
-        [&](uint32_t c, uint32_t item, uint32_t task, uint32_t, uint32_t tasks) {
+        [&](uint32_t c, uint32_t item, uint32_t task, uint32_t, uint32_t tasks, uint2) {
             if (!DIRECT) {
                 r.fo[item] = task;
                 r.fv[item] = c;
@@ -1257,6 +1257,7 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     Frontier f = make_frontier(g, ws, s);
     f.delta = choose_delta(algo);
     f.heavy = choose_heavy(algo);
+    f.bdelta = choose_bucket_width(algo, g);
     uint32_t* rcap = d_rcap_out ? d_rcap_out : ws.buf<uint32_t>(Workspace::kRcap, g.V);
     uint32_t* rcup = d_rcup_out ? d_rcup_out : ws.buf<uint32_t>(Workspace::kRcup, g.V);
     bounds_impl(g, algo, source, W, rcap, rcup, f, qo, s, tm);
@@ -1290,6 +1291,7 @@ void run_query_compact(const Graph& g, uint32_t algo, uint32_t source, const Win
     Frontier f = make_frontier(g, ws, s);
     f.delta = choose_delta(algo);
     f.heavy = choose_heavy(algo);
+    f.bdelta = choose_bucket_width(algo, g);
     uint32_t* rcup = ws.buf<uint32_t>(Workspace::kRcup, g.V);
     bounds_impl(g, algo, source, W, c.rcap, rcup, f, qo, s, tm);
     qo.bounds_done = std::chrono::steady_clock::now();
@@ -1352,6 +1354,7 @@ void run_sequential(const Graph& g, uint32_t algo, uint32_t source, const Window
     Frontier f = make_frontier(g, ws, s);
     f.delta = choose_delta(algo);
     f.heavy = choose_heavy(algo);
+    f.bdelta = choose_bucket_width(algo, g);
     uint32_t* rcap = ws.buf<uint32_t>(Workspace::kRcap, g.V);
     uint32_t* rcup = ws.buf<uint32_t>(Workspace::kRcup, g.V);
     bounds_impl(g, algo, source, W, rcap, rcup, f, qo, s, tm);

@@ -332,6 +332,7 @@ evq_tuning tuning_from_env() {
     t.append_edges = env_u32("EVQ_APPEND_EDGES", 1u << 17);
     t.append_items = env_u32("EVQ_APPEND_ITEMS", 0u);
     t.relax_staged = env_u32("EVQ_RELAX_STAGED", 2u);
+    t.bucket_width = env_u32("EVQ_BUCKET_WIDTH", 0u);
     static const char* delta_names[5] = {"EVQ_DELTA_SSSP", "EVQ_DELTA_BFS", "EVQ_DELTA_SSWP", "EVQ_DELTA_SSNP",
                                          "EVQ_DELTA_VITERBI"};
     static const char* heavy_names[5] = {"EVQ_HEAVY_SSSP", "EVQ_HEAVY_BFS", "EVQ_HEAVY_SSWP", "EVQ_HEAVY_SSNP",

@@ -81,6 +81,9 @@ struct SolveArgs {
     const uint32_t* rv_dst;
     const uint32_t* rv_cnt;
     uint32_t pull_frac;
+    // bucketed schedule (null: off): heavy edges at the front of each row's
+    // all-present prefix in col/wgt (a weight-ordered copy of the rows)
+    const uint32_t* nheavy;
 };
 
 // MODE: 0 = intersection over all K snapshots (only the all-present prefix of
@@ -101,7 +104,7 @@ __device__ __forceinline__ bool partial_in(const uint64_t* __restrict__ mask, ui
 }
 
 template <int A>
-__device__ __forceinline__ uint32_t order_key(uint32_t x) {
+__host__ __device__ __forceinline__ uint32_t order_key(uint32_t x) {
     return (A == EVQ_SSWP || A == EVQ_VITERBI) ? ~x : x;
 }
 
@@ -132,32 +135,85 @@ __device__ __forceinline__ void count_visits(const SolveArgs& a, uint32_t n) {
 // With near/far scheduling on (delta > 0), a vertex whose order key (its
 // value, complemented where larger is better, so smaller is better) is not
 // below the threshold keeps its flag for a later iteration.  With a heavy
-// bound, only vertices with at least that many edges in this solve's graph
-// are gated: re-expanding a vertex costs its whole row, and the rows of the
-// few high-degree vertices carry most of the repeated edge visits, while light
-// vertices keep the iterations full.
+// bound, only vertices with at least that many edges are gated: re-expanding
+// a vertex costs its whole row, and the rows of the few high-degree vertices
+// carry most of the repeated edge visits, while light vertices keep the
+// iterations full.
+// Bucketed schedule (nheavy set; additive weights): the delta-stepping of
+// Meyer and Sanders with the buckets' iterations as frontier iterations.  The
+// rows are read from a copy whose all-present prefix holds the heavy edges
+// (weight above the bucket width) first and the light ones after.  Flag byte 1
+// marks a vertex improved since its last light expansion, 2 one whose light
+// edges are done and whose heavy edges wait for the end of its bucket.  A
+// bucket ends when the expansion before improved nothing below its bound:
+// every value below the bound is then final (a value comes from a flagged
+// vertex's edge, so it is at least the smallest flagged value, and a heavy
+// edge of the bucket lands above the bound), so the heavy edges of the waiting
+// vertices are expanded once, in the same iteration as the light edges of the
+// next bucket, which spans the width above the smallest value still flagged.
 template <int A, int MODE>
 __global__ void __launch_bounds__(kCompactBlock) k_compact_frontier(SolveArgs a, int p, int first) {
-    if (compaction_skips(a.cnt, p, first)) return;
-    const uint32_t thr = a.cnt->thr;
-    const bool nf = a.cnt->delta != 0;
-    const uint32_t heavy = nf ? a.cnt->heavy : 0u;
+    FrontierCounters* const c = a.cnt;
+    const bool lh = a.nheavy != nullptr;
+    uint32_t bt = 0xFFFFFFFFu;  // bucket bound: light edges of flagged vertices below it are expanded
+    bool ended = false;         // the previous bucket ended: its waiting heavy edges are expanded
+    if (lh) {
+        bt = c->bthr[p ^ 1];
+        ended = !first && c->near[p ^ 1] == 0u;
+        if (ended) {
+            const uint32_t m = umin32(c->nmin[p ^ 1], c->fmin[p ^ 1]);
+            if (m != 0xFFFFFFFFu) {
+                const uint64_t t = (uint64_t)m + c->bdelta;
+                bt = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
+            }
+        }
+    }
+    const bool skip = compaction_skips(c, p, first);
+    if (lh && blockIdx.x == 0 && threadIdx.x == 0) c->bthr[p] = bt;
+    if (skip) return;
+    const uint32_t thr = c->thr;
+    const bool nf = c->delta != 0;
+    const uint32_t heavy = nf ? c->heavy : 0u;
     compact_flags(
-        a.flags, a.V, &a.cnt->packed[p], &a.cnt->far[p], &a.cnt->fmin[p],
-        [&](uint32_t v, uint32_t& items, uint32_t& edges, uint32_t& key) {
-            edges = row_end<MODE>(a, v) - a.row_ptr[v];
+        a.flags, a.V, &c->packed[p], &c->far[p], &c->fmin[p],
+        [&](uint32_t v, uint32_t fl, uint32_t& items, uint32_t& edges, uint32_t& key, uint2& rows) {
+            const uint32_t rp = a.row_ptr[v], re = row_end<MODE>(a, v);
+            if (MODE != 0) rows.y = a.row_split[v];
+            if (lh) {
+                const uint32_t nh = a.nheavy[v];
+                if (fl == 2u) {
+                    if (!ended) return 2u;  // still waiting (no key: not a deferred vertex)
+                    rows.x = rp;
+                    edges = nh;
+                    items = nh ? 1u : 0u;
+                    return 0u;
+                }
+                const uint32_t x = order_key<A>(a.R[v]);
+                if (x >= bt) {  // a later bucket
+                    key = x;
+                    return 1u;
+                }
+                rows.x = rp + nh;
+                edges = re - rows.x;
+                items = edges ? 1u : 0u;
+                return nh ? 2u : 0u;
+            }
+            rows.x = rp;
+            edges = re - rp;
             items = edges ? 1u : 0u;
-            if (!nf || !edges) return true;
+            if (!nf || !edges) return 0u;
             key = order_key<A>(a.R[v]);
-            return key < thr || edges < heavy;
+            if (key < thr || edges < heavy) return 0u;
+            items = edges = 0;  // deferred
+            return 1u;
         },
-        [&](uint32_t v, uint32_t item, uint32_t edge, uint32_t, uint32_t) {
+        [&](uint32_t v, uint32_t item, uint32_t edge, uint32_t, uint32_t, uint2 rows) {
             a.fo[p][item] = edge;
-            a.fd[p][item] = a.row_ptr[v] - edge;
-            if (MODE != 0) a.fs[p][item] = a.row_split[v];
+            a.fd[p][item] = rows.x - edge;
+            if (MODE != 0) a.fs[p][item] = rows.y;
             a.fv[p][item] = v;
         },
-        heavy ? &a.cnt->kall[p] : nullptr);
+        heavy ? &c->kall[p] : nullptr);
 }
 
 // One 64-edge step of a walker over the frontier's edge range: the lane's
@@ -274,8 +330,8 @@ __device__ __forceinline__ void pull_walk(const SolveArgs& a, uint32_t T) {
             ++nup;
         }
         const uint64_t cm = __ballot(carry);
-        carry_v = cm ? uniform((uint32_t)__shfl((int)key, 63, 64)) : kNone;
-        carry_c = cm ? (uint32_t)__shfl((int)c, 63, 64) : worst;
+        carry_v = cm ? lane_value(key, 63) : kNone;
+        carry_c = cm ? lane_value(c, 63) : worst;
         u = un;
         w = wn;
         v = vn;
@@ -310,11 +366,11 @@ __device__ __forceinline__ void append_next(const SolveArgs& a, int p, bool impr
     if (!bal) return;
     if (!app) deg = 0;
     const uint32_t incl = wave_incl_scan(deg);
-    const uint32_t tot = __shfl(incl, 63, 64);
+    const uint32_t tot = lane_value(incl, 63);
     unsigned long long base = 0;
     if (lane_id() == 0) base = atomicAdd(&a.cnt->packed[p ^ 1], ((unsigned long long)__popcll(bal) << 32) | tot);
-    const uint32_t bi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), 0, 64);
-    const uint32_t be = (uint32_t)__shfl((int)(uint32_t)base, 0, 64);
+    const uint32_t bi = lane_value((uint32_t)(base >> 32), 0);
+    const uint32_t be = lane_value((uint32_t)base, 0);
     if (app) {
         const uint32_t item = bi + (uint32_t)__popcll(bal & lanemask_lt());
         const uint32_t edge = be + incl - deg;
@@ -337,7 +393,8 @@ __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int 
     // a sparse iteration (and no near/far schedule) lists the next frontier itself
     const bool small = (a.append_edges && edges_of(c0) <= a.append_edges) ||
                        (a.append_items && items_of(c0) <= a.append_items);
-    const bool appends = !pull && small && a.cnt->delta == 0;
+    const bool lh = a.nheavy != nullptr;
+    const bool appends = !pull && small && a.cnt->delta == 0 && !lh;
     const unsigned long long cx = expand_prologue(a.cnt, p, slot, appends);
     const uint32_t n = items_of(cx), T = edges_of(cx);
     if (T == 0) return;
@@ -366,6 +423,11 @@ __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int 
     count_visits<ST>(a, lane == 0 ? end[NW - 1] - base[0] : 0u);
 #pragma unroll
     for (int j = 0; j < NW; ++j) cur[j] = base[j] < end[j] ? wave_search(fo, n, base[j]) : 0u;
+    // bucketed schedule: report whether a value below the bucket's bound was
+    // written (once per wave) and the smallest one written at or above it
+    const uint32_t bt = lh ? a.cnt->bthr[p] : 0u;
+    bool near_told = false;
+    uint32_t above = 0xFFFFFFFFu;
     while (base[0] < end[0]) {
         Step st[NW];
         uint32_t off[NW];
@@ -409,14 +471,29 @@ __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int 
             if (st[j].want) st[j].want = Alg<A>::better(st[j].cand, a.R[st[j].v]);
         // then the updates
         uint32_t nup = 0;
+        bool below = false;
+        uint32_t amin = 0xFFFFFFFFu;
 #pragma unroll
         for (int j = 0; j < NW; ++j) {
             if (st[j].want) {
                 Alg<A>::improve_nr(&a.R[st[j].v], st[j].cand);
                 if (!appends) mark(a.flags, st[j].v);
                 ++nup;
+                if (lh) {
+                    const uint32_t k = order_key<A>(st[j].cand);
+                    if (k < bt) below = true;
+                    else amin = k < amin ? k : amin;
+                }
             }
             if (appends) append_next<MODE>(a, p, st[j].want, st[j].v, epoch);
+        }
+        if (lh) {
+            if (!near_told && __ballot(below)) {
+                if (lane == 0) a.cnt->near[p] = 1u;
+                near_told = true;
+            }
+            const uint32_t m = wave_min(amin);
+            above = m < above ? m : above;
         }
         if (ST) {
             const uint32_t su = wave_sum(nup);
@@ -434,17 +511,28 @@ __global__ void __launch_bounds__(kBlock) k_expand(SolveArgs a, Mask<MW> W, int 
             base[j] = nb;
         }
     }
+    // a plain read first: most waves hold no new minimum and skip the atomic
+    if (lh && lane == 0 && above != 0xFFFFFFFFu &&
+        above < __hip_atomic_load(&a.cnt->nmin[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin(&a.cnt->nmin[p], above);
 }
 
 // Start of a solve: the threshold starts one step above the best key.
+// With a bucket width (bdelta > 0), the first bucket spans the width above
+// the source's key, and the first compaction reads it as unfinished.
 __global__ void k_solve_start(FrontierCounters* c, uint32_t delta, uint32_t heavy, uint32_t* R, uint8_t* flags,
-                              uint32_t source, uint32_t at_source) {
+                              uint32_t source, uint32_t at_source, uint32_t bdelta, uint32_t first_bound) {
     if (threadIdx.x == 0) {
         c->delta = delta;
         c->heavy = delta ? heavy : 0u;
         c->thr = delta ? delta : 0xFFFFFFFFu;
+        c->far[0] = c->far[1] = 0u;
         c->fmin[0] = c->fmin[1] = 0xFFFFFFFFu;
         c->kall[0] = c->kall[1] = 0xFFFFFFFFu;
+        c->bdelta = bdelta;
+        c->bthr[0] = c->bthr[1] = bdelta ? first_bound : 0xFFFFFFFFu;
+        c->near[0] = c->near[1] = 1u;
+        c->nmin[0] = c->nmin[1] = 0xFFFFFFFFu;
         if (R) {
             R[source] = at_source;
             flags[source] = 1;
@@ -532,6 +620,7 @@ SolveArgs make_args(const Graph& g, const Frontier& f, uint32_t* R) {
     a.V = g.V;
     a.rv_src = a.rv_w = a.rv_dst = a.rv_cnt = nullptr;
     a.pull_frac = kNone;
+    a.nheavy = nullptr;
     return a;
 }
 
@@ -539,10 +628,23 @@ template <int A, int MW, bool ST>
 uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t* R, Frontier& f, hipStream_t s) {
     SolveArgs a = make_args(g, f, R);
     fill_u32(R, g.V, Alg<A>::unreached, s);
-    EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, f.delta, f.heavy, R, f.flags, source,
-               Alg<A>::at_source);
+    // the bucketed schedule needs additive weights (SSSP); it replaces near/far and the pull step
+    uint32_t bd = 0;
+    if (A == EVQ_SSSP && f.bdelta && g.E) {
+        if (const WeightOrder* wo = weight_order_ready(g, f.bdelta, s)) {
+            a.col = wo->col;
+            a.wgt = wo->w;
+            a.nheavy = wo->nheavy;
+            bd = f.bdelta;
+        }
+    }
+    const uint32_t fd = bd ? 0u : f.delta;
+    // a guard against runaway loops: a bucket end takes an iteration of its own at most once per vertex
+    const uint64_t cap = bd ? 4ull * g.V + 16 : (uint64_t)g.V + 2;
+    EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, fd, f.heavy, R, f.flags, source, Alg<A>::at_source,
+               bd, bd ? order_key<A>(Alg<A>::at_source) + bd : 0u);
     if (W.full) {
-        const uint32_t pf = f.delta == 0 && g.E ? pull_frac() : kNone;
+        const uint32_t pf = fd == 0 && !bd && g.E ? pull_frac() : kNone;
         if (pf != kNone && reverse_ready(g, s)) {
             a.rv_src = g.rv_src;
             a.rv_w = g.rv_w;
@@ -550,16 +652,16 @@ uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t*
             a.rv_cnt = g.rv_cnt;
             a.pull_frac = pf;
         }
-        return frontier_loop<A, 0, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
+        return frontier_loop<A, 0, MW, ST>(a, window_mask<MW>(W), f, s, cap);
     }
-    return frontier_loop<A, 1, MW, ST>(a, window_mask<MW>(W), f, s, (uint64_t)g.V + 2);
+    return frontier_loop<A, 1, MW, ST>(a, window_mask<MW>(W), f, s, cap);
 }
 
 template <int A, int MW, bool ST>
 uint64_t solve_cup_t(const Graph& g, const Window& W, uint32_t* R, Frontier& f, hipStream_t s) {
     SolveArgs a = make_args(g, f, R);
     EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, f.delta, f.heavy, (uint32_t*)nullptr, f.flags, 0u,
-               0u);
+               0u, 0u, 0u);
     if (g.n_partial)
         EVQ_LAUNCH("solve_seed_partial", (k_seed_partial<A, MW, ST>), grid_for(g.n_partial, kBlock, 16384), kBlock, s,
                    a, window_mask<MW>(W), g.p_src, g.p_dst, g.p_w, g.p_mask, (uint32_t)g.n_partial);

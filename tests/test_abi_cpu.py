@@ -147,3 +147,25 @@ def test_build_rejects_incomplete_allocator(evq):
     a = evq.Allocator(evq.ALLOC_FN(lambda n, c: None), evq.FREE_FN(), None)
     rc, h = _build(evq, 4, [[0, 1, 1]], [([], [])], allocator=a)
     assert rc == evq.EVQ_EINVAL and not h.value
+
+
+def test_tuning_round_trip_and_validation(evq):
+    """evq_tuning_get / evq_tuning_set are host-only: the defaults, a round trip of every field
+    (the bucket width included), and the rejected values, which leave the knobs as they were."""
+    prev = evq.get_tuning()
+    try:
+        assert prev["launch_depth"] >= 1 and prev["relax_staged"] in (0, 2, 4)
+        assert "bucket_width" in prev
+        evq.set_tuning(bucket_width=17, launch_depth=5, delta=[1, 2, 3, 4, 5])
+        t = evq.get_tuning()
+        assert t["bucket_width"] == 17 and t["launch_depth"] == 5 and t["delta"] == [1, 2, 3, 4, 5]
+        evq.set_tuning(bucket_width=evq.BUCKET_WIDTH_AUTO)
+        assert evq.get_tuning()["bucket_width"] == 0xFFFFFFFF
+        for bad in (dict(launch_depth=0), dict(launch_depth=33), dict(split_min=0), dict(relax_staged=3)):
+            with pytest.raises(evq.EvqError) as ei:
+                evq.set_tuning(**bad)
+            assert ei.value.status == evq.EVQ_EINVAL
+            assert evq.get_tuning()["launch_depth"] == 5
+    finally:
+        evq.set_tuning(**prev)
+    assert evq.get_tuning() == prev

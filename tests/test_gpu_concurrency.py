@@ -128,9 +128,11 @@ def test_appends_while_querying(evq):
 def test_threads_share_the_reverse_build(evq, tuned):
     # full-window queries from four threads and streams released together on a
     # fresh graph, pulling whenever they can: the reverse CSR is built once by
-    # whichever query asks second, the others' streams wait for it
+    # whichever query asks second, the SSSP rows ordered by weight once by
+    # whichever asks first (bucketed schedule at the graph's automatic width),
+    # the others' streams wait for them
     import torch
-    tuned(pull_frac=0.0)
+    tuned(pull_frac=0.0, bucket_width=evq.BUCKET_WIDTH_AUTO)
     inst = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=41)
     srcs = synth.pick_sources(inst, 4, seed=3)
     rep = oracle.replay(inst)
@@ -161,6 +163,7 @@ def test_threads_share_the_reverse_build(evq, tuned):
             t.join()
         grown = g.info["device_bytes"]
     assert not bad, f"wrong results on (thread, round, algo, source): {bad[:5]}"
-    # built exactly once: the handle grew by one reverse CSR (source, weight and destination per
-    # edge, two counters)
-    assert grown - held == 12 * max(E, 1) + 8, (held, grown)
+    # built exactly once each: the handle grew by one reverse CSR (source, weight and destination
+    # per edge, two counters; the SSWP queries pull) and one weight-ordered copy of the rows (edge
+    # and weight per edge, heavy count per vertex; the SSSP queries' bucketed schedule)
+    assert grown - held == 12 * max(E, 1) + 8 + 8 * max(E, 1) + 4 * max(V, 1), (held, grown)

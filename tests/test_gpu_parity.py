@@ -297,8 +297,9 @@ def test_heavy_gating_many_blocks(evq, algo, tuned):
 def test_pull_step(evq, algo, frac, tuned):
     # full-window intersection solve pulling in every iteration (0), in the
     # dense ones (0.3) or never (2): same values and bounds as the oracle, on
-    # small graphs and on one with hubs and many waves per slice
-    tuned(pull_frac=frac)
+    # small graphs and on one with hubs and many waves per slice (SSSP with
+    # its bucketed schedule off, which never pulls)
+    tuned(pull_frac=frac, bucket_width=0)
     cases = [(synth.config_instance("small", seed=s), 0) for s in (1, 2, 3)]
     big = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=41)
     cases.append((big, synth.pick_sources(big, 1, seed=3)[0]))
@@ -317,6 +318,41 @@ def test_pull_step(evq, algo, frac, tuned):
         assert_equal_values(got, want, f"pull {frac} case {ci}")
         assert_equal_values(again, want, f"pull {frac} case {ci} second query")
         assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
+
+
+@pytest.mark.parametrize("width", [0, 1, 3, 17, 100000, 0xFFFFFFFF])
+def test_bucketed_sssp(evq, width, tuned):
+    # SSSP intersection solves under delta-stepping with light and heavy edges (bucket width 1:
+    # every edge of weight > 1 heavy; 100000: every edge light, plain thresholds; the graph's
+    # automatic width; 0: off), full window and sub-windows (which also walk the window-partial
+    # edges with the light ones), one- and two-word masks, against the oracle; on the graph with
+    # hubs the schedule visits fewer edges than plain frontier iterations
+    tuned(bucket_width=width)
+    cases = [(synth.config_instance("small", seed=s), 0, [(0, 8), (2, 5), (7, 1)]) for s in (1, 2)]
+    big = synth.rmat_instance(15, 200000, 16, 150, 150, wmin=1, wmax=100, seed=41)
+    cases.append((big, synth.pick_sources(big, 1, seed=3)[0], [(0, 16), (3, 9)]))
+    wide = synth.rmat_instance(12, 40000, 100, 60, 60, wmin=1, wmax=1000, seed=43)
+    cases.append((wide, synth.pick_sources(wide, 1, seed=2)[0], [(0, 100), (10, 70), (64, 36)]))
+    for ci, (inst, src, wins) in enumerate(cases):
+        trip, bits = oracle.replay(inst)
+        with _graph(evq, inst) as g:
+            for b, L in wins:
+                want = oracle.window_values(inst, oracle.SSSP, src, b, L, replayed=(trip, bits))
+                rc_o, ru_o = oracle.bounds(inst.num_vertices, trip, bits, oracle.SSSP, src, b, L)
+                for rep in range(2):  # the first query builds the weight-ordered rows, the second reuses them
+                    got = gpu_values(g, oracle.SSSP, src, b, L)
+                    assert_equal_values(got, want, f"width {width} case {ci} [{b},{b + L}) query {rep}")
+                rc, ru = gpu_bounds(g, oracle.SSSP, src, b, L)
+                assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o), (width, ci, b, L)
+    if width in (3, 17):
+        visits = {}
+        with _graph(evq, big) as g:
+            src = cases[2][1]
+            for w in (0, width):
+                tuned(bucket_width=w)
+                _, st = gpu_values(g, oracle.SSSP, src, 0, big.K, stats=True)
+                visits[w] = st["edges_cap"]
+        assert visits[width] < visits[0], visits
 
 
 @pytest.mark.parametrize("staged", [0, 2, 4])

@@ -61,10 +61,14 @@ def test_noalloc_equals_query_two_calls(evq, graphs, algo):
     assert np.array_equal(got.reshape(small.num_vertices, 5), oracle.window_values(small, algo, ss, 2, 5))
 
 
-def test_noalloc_with_the_pull_step(evq, graphs):
+def test_noalloc_with_the_pull_step(evq, graphs, tuned):
     (big, gb, sb), _ = graphs
-    for _ in range(2):  # the second full-window evq_query builds the reverse CSR; the no-alloc call then uses it
-        gb.query(oracle.SSSP, sb, 0, big.K)
+    # the second full-window SSWP evq_query builds the reverse CSR and the SSSP one (bucketed
+    # schedule at the graph's automatic width) the weight-ordered rows; the no-alloc calls then use them
+    tuned(bucket_width=evq.BUCKET_WIDTH_AUTO)
+    for _ in range(2):
+        gb.query(oracle.SSWP, sb, 0, big.K)
+    gb.query(oracle.SSSP, sb, 0, big.K)
     for algo in ALGOS:
         got, want = _pair(evq, gb, algo, sb, 0, big.K)
         assert np.array_equal(got, want), f"algo {algo} with the pull step"
