@@ -21,7 +21,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rmat.c")
-_LIB = os.path.join(_HERE, "libsynth.so")
+# EVQ_SYNTH_LIBRARY loads another build of the same source (the sanitized one of the tests)
+_LIB = os.environ.get("EVQ_SYNTH_LIBRARY") or os.path.join(_HERE, "libsynth.so")
 _lib = None
 
 
