@@ -46,9 +46,10 @@ def snapshot_edge_counts(ex, K):
     return counts
 
 
-def counter_traffic(kernel):
-    """HBM traffic per dispatch of `kernel` from the committed rocprofv3 counter summary, or (None, reason)
-    when there is none or the kernel's sources changed since the counters were taken."""
+def counter_traffic(kernel, workload):
+    """HBM traffic per dispatch of `kernel` on `workload` ("<config> <algo> window [b,e)") from the committed
+    rocprofv3 counter summaries, or (None, reason) when there is none or the kernel's sources changed since
+    the counters were taken."""
     import glob
     import hashlib
     import re
@@ -57,7 +58,7 @@ def counter_traffic(kernel):
         if not m:
             continue
         blk = json.loads(m.group(1))
-        if blk.get("timing_name") != kernel:
+        if blk.get("timing_name") != kernel or blk.get("workload") != workload:
             continue
         h = hashlib.sha256()
         for f in blk["sources"]:
@@ -563,7 +564,7 @@ def main():
         if byts is not None:
             ach = byts * reps / (tot_ms / 1000.0) / 1e9
             avg_us = tot_ms * 1000.0 / launches
-            traffic, tsrc = counter_traffic(dom)
+            traffic, tsrc = counter_traffic(dom, f"{args.config} {args.algo} window [{b},{b + L})")
             roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
                     "avg_launch_us": round(avg_us, 3), "launches_per_query": launches // reps,
@@ -639,6 +640,14 @@ def main():
                        "lane_relaxations": hst["lane_relaxations"],
                        "workload": f"mid graph, K={hv.K} snapshots of 100000+100000 updates, {args.algo.upper()} "
                                    f"from vertex {hsrc}, window [0,{hv.K})"}
+        # counted HBM traffic of the relaxation kernel on this workload (committed counter summary)
+        htraffic, htsrc = counter_traffic("relax", f"churn {args.algo} window [0,{hv.K})")
+        relax_heavy["traffic"] = htraffic
+        relax_heavy["traffic_source"] = htsrc
+        if htraffic:
+            hus = rt * 1000.0 / rl
+            relax_heavy["traffic_GBps"] = round(htraffic / (hus * 1e-6) / 1e9, 2)
+            relax_heavy["traffic_frac"] = round(htraffic / (hus * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
         log(f"[bench] relaxer on the heavy-churn mid graph: {ach:.1f} GB/s algorithmic "
             f"({hst['n_unstable'] / hv.num_vertices:.0%} unstable, query {hms:.2f} ms)")
 
