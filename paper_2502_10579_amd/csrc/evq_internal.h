@@ -163,7 +163,7 @@ class Workspace {
   public:
     enum Slot {
         kFlags, kFo, kFd, kFs, kFv, kFo1, kFd1, kFs1, kFv1, kStamp, kControl, kRcap, kRcup, kCidOf, kUlist, kCuo,
-        kRv, kRc, kRuo, kKc, kRecs, kTasks, kX, kBatchCap, kBatchCup, kBatchTable, kSlots
+        kRv, kRc, kRuo, kKc, kRecs, kTasks, kX, kBatchCap, kBatchCup, kBatchTable, kUbits, kSlots
     };
     static Workspace& get(hipStream_t s);
     static Workspace& arena(hipStream_t s, NoAlloc& na);

@@ -132,26 +132,48 @@ struct UCounters {
 // U = {v : R_cap[v] != R_cup[v]} (all vertices when rcap is null).  Every U
 // vertex gets a compact id c (ascending within a block), ulist[c] = v and the
 // start cuo[c] of its union row in a buffer holding all of U's rows back to
-// back; cid_of[v] = kNone for the others.  U vertices with edges are also
-// listed as rows: rv (vertex), rc (compact id), ruo (row start).
+// back; cid_of[v] = kNone for the others, and bit v of ubits says whether v is
+// in U.  U vertices with edges are also listed as rows: rv (vertex), rc
+// (compact id), ruo (row start).  A thread takes 8 consecutive vertices: two
+// 16-byte loads of each bound and two 16-byte stores of their compact ids when
+// the bounds are 16-byte aligned and the 8 are in range, one byte of ubits.
+__device__ __forceinline__ void load8(const uint32_t* __restrict__ p, uint64_t v0, uint64_t V, bool vec,
+                                      uint32_t (&o)[kUPerThread]) {
+    if (vec) {
+        const uint4 x = reinterpret_cast<const uint4*>(p + v0)[0], y = reinterpret_cast<const uint4*>(p + v0)[1];
+        o[0] = x.x, o[1] = x.y, o[2] = x.z, o[3] = x.w, o[4] = y.x, o[5] = y.y, o[6] = y.z, o[7] = y.w;
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < kUPerThread; ++k) o[k] = v0 + k < V ? p[v0 + k] : 0u;
+}
+
 __global__ void __launch_bounds__(kUBlock) k_unstable(const uint32_t* __restrict__ rcap,
                                                       const uint32_t* __restrict__ rcup, uint32_t V,
                                                       const uint32_t* __restrict__ row_ptr,
                                                       uint32_t* __restrict__ cid_of, uint32_t* __restrict__ ulist,
                                                       uint32_t* __restrict__ cuo, uint32_t* __restrict__ rv,
                                                       uint32_t* __restrict__ rc, uint32_t* __restrict__ ruo,
-                                                      UCounters* cnt) {
+                                                      uint8_t* __restrict__ ubits, UCounters* cnt) {
     __shared__ unsigned long long base_id, base_row;
+    // 16-byte accesses need aligned bound arrays (the caller's, for evq_query_bounds); cid_of is a workspace buffer
+    const bool al = rcap && (((uintptr_t)rcap | (uintptr_t)rcup) % 16 == 0) && (uintptr_t)cid_of % 16 == 0;
     for (uint64_t b0 = (uint64_t)blockIdx.x * kUPerBlock; b0 < V; b0 += (uint64_t)gridDim.x * kUPerBlock) {
         const uint64_t v0 = b0 + (uint64_t)threadIdx.x * kUPerThread;
+        const bool vec = al && v0 + kUPerThread <= V;
         uint32_t bits = 0;
         uint32_t deg[kUPerThread];
         uint32_t val[3] = {0, 0, 0};  // ids, rows, edges
+        uint32_t cap[kUPerThread], cup[kUPerThread];
+        if (rcap) {
+            load8(rcap, v0, V, vec, cap);
+            load8(rcup, v0, V, vec, cup);
+        }
 #pragma unroll
         for (int k = 0; k < kUPerThread; ++k) {
             deg[k] = 0;
             const uint64_t v = v0 + k;
-            if (v < V && (!rcap || rcap[v] != rcup[v])) {
+            if (v < V && (!rcap || cap[k] != cup[k])) {
                 bits |= 1u << k;
                 deg[k] = row_ptr[v + 1] - row_ptr[v];
                 val[0] += 1;
@@ -159,6 +181,7 @@ __global__ void __launch_bounds__(kUBlock) k_unstable(const uint32_t* __restrict
                 val[2] += deg[k];
             }
         }
+        if (v0 < V) ubits[v0 >> 3] = (uint8_t)bits;
         uint32_t pre[3], tot[3];
         block_scan3(val, pre, tot);
         if (threadIdx.x == 0) {
@@ -169,12 +192,13 @@ __global__ void __launch_bounds__(kUBlock) k_unstable(const uint32_t* __restrict
         uint32_t id = (uint32_t)base_id + pre[0];
         uint32_t row = (uint32_t)(base_row >> 32) + pre[1];
         uint32_t edge = (uint32_t)base_row + pre[2];
+        uint32_t cids[kUPerThread];
 #pragma unroll
         for (int k = 0; k < kUPerThread; ++k) {
+            cids[k] = kNone;
             const uint64_t v = v0 + k;
-            if (v >= V) break;
             if ((bits >> k) & 1u) {
-                cid_of[v] = id;
+                cids[k] = id;
                 ulist[id] = (uint32_t)v;
                 cuo[id] = edge;
                 if (deg[k]) {
@@ -185,9 +209,15 @@ __global__ void __launch_bounds__(kUBlock) k_unstable(const uint32_t* __restrict
                     edge += deg[k];
                 }
                 ++id;
-            } else {
-                cid_of[v] = kNone;
             }
+        }
+        if (vec) {
+            reinterpret_cast<uint4*>(cid_of + v0)[0] = make_uint4(cids[0], cids[1], cids[2], cids[3]);
+            reinterpret_cast<uint4*>(cid_of + v0)[1] = make_uint4(cids[4], cids[5], cids[6], cids[7]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kUPerThread; ++k)
+                if (v0 + k < V) cid_of[v0 + k] = cids[k];
         }
         __syncthreads();
     }
@@ -382,6 +412,7 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
                                                        const uint32_t* __restrict__ p_w,
                                                        const uint64_t* __restrict__ p_mask, uint32_t n_partial,
                                                        const uint32_t* __restrict__ cid_of,
+                                                       const uint8_t* __restrict__ ubits,
                                                        const uint32_t* __restrict__ rcap, uint32_t b, uint32_t L,
                                                        uint32_t K, uint32_t pb, uint32_t pL) {
     using T = Lanes<LG>;
@@ -400,8 +431,10 @@ __global__ void __launch_bounds__(kBlock) k_relax_seed(RelaxArgs r, const uint32
 #pragma unroll
         for (int j = 0; j < T::NLW; ++j) lanes[j] = 0;
         if (act) {
-            cv = cid_of[p_dst[q]];
-            act = cv != kNone;
+            // the U bitmap (V / 8 bytes, cache-resident) first: most destinations are stable
+            const uint32_t d = p_dst[q];
+            act = ((ubits[d >> 3] >> (d & 7)) & 1u) != 0u;
+            if (act) cv = cid_of[d];
             if (act) {
                 // seeded lanes: the relaxed window (b, L); the edge must be
                 // partial in the bound window (pb, pL), which contains it
@@ -649,12 +682,25 @@ __global__ void __launch_bounds__(kBlock)
 
 // ------------------------------------------------------------------ init / K5
 
+// X[c][i] = R_cap[ulist[c]]: 16-byte stores when a row holds a multiple of 4 lanes.
 template <int LG>
 __global__ void k_xinit(const uint32_t* __restrict__ ulist, uint32_t nU, const uint32_t* __restrict__ rcap,
                         uint32_t* __restrict__ X) {
-    const uint64_t n = (uint64_t)nU * LG;
-    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
-        X[k] = rcap[ulist[k / LG]];
+    if constexpr (LG % 4 == 0) {
+        constexpr uint32_t Q = LG / 4;  // 16-byte words per row
+        const uint64_t n = (uint64_t)nU * Q;
+        uint4* __restrict__ X4 = reinterpret_cast<uint4*>(X);
+        for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n;
+             k += (uint64_t)gridDim.x * blockDim.x) {
+            const uint32_t b = rcap[ulist[k / Q]];
+            X4[k] = make_uint4(b, b, b, b);
+        }
+    } else {
+        const uint64_t n = (uint64_t)nU * LG;
+        for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n;
+             k += (uint64_t)gridDim.x * blockDim.x)
+            X[k] = rcap[ulist[k / LG]];
+    }
 }
 
 // Plain evaluation: every vertex starts unreached except the source (compact
@@ -905,6 +951,7 @@ struct Reduced {
     uint32_t nU = 0, nR = 0;
     uint64_t TU = 0;
     uint32_t* cid_of = nullptr;
+    uint8_t* ubits = nullptr;  // bit v: v is in U
     uint32_t* ulist = nullptr;
     uint32_t* cuo = nullptr;
     uint32_t* rv = nullptr;   // U rows: vertex, compact id, start in the record buffer
@@ -925,6 +972,7 @@ Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup,
     Reduced r;
     const uint32_t V = g.V;
     r.cid_of = ws.buf<uint32_t>(Workspace::kCidOf, V);
+    r.ubits = ws.buf<uint8_t>(Workspace::kUbits, (uint64_t)V / 8 + 8);
     r.ulist = ws.buf<uint32_t>(Workspace::kUlist, V);
     r.cuo = ws.buf<uint32_t>(Workspace::kCuo, V);
     uint32_t* rv = r.rv = ws.buf<uint32_t>(Workspace::kRv, V);
@@ -933,7 +981,7 @@ Reduced reduce_graph(const Graph& g, const uint32_t* rcap, const uint32_t* rcup,
     UCounters* uc = reinterpret_cast<UCounters*>(f.aux);
     fill_u32(reinterpret_cast<uint32_t*>(uc), sizeof(UCounters) / 4, 0u, s);
     EVQ_LAUNCH("compact_unstable", k_unstable, grid_for(V, kUPerBlock, 65535), kUBlock, s,
-               all_vertices ? nullptr : rcap, rcup, V, g.row_ptr, r.cid_of, r.ulist, r.cuo, rv, rc, ruo, uc);
+               all_vertices ? nullptr : rcap, rcup, V, g.row_ptr, r.cid_of, r.ulist, r.cuo, rv, rc, ruo, r.ubits, uc);
     EVQ_HIP(hipMemcpyAsync(mb.h, uc, sizeof(UCounters), hipMemcpyDeviceToHost, s));
     EVQ_HIP(hipStreamSynchronize(s));
     const unsigned long long* hc = reinterpret_cast<const unsigned long long*>(mb.h);
@@ -1010,13 +1058,15 @@ void relax_phase(const Graph& g, const Window& W, const Window& PW, const uint32
                    red.nU, source, Alg<A>::unreached, Alg<A>::at_source, X);
         EVQ_LAUNCH("relax_seed", k_mark_source, 1, 64, s, f.flags, red.cid_of, source);
     } else {
-        EVQ_LAUNCH("relax_xinit", k_xinit<LG>, grid_for((uint64_t)red.nU * LG, 256 * 4), 256, s, red.ulist, red.nU,
+        EVQ_LAUNCH("relax_xinit", k_xinit<LG>, grid_for((uint64_t)red.nU * (LG % 4 == 0 ? LG / 4 : LG), 256 * 4), 256,
+                   s, red.ulist, red.nU,
                    rcap, X);
         if (g.n_partial) {
             const uint32_t waves = (uint32_t)((g.n_partial + 63) / 64);
 #define EVQ_SEED(MW_)                                                                                             \
     EVQ_LAUNCH("relax_seed", (k_relax_seed<A, MW_, LG, ST>), grid_for(waves, kBlock / 64, 8192), kBlock, s, ra,   \
-               g.p_src, g.p_dst, g.p_w, g.p_mask, (uint32_t)g.n_partial, red.cid_of, rcap, W.b, W.L, g.K, PW.b, PW.L)
+               g.p_src, g.p_dst, g.p_w, g.p_mask, (uint32_t)g.n_partial, red.cid_of, red.ubits, rcap, W.b, W.L, g.K, \
+               PW.b, PW.L)
             if (g.MW == 1) EVQ_SEED(1);
             else EVQ_SEED(2);
 #undef EVQ_SEED
