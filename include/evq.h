@@ -347,9 +347,11 @@ evq_status evq_batch_config_set(const evq_batch_config* c);
  *                 iteration whose frontier holds at least this share of the
  *                 all-present edges pulls (every vertex takes its best
  *                 all-present in-edge) instead of pushing; the graph's
- *                 reverse CSR (8 bytes per all-present edge) is built by the
+ *                 reverse CSR (12 bytes per union edge) is built by the
  *                 second full-window query on a graph version (the first
- *                 pushes only).  Default 0.5; above 1 (or negative): never.
+ *                 pushes only).  Graphs with 2^30 or more vertices or union
+ *                 edges never pull.  Default 0.5; above 1 (or negative):
+ *                 never.
  *   split_frac    EVQ_SPLIT_FRAC: a window with more than split_frac * V
  *                 unstable vertices is answered as two halves, each with its
  *                 own bounds, to depth 4 (default 0: off).

@@ -268,6 +268,14 @@ __device__ __forceinline__ uint32_t seg_scan(uint32_t key, uint32_t c) {
     return c;
 }
 
+// p[i] of an array below 4 GiB, addressed as its base plus a 32-bit byte
+// offset (one 32-bit offset register per load, no 64-bit address pairs).
+__device__ __forceinline__ uint32_t load_off32(const uint32_t* __restrict__ p, uint32_t i) {
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(p) + (i << 2));
+}
+
+// The reverse CSR and the values are addressed with 32-bit byte offsets
+// (the host pulls only with fewer than 2^30 vertices and edges).
 template <int A, bool ST>
 __device__ __forceinline__ void pull_walk(const SolveArgs& a, uint32_t T) {
     const uint32_t lane = lane_id();
@@ -287,33 +295,20 @@ __device__ __forceinline__ void pull_walk(const SolveArgs& a, uint32_t T) {
     const bool cut_hi = end < T && a.rv_dst[end] == v_hi;
     uint32_t carry_v = kNone, carry_c = worst;
     uint32_t nup = 0;
-    // Two-deep pipeline: a step's in-edges are loaded two steps ahead and their
-    // sources' values one step ahead, so the step's own chain (scan, destination
-    // value, store) runs while the next steps' loads are in flight.
+    // in-edges of the step at b0 (the slice's last one for lanes and steps past its end, so that every
+    // load is issued unconditionally and in the same order)
     auto edge_at = [&](uint32_t b0, uint32_t& u, uint32_t& w, uint32_t& v) {
-        if (b0 < end) {
-            const uint32_t t = b0 + lane < end ? b0 + lane : b0;
-            u = a.rv_src[t];
-            w = a.rv_w[t];
-            v = a.rv_dst[t];
-        } else {
-            u = 0;
-            w = 0;
-            v = kNone;
-        }
+        const uint32_t t = b0 + lane < end ? b0 + lane : end - 1;
+        u = load_off32(a.rv_src, t);
+        w = load_off32(a.rv_w, t);
+        v = load_off32(a.rv_dst, t);
     };
-    uint32_t u, w, v, un, wn, vn;
-    edge_at(beg, u, w, v);
-    edge_at(beg + 64, un, wn, vn);
-    uint32_t x = a.R[u];
-    for (uint32_t base = beg; base < end; base += 64) {
+    // One step of 64 in-edges: weights w, destinations v, the sources' values
+    // x and the destinations' values rv; vn is the next step's destination.
+    auto step = [&](uint32_t base, uint32_t w, uint32_t v, uint32_t x, uint32_t rv, uint32_t vn) {
         const bool act = base + lane < end;
         const uint32_t key = act ? v : kNone;  // idle lanes form a segment of their own
         const uint32_t nb = base + 64;
-        const uint32_t xn = nb < end ? a.R[un] : 0u;
-        uint32_t unn, wnn, vnn;
-        edge_at(nb + 64, unn, wnn, vnn);
-        const uint32_t rv = a.R[v];  // read before the scan, used at the segment's end
         uint32_t c = act ? Alg<A>::extend(x, w) : worst;
         if (lane == 0 && key == carry_v && Alg<A>::better(carry_c, c)) c = carry_c;
         c = seg_scan<A>(key, c);
@@ -332,13 +327,42 @@ __device__ __forceinline__ void pull_walk(const SolveArgs& a, uint32_t T) {
         const uint64_t cm = __ballot(carry);
         carry_v = cm ? lane_value(key, 63) : kNone;
         carry_c = cm ? lane_value(c, 63) : worst;
-        u = un;
-        w = wn;
-        v = vn;
-        x = xn;
-        un = unn;
-        wn = wnn;
-        vn = vnn;
+    };
+    // Software pipeline: a step's in-edges are loaded four steps ahead and
+    // the values of its sources and destinations two steps ahead.  Each step
+    // first runs its own chain, then gathers the values two steps ahead, then
+    // loads the in-edges four steps ahead.  Loads complete in issue order, so
+    // the wait for a step's values leaves the next step's values and the
+    // in-edges of the next two in flight, and the wait for the in-edges to
+    // gather from leaves the next step's values in flight.  Four sets of
+    // in-edge registers and two of value registers rotate; the loop is
+    // unrolled four times by hand so that they are renamed rather than
+    // copied (a copy would wait for the load in flight into its source).
+    // pipe(): the step at `base` with its in-edges in (u0, w0, v0), the next
+    // step's destinations in v1, the in-edges two steps ahead in (u2, v2) and
+    // this step's values in (x0, r0); gathers the values two steps ahead into
+    // (x0, r0) and loads the in-edges four steps ahead into (u0, w0, v0).
+    // False after the slice's last step.
+    auto pipe = [&](uint32_t& base, uint32_t& u0, uint32_t& w0, uint32_t& v0, uint32_t v1, uint32_t u2, uint32_t v2,
+                    uint32_t& x0, uint32_t& r0) {
+        step(base, w0, v0, x0, r0, v1);
+        x0 = load_off32(a.R, u2);
+        r0 = load_off32(a.R, v2);
+        edge_at(base + 256, u0, w0, v0);
+        base += 64;
+        return base < end;
+    };
+    uint32_t uA, wA, vA, uB, wB, vB, uC, wC, vC, uD, wD, vD;
+    edge_at(beg, uA, wA, vA);
+    edge_at(beg + 64, uB, wB, vB);
+    edge_at(beg + 128, uC, wC, vC);
+    edge_at(beg + 192, uD, wD, vD);
+    uint32_t xP = load_off32(a.R, uA), rP = load_off32(a.R, vA), xQ = load_off32(a.R, uB), rQ = load_off32(a.R, vB);
+    for (uint32_t base = beg;;) {
+        if (!pipe(base, uA, wA, vA, vB, uC, vC, xP, rP)) break;
+        if (!pipe(base, uB, wB, vB, vC, uD, vD, xQ, rQ)) break;
+        if (!pipe(base, uC, wC, vC, vD, uA, vA, xP, rP)) break;
+        if (!pipe(base, uD, wD, vD, vA, uB, vB, xQ, rQ)) break;
     }
     if (ST) {
         const uint32_t su = wave_sum(nup);
@@ -644,7 +668,7 @@ uint64_t solve_cap_t(const Graph& g, const Window& W, uint32_t source, uint32_t*
     EVQ_LAUNCH("solve_start", k_solve_start, 1, 64, s, f.cnt, fd, f.heavy, R, f.flags, source, Alg<A>::at_source,
                bd, bd ? order_key<A>(Alg<A>::at_source) + bd : 0u);
     if (W.full) {
-        const uint32_t pf = fd == 0 && !bd && g.E ? pull_frac() : kNone;
+        const uint32_t pf = fd == 0 && !bd && g.E && g.E < (1ull << 30) && g.V < (1u << 30) ? pull_frac() : kNone;
         if (pf != kNone && reverse_ready(g, s)) {
             a.rv_src = g.rv_src;
             a.rv_w = g.rv_w;
