@@ -320,6 +320,57 @@ def test_pull_step(evq, algo, frac, tuned):
         assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
 
 
+def _indegree_pattern_instance():
+    # 16,384 vertices whose in-degrees cycle through counts on both sides of
+    # multiples of 64 (0 ... 700, about 3.5M edges from uniform sources,
+    # weights 1..100), so that the pull step's slices span several 64-edge
+    # steps and destinations run across step and slice ends at every offset;
+    # 4 snapshots of 2,000 deletions of base edges and 2,000 additions
+    rng = np.random.default_rng(20250210)
+    V = 1 << 14
+    pattern = np.array([0, 1, 2, 3, 63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256, 257, 320, 511, 512,
+                        513, 700])
+    deg = pattern[np.arange(V) % len(pattern)]
+    dst = np.repeat(np.arange(V), deg)
+    src = rng.integers(0, V, len(dst))
+    w = rng.integers(1, 101, len(dst))
+    base = np.stack([src, dst, w], axis=1).astype(np.uint32)
+    dels, adds = [], []
+    for _ in range(4):
+        dels.append(base[rng.choice(len(base), 2000, replace=False)].copy())
+        adds.append(np.stack([rng.integers(0, V, 2000), rng.integers(0, V, 2000), rng.integers(1, 101, 2000)],
+                             axis=1).astype(np.uint32))
+    return synth.Instance(V, base, dels, adds)
+
+
+@pytest.fixture(scope="module")
+def indegree_case():
+    inst = _indegree_pattern_instance()
+    trip, bits = oracle.replay(inst)
+    want = {}
+    for algo in ALGOS:
+        want[algo] = (oracle.window_values(inst, algo, 5, 0, inst.K, replayed=(trip, bits)),
+                      oracle.bounds(inst.num_vertices, trip, bits, algo, 5, 0, inst.K))
+    return inst, want
+
+
+@pytest.mark.parametrize("frac", [0.0, 0.3])
+@pytest.mark.parametrize("algo", ALGOS)
+def test_pull_step_multi_step_slices(evq, algo, frac, tuned, indegree_case):
+    # the pull step where each wave's slice holds several 64-edge steps (its
+    # loads run four steps ahead): values and bounds equal the oracle's
+    tuned(pull_frac=frac, bucket_width=0)
+    inst, want = indegree_case
+    vals_o, (rc_o, ru_o) = want[algo]
+    with _graph(evq, inst) as g:
+        first = gpu_values(g, algo, 5, 0, inst.K)  # pushes only
+        rc, ru = gpu_bounds(g, algo, 5, 0, inst.K)  # builds the reverse CSR
+        got = gpu_values(g, algo, 5, 0, inst.K)
+    assert_equal_values(first, vals_o, f"push only, algo {algo}")
+    assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o), f"bounds, pull {frac}, algo {algo}"
+    assert_equal_values(got, vals_o, f"pull {frac}, algo {algo}")
+
+
 @pytest.mark.parametrize("width", [0, 1, 3, 17, 100000, 0xFFFFFFFF])
 def test_bucketed_sssp(evq, width, tuned):
     # SSSP intersection solves under delta-stepping with light and heavy edges (bucket width 1:
