@@ -396,6 +396,16 @@ evq_status evq_batch_config_set(const evq_batch_config* c);
  *                 off, since on R-MAT graphs the extra iterations cost more
  *                 than the edge visits saved; 0xFFFFFFFF: a width from the
  *                 graph's largest weight and mean out-degree.
+ *   vertex_order  EVQ_VERTEX_ORDER: evq_build numbers the vertices inside the
+ *                 graph by descending degree over the base edges and all
+ *                 batch events (both endpoints; ties by id), so that the
+ *                 values of the hubs, which most edges read, share cache
+ *                 lines (default 1; 0: the caller's numbering).  Sources are
+ *                 mapped on the way in and every output (values, bounds,
+ *                 compact results, exports) is in the caller's numbering;
+ *                 the graph holds the map both ways on the device (8 bytes
+ *                 per vertex) and on the host (4).  Read by evq_build; later
+ *                 versions (evq_append) keep their graph's numbering.
  * evq_tuning_set: EVQ_EINVAL on NULL, launch_depth outside 1..32,
  * split_min == 0 or relax_staged not 0, 2 or 4; calls already running keep
  * the values they started with.
@@ -414,6 +424,7 @@ typedef struct {
     uint32_t relax_staged;
     uint32_t append_items;
     uint32_t bucket_width;
+    uint32_t vertex_order;
 } evq_tuning;
 
 evq_status evq_tuning_get(evq_tuning* t);

@@ -102,7 +102,7 @@ class Tuning(ctypes.Structure):
                 ("append_rebuild", ctypes.c_uint32), ("trace_loops", ctypes.c_uint32),
                 ("delta", ctypes.c_uint32 * 5), ("heavy", ctypes.c_uint32 * 5), ("append_edges", ctypes.c_uint32),
                 ("relax_staged", ctypes.c_uint32), ("append_items", ctypes.c_uint32),
-                ("bucket_width", ctypes.c_uint32)]
+                ("bucket_width", ctypes.c_uint32), ("vertex_order", ctypes.c_uint32)]
 
 
 class KernelTime(ctypes.Structure):

@@ -1,8 +1,11 @@
 // C ABI of the library: argument validation, error capture and dispatch.
 // Nothing throws across this boundary; every failure becomes an evq_status
 // with a thread-local message.
+#include <algorithm>
 #include <memory>
 #include <mutex>
+#include <thread>
+#include <vector>
 
 #include "batch.h"
 #include "ceiling.h"
@@ -116,6 +119,64 @@ evq_status evq_graph_info_get(const evq_graph* h, evq_graph_info* info) {
     return EVQ_OK;
 }
 
+namespace {
+
+// Export of a graph that numbers its vertices itself: its arrays come to the
+// host and are rewritten in the caller's numbering, row by row, each row's
+// all-present edges and then its partial ones ordered by (destination,
+// weight), as a graph built in the caller's numbering holds them.  Rows are
+// rewritten by up to 16 host threads.
+void export_caller_order(const evq::Graph& g, uint32_t* row_ptr, uint32_t* row_split, uint32_t* col, uint32_t* w,
+                         uint64_t* mask, hipStream_t s) {
+    const uint32_t V = g.V, MW = g.MW;
+    const uint64_t E = g.E;
+    std::vector<uint32_t> rp((uint64_t)V + 1), rs(V), iperm(V), c(E), ww(E);
+    std::vector<uint64_t> m(E * MW);
+    EVQ_HIP(hipMemcpyAsync(rp.data(), g.row_ptr, ((uint64_t)V + 1) * 4, hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipMemcpyAsync(rs.data(), g.row_split, (uint64_t)V * 4, hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipMemcpyAsync(iperm.data(), g.iperm, (uint64_t)V * 4, hipMemcpyDeviceToHost, s));
+    if (E) {
+        EVQ_HIP(hipMemcpyAsync(c.data(), g.col, E * 4, hipMemcpyDeviceToHost, s));
+        EVQ_HIP(hipMemcpyAsync(ww.data(), g.wgt, E * 4, hipMemcpyDeviceToHost, s));
+        EVQ_HIP(hipMemcpyAsync(m.data(), g.mask, E * 8 * MW, hipMemcpyDeviceToHost, s));
+    }
+    EVQ_HIP(hipStreamSynchronize(s));
+    const std::vector<uint32_t>& perm = *g.perm_h;
+    std::vector<uint32_t> nrp((uint64_t)V + 1);
+    nrp[0] = 0;
+    for (uint32_t v = 0; v < V; ++v) nrp[v + 1] = nrp[v] + (rp[perm[v] + 1] - rp[perm[v]]);
+    if (row_ptr) std::memcpy(row_ptr, nrp.data(), ((uint64_t)V + 1) * 4);
+    auto rows = [&](uint32_t v0, uint32_t v1) {
+        std::vector<uint32_t> idx;
+        for (uint32_t v = v0; v < v1; ++v) {
+            const uint32_t i = perm[v], b = rp[i], e = rp[i + 1], sp = rs[i];
+            if (row_split) row_split[v] = nrp[v] + (sp - b);
+            idx.resize(e - b);
+            for (uint32_t j = b; j < e; ++j) idx[j - b] = j;
+            auto by_dst_w = [&](uint32_t x, uint32_t y) {
+                const uint32_t dx = iperm[c[x]], dy = iperm[c[y]];
+                return dx != dy ? dx < dy : ww[x] < ww[y];
+            };
+            std::sort(idx.begin(), idx.begin() + (sp - b), by_dst_w);
+            std::sort(idx.begin() + (sp - b), idx.end(), by_dst_w);
+            for (uint32_t k = 0; k < e - b; ++k) {
+                const uint64_t o = (uint64_t)nrp[v] + k, j = idx[k];
+                if (col) col[o] = iperm[c[j]];
+                if (w) w[o] = ww[j];
+                if (mask)
+                    for (uint32_t q = 0; q < MW; ++q) mask[o * MW + q] = m[j * MW + q];
+            }
+        }
+    };
+    const uint32_t nt = std::max(1u, std::min(16u, std::min(std::thread::hardware_concurrency(), V / 4096 + 1)));
+    std::vector<std::thread> th;
+    for (uint32_t t = 0; t < nt; ++t)
+        th.emplace_back(rows, (uint32_t)((uint64_t)V * t / nt), (uint32_t)((uint64_t)V * (t + 1) / nt));
+    for (std::thread& t : th) t.join();
+}
+
+}  // namespace
+
 evq_status evq_graph_export(const evq_graph* h, uint32_t* row_ptr, uint32_t* row_split, uint32_t* col, uint32_t* w,
                             uint64_t* mask, void* stream) {
     g_last_error.clear();
@@ -125,6 +186,10 @@ evq_status evq_graph_export(const evq_graph* h, uint32_t* row_ptr, uint32_t* row
         const evq::Graph& g = *gp;
         hipStream_t s = (hipStream_t)stream;
         evq::UseGuard ug{g, s};
+        if (g.perm_h) {
+            export_caller_order(g, row_ptr, row_split, col, w, mask, s);
+            return EVQ_OK;
+        }
         if (row_ptr) EVQ_HIP(hipMemcpyAsync(row_ptr, g.row_ptr, ((uint64_t)g.V + 1) * 4, hipMemcpyDeviceToHost, s));
         if (row_split) EVQ_HIP(hipMemcpyAsync(row_split, g.row_split, (uint64_t)g.V * 4, hipMemcpyDeviceToHost, s));
         if (g.E) {
@@ -168,7 +233,8 @@ evq_status evq_query(const evq_graph* h, uint32_t algo, uint32_t source, uint32_
         evq::QueryOut qo;
         qo.want_stats = stats != nullptr;
         evq::UseGuard ug{*gp, (hipStream_t)stream};
-        evq::run_query(*gp, algo, source, W, d_values, nullptr, nullptr, false, qo, (hipStream_t)stream);
+        evq::run_query(*gp, algo, evq::internal_id(*gp, source), W, d_values, nullptr, nullptr, false, qo,
+                       (hipStream_t)stream);
         if (stats) *stats = qo.st;
         return EVQ_OK;
     } catch (...) {
@@ -206,7 +272,7 @@ evq_status evq_query_noalloc(const evq_graph* h, uint32_t algo, uint32_t source,
         evq::Workspace::arena(s, na);
         evq::QueryOut qo;
         try {
-            evq::run_query(*gp, algo, source, W, d_values, nullptr, nullptr, false, qo, s);
+            evq::run_query(*gp, algo, evq::internal_id(*gp, source), W, d_values, nullptr, nullptr, false, qo, s);
         } catch (...) {
             (void)hipStreamSynchronize(s);  // nothing queued may still use the scratch or this version
             throw;
@@ -229,7 +295,8 @@ evq_status evq_query_bounds(const evq_graph* h, uint32_t algo, uint32_t source, 
     try {
         evq::QueryOut qo;
         evq::UseGuard ug{*gp, (hipStream_t)stream};
-        evq::run_query(*gp, algo, source, W, nullptr, d_rcap, d_rcup, true, qo, (hipStream_t)stream);
+        evq::run_query(*gp, algo, evq::internal_id(*gp, source), W, nullptr, d_rcap, d_rcup, true, qo,
+                       (hipStream_t)stream);
         return EVQ_OK;
     } catch (...) {
         return guard_exc();
@@ -249,7 +316,7 @@ evq_status evq_query_plain(const evq_graph* h, uint32_t algo, uint32_t source, u
         evq::QueryOut qo;
         qo.want_stats = stats != nullptr;
         evq::UseGuard ug{*gp, (hipStream_t)stream};
-        evq::run_plain(*gp, algo, source, W, d_values, qo, (hipStream_t)stream);
+        evq::run_plain(*gp, algo, evq::internal_id(*gp, source), W, d_values, qo, (hipStream_t)stream);
         if (stats) *stats = qo.st;
         return EVQ_OK;
     } catch (...) {
@@ -270,7 +337,7 @@ evq_status evq_query_sequential(const evq_graph* h, uint32_t algo, uint32_t sour
         evq::QueryOut qo;
         qo.want_stats = stats != nullptr;
         evq::UseGuard ug{*gp, (hipStream_t)stream};
-        evq::run_sequential(*gp, algo, source, W, d_values, qo, (hipStream_t)stream);
+        evq::run_sequential(*gp, algo, evq::internal_id(*gp, source), W, d_values, qo, (hipStream_t)stream);
         if (stats) *stats = qo.st;
         return EVQ_OK;
     } catch (...) {
@@ -295,7 +362,7 @@ evq_status evq_query_batch(const evq_graph* h, const evq_query_desc* q, uint32_t
                 return rc;
             }
             bq[i].algo = q[i].algo;
-            bq[i].source = q[i].source;
+            bq[i].source = evq::internal_id(*gp, q[i].source);
         }
         std::vector<evq::Compact> c(n);
         evq::UseGuard ug{*gp, (hipStream_t)stream};  // the stream waits for every worker stream
@@ -445,7 +512,7 @@ evq_status evq_batch_autotune(const evq_graph* h, const evq_query_desc* q, uint3
                 return rc;
             }
             bq[i].algo = q[i].algo;
-            bq[i].source = q[i].source;
+            bq[i].source = evq::internal_id(*gp, q[i].source);
         }
         evq::UseGuard ug{*gp, (hipStream_t)stream};
         const evq::BatchTuning t = evq::autotune_batch(*gp, bq.data(), n, (hipStream_t)stream, best_ms);

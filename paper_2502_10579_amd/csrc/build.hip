@@ -1005,12 +1005,77 @@ void reverse_sorted(const Graph& g, int vb, int wb, hipStream_t s, Arena& ar) {
                g.rv_cnt);
 }
 
+// Vertex numbering by descending degree: every event adds one to the degree
+// of both its endpoints (base edges, deletions and additions alike: a rough
+// count of how often each vertex's value will be read).
+__global__ void k_degree(const uint32_t* __restrict__ ev, uint64_t n, uint32_t* __restrict__ deg) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        atomicAdd(&deg[ev[3 * i]], 1u);
+        atomicAdd(&deg[ev[3 * i + 1]], 1u);
+    }
+}
+
+// Sort key of vertex v: the complement of its degree (clamped to db bits)
+// above its id, so that ascending keys rank the highest degree first and
+// break ties by id.
+__global__ void k_order_keys(const uint32_t* __restrict__ deg, uint32_t V, int vb, int db,
+                             uint64_t* __restrict__ keys) {
+    const uint64_t dmax = (db >= 64 ? ~0ull : (1ull << db) - 1);
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t d = deg[v] < dmax ? deg[v] : dmax;
+        keys[v] = ((dmax - d) << vb) | v;
+    }
+}
+
+// Rank r of the sorted keys is internal id r: iperm[r] = caller id, perm the inverse.
+__global__ void k_order_maps(const uint64_t* __restrict__ sorted, uint32_t V, int vb, uint32_t* __restrict__ perm,
+                             uint32_t* __restrict__ iperm) {
+    const uint64_t vmask = (1ull << vb) - 1;
+    for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < V; r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)(sorted[r] & vmask);
+        iperm[r] = v;
+        perm[v] = (uint32_t)r;
+    }
+}
+
+// Events (src, dst, w) in the caller's ids -> internal ids, in place.
+__global__ void k_relabel_events(uint32_t* __restrict__ ev, uint64_t n, const uint32_t* __restrict__ perm) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        ev[3 * i] = perm[ev[3 * i]];
+        ev[3 * i + 1] = perm[ev[3 * i + 1]];
+    }
+}
+
+// Numbers the vertices of a new graph by descending degree over its N events
+// (d_ev, device, relabelled in place): g->perm, g->iperm (graph arrays) and
+// g->perm_h.  Synchronises s.
+void order_vertices(Graph* g, uint32_t* d_ev, uint64_t N, hipStream_t s, Arena& ar) {
+    const uint32_t V = g->V;
+    uint32_t* deg = ar.alloc<uint32_t>(V);
+    uint64_t* keys = ar.alloc<uint64_t>(V);
+    uint64_t* tmp = ar.alloc<uint64_t>(V);
+    g->perm = (uint32_t*)graph_alloc(*g, (uint64_t)V * 4, s);
+    g->iperm = (uint32_t*)graph_alloc(*g, (uint64_t)V * 4, s);
+    fill_u32(deg, V, 0u, s);
+    EVQ_LAUNCH("order_degree", k_degree, grid_for(N, 256, 65536), 256, s, d_ev, N, deg);
+    const int vb = bits_for(V - 1), db = std::min(32, bits_for(2 * N));
+    EVQ_LAUNCH("order_keys", k_order_keys, grid_for(V, 256, 65536), 256, s, deg, V, vb, db, keys);
+    uint64_t* sorted = radix_sort<uint64_t>(keys, tmp, V, vb + db, s, ar);
+    EVQ_LAUNCH("order_maps", k_order_maps, grid_for(V, 256, 65536), 256, s, sorted, V, vb, g->perm, g->iperm);
+    EVQ_LAUNCH("order_relabel", k_relabel_events, grid_for(N, 256, 65536), 256, s, d_ev, N, g->perm);
+    auto h = std::make_shared<std::vector<uint32_t>>(V);
+    EVQ_HIP(hipMemcpyAsync(h->data(), g->perm, (uint64_t)V * 4, hipMemcpyDeviceToHost, s));
+    EVQ_HIP(hipStreamSynchronize(s));
+    g->perm_h = std::move(h);
+}
+
 }  // namespace
 
 void free_graph(Graph* g, hipStream_t s) {
     if (!g) return;
     std::vector<void*> arrays = {g->row_ptr, g->row_split, g->col,  g->wgt,   g->mask,   g->p_src, g->p_dst,
-                                 g->p_w,     g->p_mask,    g->rv_src, g->rv_w, g->rv_dst, g->rv_cnt};
+                                 g->p_w,     g->p_mask,    g->rv_src, g->rv_w, g->rv_dst, g->rv_cnt,
+                                 g->perm,    g->iperm};
     for (uint32_t i = 0; i < g->n_wo; ++i) {
         arrays.push_back(g->wo[i].col);
         arrays.push_back(g->wo[i].w);
@@ -1102,6 +1167,7 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
         uint64_t* d_seg = ar.alloc<uint64_t>(nseg);
         EVQ_HIP(hipMemcpyAsync(d_seg, seg.data(), nseg * sizeof(uint64_t), hipMemcpyHostToDevice, s));
 
+        if (N > 0 && V >= 2 && tuning().vertex_order) order_vertices(g, d_ev, N, s, ar);
         KeyLayout L;
         L.vb = bits_for(V - 1);
         L.wb = bits_for(maxw);
@@ -1130,6 +1196,7 @@ Graph* build_graph(uint32_t V, const evq_edge* base, uint64_t n_base, const evq_
             else build_impl<u128, 2>(g, d_ev, N, d_seg, nseg - 1, L, s, ar);
         }
         if (g->E >= 0xFFFFFFFEull) fail(EVQ_ERANGE, "more than 2^32 - 2 union edges");
+        if (g->perm) g->bytes += (uint64_t)V * 8;
     } catch (...) {
         (void)hipStreamSynchronize(s);
         free_graph(g, s);
@@ -1177,6 +1244,16 @@ Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
         if (b.n_del) EVQ_HIP(hipMemcpyAsync(d_ev, b.del, b.n_del * sizeof(evq_edge), hipMemcpyHostToDevice, s));
         if (b.n_add)
             EVQ_HIP(hipMemcpyAsync(d_ev + 3 * b.n_del, b.add, b.n_add * sizeof(evq_edge), hipMemcpyHostToDevice, s));
+        if (old.perm) {  // the new version keeps the old one's numbering
+            g->perm = (uint32_t*)graph_alloc(*g, (uint64_t)V * 4, s);
+            g->iperm = (uint32_t*)graph_alloc(*g, (uint64_t)V * 4, s);
+            g->perm_h = old.perm_h;
+            EVQ_HIP(hipMemcpyAsync(g->perm, old.perm, (uint64_t)V * 4, hipMemcpyDeviceToDevice, s));
+            EVQ_HIP(hipMemcpyAsync(g->iperm, old.iperm, (uint64_t)V * 4, hipMemcpyDeviceToDevice, s));
+            if (n_ev)
+                EVQ_LAUNCH("order_relabel", k_relabel_events, grid_for(n_ev, 256, 65536), 256, s, d_ev, n_ev,
+                           g->perm);
+        }
         KeyLayout L;
         const int ib = bits_for(std::max<uint64_t>(old.E, n_ev));
         L.vb = bits_for(V - 1);
@@ -1216,6 +1293,7 @@ Graph* append_graph(const Graph& old, const evq_batch& b, hipStream_t s) {
             fail(EVQ_ERANGE, "append key does not fit 128 bits");
         }
         if (g->E >= 0xFFFFFFFEull) fail(EVQ_ERANGE, "more than 2^32 - 2 union edges");
+        if (g->perm) g->bytes += (uint64_t)V * 8;
     } catch (...) {
         (void)hipStreamSynchronize(s);
         free_graph(g, s);

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -64,6 +65,12 @@ struct Graph {
     uint32_t* p_dst = nullptr;      // n_partial: destination
     uint32_t* p_w = nullptr;        // n_partial: weight
     uint64_t* p_mask = nullptr;     // n_partial * MW: presence mask
+    // Vertex numbering: every array above is indexed by internal ids, the
+    // vertices ranked by descending degree when the graph was first built
+    // (the values of the hubs then share cache lines); null: the caller's ids.
+    uint32_t* perm = nullptr;   // V: caller id -> internal id
+    uint32_t* iperm = nullptr;  // V: internal id -> caller id
+    std::shared_ptr<const std::vector<uint32_t>> perm_h;  // host copy of perm, shared by later versions
     int device = 0;
     uint64_t bytes = 0;
     double build_ms = 0.0;
@@ -94,6 +101,9 @@ struct Graph {
     mutable WeightOrder wo[kWeightOrders];
     mutable uint32_t n_wo = 0;
 };
+
+// Internal id of the caller's vertex v.
+inline uint32_t internal_id(const Graph& g, uint32_t v) { return g.perm_h ? (*g.perm_h)[v] : v; }
 
 // Records that work reading g was queued on s (call after the last launch).
 void note_use(const Graph& g, hipStream_t s);
@@ -163,7 +173,7 @@ class Workspace {
   public:
     enum Slot {
         kFlags, kFo, kFd, kFs, kFv, kFo1, kFd1, kFs1, kFv1, kStamp, kControl, kRcap, kRcup, kCidOf, kUlist, kCuo,
-        kRv, kRc, kRuo, kKc, kRecs, kTasks, kX, kBatchCap, kBatchCup, kBatchTable, kUbits, kSlots
+        kRv, kRc, kRuo, kKc, kRecs, kTasks, kX, kBatchCap, kBatchCup, kBatchTable, kUbits, kOrder, kSlots
     };
     static Workspace& get(hipStream_t s);
     static Workspace& arena(hipStream_t s, NoAlloc& na);

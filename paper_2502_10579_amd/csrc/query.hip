@@ -736,6 +736,7 @@ __device__ __forceinline__ void stream_store(uint4 v, uint4* p) {
 // instruction, with eight instructions' values gathered before any is
 // stored, so that the per-row loads do not serialise the stores.
 __global__ void __launch_bounds__(kBlock) k_writeback4(uint32_t V, uint32_t L, uint32_t S, uint32_t OS,
+                                                       const uint32_t* __restrict__ perm,
                                                        const uint32_t* __restrict__ cid_of,
                                                        const uint32_t* __restrict__ rcap,
                                                        const uint32_t* __restrict__ X, uint32_t* __restrict__ out) {
@@ -752,8 +753,9 @@ __global__ void __launch_bounds__(kBlock) k_writeback4(uint32_t V, uint32_t L, u
         const uint64_t v0 = w * 64;
         uint32_t c = kNone, b = 0;
         if (v0 + lane < V) {
-            if (cid_of) c = cid_of[v0 + lane];
-            if (c == kNone) b = rcap[v0 + lane];
+            const uint32_t u = perm ? perm[v0 + lane] : (uint32_t)(v0 + lane);
+            if (cid_of) c = cid_of[u];
+            if (c == kNone) b = rcap[u];
         }
         for (uint32_t s0 = 0; s0 < steps; s0 += 8) {
             uint4 val[8];
@@ -781,6 +783,7 @@ __global__ void __launch_bounds__(kBlock) k_writeback4(uint32_t V, uint32_t L, u
 // LDS; magic = floor(2^32 / L) + 1 turns the row lookup into a multiply-high,
 // exact for offsets below 64 L.
 __global__ void __launch_bounds__(kBlock) k_writeback_flat(uint32_t V, uint32_t L, uint32_t S, uint32_t magic,
+                                                           const uint32_t* __restrict__ perm,
                                                            const uint32_t* __restrict__ cid_of,
                                                            const uint32_t* __restrict__ rcap,
                                                            const uint32_t* __restrict__ X,
@@ -793,8 +796,9 @@ __global__ void __launch_bounds__(kBlock) k_writeback_flat(uint32_t V, uint32_t 
         const uint32_t rows = V - v0 < 64 ? (uint32_t)(V - v0) : 64u;
         uint32_t c = kNone, b = 0;
         if (lane < rows) {
-            if (cid_of) c = cid_of[v0 + lane];
-            if (c == kNone) b = rcap[v0 + lane];
+            const uint32_t u = perm ? perm[v0 + lane] : (uint32_t)(v0 + lane);
+            if (cid_of) c = cid_of[u];
+            if (c == kNone) b = rcap[u];
         }
         sc[wave][lane] = c;
         sb[wave][lane] = b;
@@ -826,8 +830,51 @@ __global__ void __launch_bounds__(kBlock) k_writeback_flat(uint32_t V, uint32_t 
     }
 }
 
+// values[v * L + i] (L % 4 == 0, 16-byte aligned rows back to back) of a
+// graph that numbers its vertices itself: a wave takes 64 consecutive
+// internal ids, reads their caller ids, compact ids and R_cap values with
+// coalesced loads, and writes each row at its caller id with lane-contiguous
+// 16-byte streaming stores (a row's values are one contiguous span, so the
+// scattered rows still fill whole lines).
+__global__ void __launch_bounds__(kBlock) k_writeback_scatter(uint32_t V, uint32_t L, uint32_t S,
+                                                              const uint32_t* __restrict__ iperm,
+                                                              const uint32_t* __restrict__ cid_of,
+                                                              const uint32_t* __restrict__ rcap,
+                                                              const uint32_t* __restrict__ X,
+                                                              uint32_t* __restrict__ out) {
+    __shared__ uint32_t sc[kBlock / 64][64], sb[kBlock / 64][64], so[kBlock / 64][64];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t Lq = L >> 2, Sq = S >> 2;
+    const uint64_t nw = (uint64_t)gridDim.x * (kBlock / 64);
+    uint4* __restrict__ o4 = reinterpret_cast<uint4*>(out);
+    const uint4* __restrict__ x4 = reinterpret_cast<const uint4*>(X);
+    for (uint64_t w = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w * 64 < V; w += nw) {
+        const uint64_t v0 = w * 64;
+        const uint32_t rows = V - v0 < 64 ? (uint32_t)(V - v0) : 64u;
+        uint32_t c = kNone, b = 0, o = 0;
+        if (lane < rows) {
+            o = iperm[v0 + lane];
+            if (cid_of) c = cid_of[v0 + lane];
+            if (c == kNone) b = rcap[v0 + lane];
+        }
+        sc[wave][lane] = c;
+        sb[wave][lane] = b;
+        so[wave][lane] = o;
+        wave_lds_sync();
+        const uint32_t n4 = rows * Lq;
+        for (uint32_t q = lane; q < n4; q += 64) {
+            const uint32_t row = q / Lq, j = q - row * Lq;
+            const uint32_t cr = sc[wave][row], br = sb[wave][row];
+            const uint4 val = cr == kNone ? make_uint4(br, br, br, br) : x4[(uint64_t)cr * Sq + j];
+            stream_store(val, &o4[(uint64_t)so[wave][row] * Lq + j]);
+        }
+        wave_lds_sync();
+    }
+}
+
 // values[v * L + i], one value per lane (any L).
 __global__ void __launch_bounds__(kBlock) k_writeback1(uint32_t V, uint32_t L, uint32_t S, uint32_t OS,
+                                                       const uint32_t* __restrict__ perm,
                                                        const uint32_t* __restrict__ cid_of,
                                                        const uint32_t* __restrict__ rcap,
                                                        const uint32_t* __restrict__ X, uint32_t* __restrict__ out) {
@@ -835,8 +882,9 @@ __global__ void __launch_bounds__(kBlock) k_writeback1(uint32_t V, uint32_t L, u
     for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t v = k / L;
         const uint32_t i = (uint32_t)(k - v * L);
-        const uint32_t c = cid_of ? cid_of[v] : kNone;
-        __builtin_nontemporal_store(c == kNone ? rcap[v] : X[(uint64_t)c * S + i], &out[v * OS + i]);
+        const uint32_t u = perm ? perm[v] : (uint32_t)v;
+        const uint32_t c = cid_of ? cid_of[u] : kNone;
+        __builtin_nontemporal_store(c == kNone ? rcap[u] : X[(uint64_t)c * S + i], &out[v * OS + i]);
     }
 }
 
@@ -878,12 +926,28 @@ __global__ void k_scatter_rows1(const uint32_t* __restrict__ ulist, uint32_t nU,
 }
 
 // Column of one snapshot: col[v] = R_cap[v] for stable v, else its relaxed value.
-__global__ void k_column(uint32_t V, const uint32_t* __restrict__ cid_of, const uint32_t* __restrict__ rcap,
-                         const uint32_t* __restrict__ X, uint32_t* __restrict__ col) {
+__global__ void k_column(uint32_t V, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ cid_of,
+                         const uint32_t* __restrict__ rcap, const uint32_t* __restrict__ X,
+                         uint32_t* __restrict__ col) {
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t c = cid_of ? cid_of[v] : kNone;
-        col[v] = c == kNone ? rcap[v] : X[c];
+        const uint32_t u = perm ? perm[v] : (uint32_t)v;
+        const uint32_t c = cid_of ? cid_of[u] : kNone;
+        col[v] = c == kNone ? rcap[u] : X[c];
     }
+}
+
+// out[v] = in[perm[v]]: an array over internal ids in the caller's order.
+__global__ void k_to_caller_order(const uint32_t* __restrict__ in, const uint32_t* __restrict__ perm, uint32_t V,
+                                  uint32_t* __restrict__ out) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x)
+        out[v] = in[perm[v]];
+}
+
+// out[i] = iperm[in[i]]: internal vertex ids as the caller's.
+__global__ void k_to_caller_ids(const uint32_t* __restrict__ in, const uint32_t* __restrict__ iperm, uint32_t n,
+                                uint32_t* __restrict__ out) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = iperm[in[i]];
 }
 
 // T[i][v] (L columns of V values) -> out[v * L + i], through a 64 x 64 LDS tile.
@@ -1136,23 +1200,30 @@ void relax_algo(uint32_t algo, uint32_t LG, bool st, const Graph& g, const Windo
 }
 
 // values[v * OS + i], i < L (OS: the output's row stride, >= L).
-void writeback(uint32_t LG, uint32_t V, uint32_t L, const uint32_t* cid_of, const uint32_t* rcap, const uint32_t* X,
-               uint32_t* out, hipStream_t s, uint32_t OS = 0) {
+// Row v of out (the caller's id) is internal vertex perm[v] (perm null: v;
+// iperm, the inverse, given with it).
+void writeback(uint32_t LG, uint32_t V, uint32_t L, const uint32_t* perm, const uint32_t* iperm, const uint32_t* cid_of,
+               const uint32_t* rcap, const uint32_t* X, uint32_t* out, hipStream_t s, uint32_t OS = 0) {
     if (OS == 0) OS = L;
+    if (perm && OS == L && L % 4 == 0 && L <= 256 && (uintptr_t)out % 16 == 0 && (X == nullptr || LG % 4 == 0)) {
+        EVQ_LAUNCH("writeback", k_writeback_scatter, grid_for(V, kBlock, 65535), kBlock, s, V, L, LG, iperm, cid_of,
+                   rcap, X, out);
+        return;
+    }
     if (OS == L && L >= 4 && L <= 256 && (uintptr_t)out % 16 == 0) {
         const uint32_t magic = (uint32_t)((1ull << 32) / L + 1);
-        EVQ_LAUNCH("writeback", k_writeback_flat, grid_for(V, kBlock, 65535), kBlock, s, V, L, LG, magic, cid_of,
-                   rcap, X, out);
+        EVQ_LAUNCH("writeback", k_writeback_flat, grid_for(V, kBlock, 65535), kBlock, s, V, L, LG, magic, perm,
+                   cid_of, rcap, X, out);
         return;
     }
     const bool vec = (L % 4 == 0) && (L <= 256) && (OS % 4 == 0) && ((uintptr_t)out % 16 == 0) &&
                      (X == nullptr || LG % 4 == 0);
     if (vec) {
-        EVQ_LAUNCH("writeback", k_writeback4, grid_for(V, kBlock, 65535), kBlock, s, V, L, LG, OS, cid_of, rcap, X,
-                   out);
+        EVQ_LAUNCH("writeback", k_writeback4, grid_for(V, kBlock, 65535), kBlock, s, V, L, LG, OS, perm, cid_of,
+                   rcap, X, out);
     } else {
         EVQ_LAUNCH("writeback", k_writeback1, grid_for((uint64_t)V * L, kBlock * 4, 65535), kBlock, s, V, L, LG, OS,
-                   cid_of, rcap, X, out);
+                   perm, cid_of, rcap, X, out);
     }
 }
 
@@ -1220,8 +1291,12 @@ bool tail_impl(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
             char* p = static_cast<char*>(stream_alloc(ub + (uint64_t)red.nU * LG * 4, s));
             c->ulist = reinterpret_cast<uint32_t*>(p);
             c->X = reinterpret_cast<uint32_t*>(p + ub);
-            EVQ_LAUNCH("result_copy", k_copy4, grid_for((red.nU + 3) / 4, 256 * 4, 8192), 256, s, red.ulist,
-                       c->ulist, red.nU);
+            if (g.iperm)
+                EVQ_LAUNCH("result_ids", k_to_caller_ids, grid_for(red.nU, 256 * 4, 8192), 256, s, red.ulist,
+                           g.iperm, red.nU, c->ulist);
+            else
+                EVQ_LAUNCH("result_copy", k_copy4, grid_for((red.nU + 3) / 4, 256 * 4, 8192), 256, s, red.ulist,
+                           c->ulist, red.nU);
             X = c->X;
         }
     } else if (red.nU) {
@@ -1229,7 +1304,13 @@ bool tail_impl(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     }
     if (red.nU) relax_algo(algo, LG, st, g, W, W, rcap, red, X, false, source, f, ws, s, qo);
     tm.mark();
-    if (d_values) writeback(LG, g.V, W.L, red.cid_of, rcap, X, d_values, s, OS);
+    if (d_values) writeback(LG, g.V, W.L, g.perm, g.iperm, red.cid_of, rcap, X, d_values, s, OS);
+    if (c && g.perm) {  // the compact result's bound in the caller's order (its ids are mapped above)
+        uint32_t* t = ws.buf<uint32_t>(Workspace::kOrder, g.V);
+        EVQ_LAUNCH("result_order", k_copy4, grid_for((g.V + 3) / 4, 256 * 4, 8192), 256, s, c->rcap, t, g.V);
+        EVQ_LAUNCH("result_order", k_to_caller_order, grid_for(g.V, 256 * 4, 8192), 256, s, t, g.perm, g.V,
+                   c->rcap);
+    }
     tm.mark();
     qo.st.n_unstable += red.nU;
     qo.st.subwindows += 1;
@@ -1308,10 +1389,17 @@ void run_query(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     f.delta = choose_delta(algo);
     f.heavy = choose_heavy(algo);
     f.bdelta = choose_bucket_width(algo, g);
-    uint32_t* rcap = d_rcap_out ? d_rcap_out : ws.buf<uint32_t>(Workspace::kRcap, g.V);
-    uint32_t* rcup = d_rcup_out ? d_rcup_out : ws.buf<uint32_t>(Workspace::kRcup, g.V);
+    // the bounds go straight to the caller's arrays unless the graph numbers its vertices itself
+    uint32_t* rcap = d_rcap_out && !g.perm ? d_rcap_out : ws.buf<uint32_t>(Workspace::kRcap, g.V);
+    uint32_t* rcup = d_rcup_out && !g.perm ? d_rcup_out : ws.buf<uint32_t>(Workspace::kRcup, g.V);
     bounds_impl(g, algo, source, W, rcap, rcup, f, qo, s, tm);
     if (bounds_only) {
+        if (g.perm && d_rcap_out)
+            EVQ_LAUNCH("bounds_order", k_to_caller_order, grid_for(g.V, 256 * 4, 8192), 256, s, rcap, g.perm, g.V,
+                       d_rcap_out);
+        if (g.perm && d_rcup_out)
+            EVQ_LAUNCH("bounds_order", k_to_caller_order, grid_for(g.V, 256 * 4, 8192), 256, s, rcup, g.perm, g.V,
+                       d_rcup_out);
         EVQ_HIP(hipStreamSynchronize(s));
         ws.in_use = false;
         return;
@@ -1378,7 +1466,7 @@ void run_tail_compact(const Graph& g, uint32_t algo, uint32_t source, const Wind
 
 void expand_compact(uint32_t V, uint32_t L, const uint32_t* rcap, const uint32_t* ulist, const uint32_t* X,
                     uint32_t nU, uint32_t LG, uint32_t* d_values, hipStream_t s) {
-    writeback(LG, V, L, nullptr, rcap, nullptr, d_values, s);
+    writeback(LG, V, L, nullptr, nullptr, nullptr, rcap, nullptr, d_values, s);
     if (!nU) return;
     if (L % 4 == 0 && (uintptr_t)d_values % 16 == 0) {
         EVQ_LAUNCH("expand_rows", k_scatter_rows4, grid_for((uint64_t)nU * (L / 4), 256 * 4, 65535), 256, s, ulist,
@@ -1432,7 +1520,7 @@ void run_sequential(const Graph& g, uint32_t algo, uint32_t source, const Window
                 EVQ_LAUNCH("query_init", k_init_frontier_stats, 1, 64, s, f.stats);
             }
         }
-        EVQ_LAUNCH("writeback", k_column, grid_for(g.V, 256 * 4, 65535), 256, s, g.V,
+        EVQ_LAUNCH("writeback", k_column, grid_for(g.V, 256 * 4, 65535), 256, s, g.V, g.perm,
                    red.nU ? red.cid_of : nullptr, rcap, X, T + (uint64_t)i * g.V);
     }
     tm.mark();
@@ -1472,7 +1560,7 @@ void run_plain(const Graph& g, uint32_t algo, uint32_t source, const Window& W, 
     uint32_t* X = ws.buf<uint32_t>(Workspace::kX, (uint64_t)g.V * LG);
     relax_algo(algo, LG, st, g, W, W, nullptr, red, X, true, source, f, ws, s, qo);
     tm.mark();
-    writeback(LG, g.V, W.L, red.cid_of, nullptr, X, d_values, s);
+    writeback(LG, g.V, W.L, g.perm, g.iperm, red.cid_of, nullptr, X, d_values, s);
     tm.mark();
     ws.in_use = false;
     if (st) {

@@ -333,6 +333,7 @@ evq_tuning tuning_from_env() {
     t.append_items = env_u32("EVQ_APPEND_ITEMS", 0u);
     t.relax_staged = env_u32("EVQ_RELAX_STAGED", 2u);
     t.bucket_width = env_u32("EVQ_BUCKET_WIDTH", 0u);
+    t.vertex_order = env_u32("EVQ_VERTEX_ORDER", 1u) != 0;
     static const char* delta_names[5] = {"EVQ_DELTA_SSSP", "EVQ_DELTA_BFS", "EVQ_DELTA_SSWP", "EVQ_DELTA_SSNP",
                                          "EVQ_DELTA_VITERBI"};
     static const char* heavy_names[5] = {"EVQ_HEAVY_SSSP", "EVQ_HEAVY_BFS", "EVQ_HEAVY_SSWP", "EVQ_HEAVY_SSNP",

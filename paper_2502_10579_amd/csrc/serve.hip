@@ -146,7 +146,7 @@ Window window_of(const Graph& g, const SQuery* q) {
 void run_single(evq_server* sv, const Graph& g, SQuery* q, hipStream_t ws) {
     try {
         q->c.rcap = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
-        run_query_compact(g, q->algo, q->source, window_of(g, q), q->c, q->qo, ws);
+        run_query_compact(g, q->algo, internal_id(g, q->source), window_of(g, q), q->c, q->qo, ws);
         q->t_bounds = std::chrono::duration<double, std::milli>(q->qo.bounds_done - sv->t0).count();
     } catch (...) {
         fail_query(q, current_error(), ws);
@@ -189,7 +189,7 @@ void launch_group(evq_server* sv, std::shared_ptr<const Graph> gp, std::vector<S
                 grp[k]->c.rcap = rcap[k] = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
                 grp[k]->rcup = rcup[k] = static_cast<uint32_t*>(stream_alloc((uint64_t)g.V * 4, ws));
                 wins[k] = window_of(g, grp[k]);
-                srcs[k] = grp[k]->source;
+                srcs[k] = internal_id(g, grp[k]->source);
             }
             BatchTimes bt;
             batch_bounds(g, grp[0]->algo, wins.data(), srcs.data(), nq, rcap.data(), rcup.data(), tu, ws, bt);
@@ -230,7 +230,7 @@ void launch_group(evq_server* sv, std::shared_ptr<const Graph> gp, std::vector<S
                 UseGuard ug{g, ts};
                 try {
                     EVQ_HIP(hipStreamWaitEvent(ts, (hipEvent_t)evp.get(), 0));
-                    run_tail_compact(g, q->algo, q->source, window_of(g, q), q->rcup, q->c, q->qo, ts);
+                    run_tail_compact(g, q->algo, internal_id(g, q->source), window_of(g, q), q->rcup, q->c, q->qo, ts);
                 } catch (...) {
                     fail_query(q, current_error(), ts);
                 }

@@ -371,6 +371,53 @@ def test_pull_step_multi_step_slices(evq, algo, frac, tuned, indegree_case):
     assert_equal_values(got, vals_o, f"pull {frac}, algo {algo}")
 
 
+def _device_u32(ptr, n):
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    out = np.empty(max(n, 1), np.uint32)
+    if n:
+        rc = hip.hipMemcpy(ctypes.c_void_p(out.ctypes.data), ctypes.c_void_p(ptr), ctypes.c_size_t(n * 4), 2)
+        assert rc == 0, rc
+    return out[:n]
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_vertex_numbering(evq, order, tuned):
+    # a graph numbered by degree inside (1) or in the caller's ids (0):
+    # values, both bounds, compact results (the intersection bound in vertex
+    # order, the unstable vertices as caller ids: those whose two bounds
+    # differ), the export, and values after an append, all in the caller's
+    # numbering and equal to the oracle's
+    tuned(vertex_order=order)
+    full = synth.rmat_instance(12, 40000, 9, 300, 300, wmin=1, wmax=60, seed=91)
+    inst = synth.Instance(full.num_vertices, full.base, full.dels[:8], full.adds[:8])
+    V, K = inst.num_vertices, inst.K
+    srcs = synth.pick_sources(inst, 2, seed=9)
+    trip, bits = oracle.replay(inst)
+    with _graph(evq, inst) as g:
+        for algo in ALGOS:
+            for s in srcs:
+                want = oracle.window_values(inst, algo, s, 1, 6, replayed=(trip, bits))
+                assert_equal_values(gpu_values(g, algo, s, 1, 6), want, f"order {order} algo {algo} src {s}")
+                rc, ru = gpu_bounds(g, algo, s, 0, K)
+                rc_o, ru_o = oracle.bounds(V, trip, bits, algo, s, 0, K)
+                assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
+        qs = [(algo, s, 0, K) for algo in ALGOS for s in srcs]
+        for (algo, s, b, L), r in zip(qs, g.query_batch(qs)):
+            want = oracle.window_values(inst, algo, s, b, L, replayed=(trip, bits))
+            assert_equal_values(evq.to_u32(r.expand()).reshape(V, L), want, f"order {order} compact {algo}")
+            rc_o, ru_o = oracle.bounds(V, trip, bits, algo, s, b, L)
+            assert np.array_equal(_device_u32(r._c.d_rcap, V), rc_o)
+            ids = _device_u32(r._c.d_unstable, r._c.n_unstable)
+            assert np.array_equal(np.sort(ids), np.flatnonzero(rc_o != ru_o).astype(np.uint32))
+            r.free()
+        _check_export(g, inst)
+        g.append(full.dels[8], full.adds[8])
+        for algo in ALGOS:
+            want = oracle.window_values(full, algo, srcs[0], 1, K)
+            assert_equal_values(gpu_values(g, algo, srcs[0], 1, K), want, f"order {order} after append")
+
+
 @pytest.mark.parametrize("width", [0, 1, 3, 17, 100000, 0xFFFFFFFF])
 def test_bucketed_sssp(evq, width, tuned):
     # SSSP intersection solves under delta-stepping with light and heavy edges (bucket width 1:
