@@ -248,12 +248,18 @@ __global__ void k_compact(const KT* __restrict__ keys, uint64_t n, KeyLayout L, 
     }
 }
 
-// row_ptr[v] = first compacted edge with src >= v (sources are sorted).
+// row_ptr[v] = first compacted edge with src >= v (sources are sorted), by a
+// binary search per vertex, so that long runs of vertices without edges (the
+// lowest-degree ids come last) cost no more than any other.
 __global__ void k_row_ptr(const uint32_t* __restrict__ c_src, uint64_t E, uint32_t V, uint32_t* __restrict__ row_ptr) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= E; i += (uint64_t)gridDim.x * blockDim.x) {
-        int64_t prev = i == 0 ? -1 : (int64_t)c_src[i - 1];
-        int64_t cur = i == E ? (int64_t)V : (int64_t)c_src[i];
-        for (int64_t v = prev + 1; v <= cur; ++v) row_ptr[v] = (uint32_t)i;
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v <= V; v += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t lo = 0, hi = E;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (c_src[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        row_ptr[v] = (uint32_t)lo;
     }
 }
 
@@ -338,7 +344,7 @@ void finish_build(Graph* g, KT* sorted, uint64_t N, KeyLayout L, uint64_t* mtmp,
     g->mask = (uint64_t*)graph_alloc(*g, E * 8 * MW, s);
     g->bytes = ((uint64_t)g->V + 1) * 4 + (uint64_t)g->V * 4 + E * (8 + 8 * MW);
 
-    EVQ_LAUNCH("build_row_ptr", k_row_ptr, grid_for(E + 1, 256), 256, s, c_src, E, g->V, g->row_ptr);
+    EVQ_LAUNCH("build_row_ptr", k_row_ptr, grid_for((uint64_t)g->V + 1, 256), 256, s, c_src, E, g->V, g->row_ptr);
     scan_exclusive(c_full, fb, E, fb + E, s, ar);
     EVQ_HIP(hipMemcpyAsync(mb.h, fb + E, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     EVQ_HIP(hipStreamSynchronize(s));

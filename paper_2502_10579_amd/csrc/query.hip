@@ -830,12 +830,12 @@ __global__ void __launch_bounds__(kBlock) k_writeback_flat(uint32_t V, uint32_t 
     }
 }
 
-// values[v * L + i] (L % 4 == 0, 16-byte aligned rows back to back) of a
+// values[v * L + i] (L % 32 == 0, 128-byte aligned rows back to back) of a
 // graph that numbers its vertices itself: a wave takes 64 consecutive
 // internal ids, reads their caller ids, compact ids and R_cap values with
 // coalesced loads, and writes each row at its caller id with lane-contiguous
-// 16-byte streaming stores (a row's values are one contiguous span, so the
-// scattered rows still fill whole lines).
+// 16-byte streaming stores (a row is whole 128-byte lines, so the scattered
+// rows write no partial line).
 __global__ void __launch_bounds__(kBlock) k_writeback_scatter(uint32_t V, uint32_t L, uint32_t S,
                                                               const uint32_t* __restrict__ iperm,
                                                               const uint32_t* __restrict__ cid_of,
@@ -1205,7 +1205,9 @@ void relax_algo(uint32_t algo, uint32_t LG, bool st, const Graph& g, const Windo
 void writeback(uint32_t LG, uint32_t V, uint32_t L, const uint32_t* perm, const uint32_t* iperm, const uint32_t* cid_of,
                const uint32_t* rcap, const uint32_t* X, uint32_t* out, hipStream_t s, uint32_t OS = 0) {
     if (OS == 0) OS = L;
-    if (perm && OS == L && L % 4 == 0 && L <= 256 && (uintptr_t)out % 16 == 0 && (X == nullptr || LG % 4 == 0)) {
+    // rows of whole 128-byte lines are scattered to their caller ids; other
+    // lengths keep the output contiguous and gather the rows' inputs
+    if (perm && OS == L && L % 32 == 0 && L <= 256 && (uintptr_t)out % 128 == 0 && (X == nullptr || LG % 4 == 0)) {
         EVQ_LAUNCH("writeback", k_writeback_scatter, grid_for(V, kBlock, 65535), kBlock, s, V, L, LG, iperm, cid_of,
                    rcap, X, out);
         return;
