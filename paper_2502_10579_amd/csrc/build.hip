@@ -1013,12 +1013,39 @@ void reverse_sorted(const Graph& g, int vb, int wb, hipStream_t s, Arena& ar) {
 
 // Vertex numbering by descending degree: every event adds one to the degree
 // of both its endpoints (base edges, deletions and additions alike: a rough
-// count of how often each vertex's value will be read).
-__global__ void k_degree(const uint32_t* __restrict__ ev, uint64_t n, uint32_t* __restrict__ deg) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        atomicAdd(&deg[ev[3 * i]], 1u);
-        atomicAdd(&deg[ev[3 * i + 1]], 1u);
+// count of how often each vertex's value will be read).  A block first counts
+// in an LDS hash table (open addressing, four probes), so that a hub's many
+// endpoints cost one device atomic per block rather than one each (the
+// same-address device atomics serialise); an endpoint that finds no slot
+// goes to the device array directly.
+constexpr uint32_t kDegSlots = 2048;
+__global__ void __launch_bounds__(256) k_degree(const uint32_t* __restrict__ ev, uint64_t n,
+                                                uint32_t* __restrict__ deg) {
+    __shared__ uint32_t key[kDegSlots], cnt[kDegSlots];
+    for (uint32_t i = threadIdx.x; i < kDegSlots; i += blockDim.x) {
+        key[i] = 0xFFFFFFFFu;  // no vertex id (ids are below V <= 2^32 - 1)
+        cnt[i] = 0;
     }
+    __syncthreads();
+    auto add = [&](uint32_t v) {
+        const uint32_t h = (v * 2654435761u) >> 21;  // 11 bits: kDegSlots
+        for (uint32_t p = 0; p < 4; ++p) {
+            const uint32_t slot = (h + p) & (kDegSlots - 1);
+            const uint32_t old = atomicCAS(&key[slot], 0xFFFFFFFFu, v);
+            if (old == 0xFFFFFFFFu || old == v) {
+                atomicAdd(&cnt[slot], 1u);
+                return;
+            }
+        }
+        atomicAdd(&deg[v], 1u);
+    };
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        add(ev[3 * i]);
+        add(ev[3 * i + 1]);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kDegSlots; i += blockDim.x)
+        if (cnt[i]) atomicAdd(&deg[key[i]], cnt[i]);
 }
 
 // Sort key of vertex v: the complement of its degree (clamped to db bits)
@@ -1063,7 +1090,7 @@ void order_vertices(Graph* g, uint32_t* d_ev, uint64_t N, hipStream_t s, Arena& 
     g->perm = (uint32_t*)graph_alloc(*g, (uint64_t)V * 4, s);
     g->iperm = (uint32_t*)graph_alloc(*g, (uint64_t)V * 4, s);
     fill_u32(deg, V, 0u, s);
-    EVQ_LAUNCH("order_degree", k_degree, grid_for(N, 256, 65536), 256, s, d_ev, N, deg);
+    EVQ_LAUNCH("order_degree", k_degree, grid_for(N, 256 * 16, 2048), 256, s, d_ev, N, deg);
     const int vb = bits_for(V - 1), db = std::min(32, bits_for(2 * N));
     EVQ_LAUNCH("order_keys", k_order_keys, grid_for(V, 256, 65536), 256, s, deg, V, vb, db, keys);
     uint64_t* sorted = radix_sort<uint64_t>(keys, tmp, V, vb + db, s, ar);
