@@ -175,6 +175,10 @@ evq_status evq_graph_info_get(const evq_graph* g, evq_graph_info* info);
  *   row_ptr: V + 1 entries; row_split: V entries (end of the all-present
  *   prefix of each row); col, w: num_edges entries; mask: num_edges *
  *   mask_words 64-bit words, word j of edge e at mask[e * mask_words + j].
+ * Rows and columns are in the caller's vertex ids; each row holds its edges
+ * present in all snapshots first, then the others, each part ordered by
+ * (destination, weight).  (A graph that numbers its vertices itself,
+ * evq_tuning.vertex_order, rewrites its rows on the host for this.)
  * Any pointer may be NULL to skip that array.  Synchronises `stream`.
  */
 evq_status evq_graph_export(const evq_graph* g, uint32_t* row_ptr, uint32_t* row_split, uint32_t* col,
