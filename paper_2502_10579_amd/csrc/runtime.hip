@@ -201,6 +201,7 @@ void* Workspace::raw(Slot slot, uint64_t bytes) {
         cap_[slot] = want;
         na_->used += want;
         if (slot == kFlags) fresh_flags = true;
+        if (slot == kStamp) stamp_seen = nullptr;  // new memory: its stamps are unknown
         return p_[slot];
     }
     if (p_[slot]) {
@@ -212,6 +213,8 @@ void* Workspace::raw(Slot slot, uint64_t bytes) {
     p_[slot] = stream_alloc(want, s_);
     cap_[slot] = want;
     if (slot == kFlags) fresh_flags = true;
+    // a larger buffer may start at the old one's address: its stamps are unknown all the same
+    if (slot == kStamp) stamp_seen = nullptr;
     return p_[slot];
 }
 
