@@ -5,7 +5,9 @@ mid   (R-MAT scale 20, K = 64): SSSP, BFS, SSWP, SSNP and Viterbi from four
       element by element, and both bounds.  Warm-up queries run first on the
       graph, so every checked query runs with the pull step of the full-window
       intersection solve available (its reverse CSR is built by the second
-      full-window query that asks for it), as in the timed benchmark.
+      full-window query that asks for it), as in the timed benchmark.  From
+      the first source also with the pull step in every iteration and in none
+      (values and bounds).
 large (R-MAT scale 23, K = 100, weights [1, 1000], two-word masks): SSWP and
       SSNP; all 100 snapshots and both bounds compared with the oracle through
       per-snapshot digests that tests/golden/make_fullsize_digests.py wrote
@@ -63,6 +65,29 @@ def test_mid_all_snapshots(evq, mid, algo, si):
     assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
     assert_equal_values(got, want, f"mid algo {algo} source {src}")
     assert st["n_unstable"] == int((rc_o != ru_o).sum())
+
+
+_MID_WANT = {}
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("frac", [0.0, 2.0])
+@pytest.mark.parametrize("algo", [oracle.SSSP, oracle.BFS, oracle.SSWP, oracle.SSNP, oracle.VITERBI])
+def test_mid_pull_always_and_never(evq, mid, algo, frac, tuned):
+    # the full-window intersection solve pulling in every iteration (frac 0: hub destinations cut
+    # across hundreds of wave slices in each one) and in none (2: pushes only), at full size
+    inst, rep, srcs, g = mid
+    V, K, src = inst.num_vertices, inst.K, srcs[0]
+    print(f"mid pull_frac {frac}: algo {algo} source {src}", flush=True)
+    if algo not in _MID_WANT:
+        _MID_WANT[algo] = (oracle.window_values(inst, algo, src, 0, K, replayed=rep),
+                           oracle.bounds(V, rep[0], rep[1], algo, src, 0, K))
+    want, (rc_o, ru_o) = _MID_WANT[algo]
+    tuned(pull_frac=frac)
+    got = gpu_values(g, algo, src, 0, K)
+    rc, ru = gpu_bounds(g, algo, src, 0, K)
+    assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
+    assert_equal_values(got, want, f"mid pull_frac {frac} algo {algo}")
 
 
 @pytest.fixture(scope="module")
