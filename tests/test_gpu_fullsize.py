@@ -7,7 +7,7 @@ mid   (R-MAT scale 20, K = 64): SSSP, BFS, SSWP, SSNP and Viterbi from four
       intersection solve available (its reverse CSR is built by the second
       full-window query that asks for it), as in the timed benchmark.  From
       the first source also with the pull step in every iteration and in none
-      (values and bounds).
+      (values and bounds), and from the second over sub-windows.
 large (R-MAT scale 23, K = 100, weights [1, 1000], two-word masks): SSWP and
       SSNP; all 100 snapshots and both bounds compared with the oracle through
       per-snapshot digests that tests/golden/make_fullsize_digests.py wrote
@@ -88,6 +88,24 @@ def test_mid_pull_always_and_never(evq, mid, algo, frac, tuned):
     rc, ru = gpu_bounds(g, algo, src, 0, K)
     assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
     assert_equal_values(got, want, f"mid pull_frac {frac} algo {algo}")
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("win", [(3, 37), (17, 47), (63, 1)])
+@pytest.mark.parametrize("algo", [oracle.SSSP, oracle.SSWP, oracle.VITERBI])
+def test_mid_sub_windows(evq, mid, algo, win):
+    # windows that start past the first snapshot and end before the last (the intersection solve
+    # over a sub-window: masked rows, no pull step), and the last snapshot alone, at full size
+    inst, rep, srcs, g = mid
+    V, src = inst.num_vertices, srcs[1]
+    b, L = win
+    print(f"mid window [{b},{b + L}): algo {algo} source {src}", flush=True)
+    want = oracle.window_values(inst, algo, src, b, L, replayed=rep)
+    rc_o, ru_o = oracle.bounds(V, rep[0], rep[1], algo, src, b, L)
+    got = gpu_values(g, algo, src, b, L)
+    rc, ru = gpu_bounds(g, algo, src, b, L)
+    assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
+    assert_equal_values(got, want, f"mid window [{b},{b + L}) algo {algo}")
 
 
 @pytest.fixture(scope="module")
