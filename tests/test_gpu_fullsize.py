@@ -8,6 +8,8 @@ mid   (R-MAT scale 20, K = 64): SSSP, BFS, SSWP, SSNP and Viterbi from four
       full-window query that asks for it), as in the timed benchmark.  From
       the first source also with the pull step in every iteration and in none
       (values and bounds), and from the second over sub-windows.
+churn (the mid graph with 100k + 100k updates per snapshot, as timed for the
+      relaxer's roofline): SSSP and Viterbi, all 64 snapshots and both bounds.
 large (R-MAT scale 23, K = 100, weights [1, 1000], two-word masks): SSWP and
       SSNP; all 100 snapshots and both bounds compared with the oracle through
       per-snapshot digests that tests/golden/make_fullsize_digests.py wrote
@@ -148,3 +150,27 @@ def test_large_all_snapshots(evq, large, algo):
     assert (got >= lo[:, None]).all() and (got <= hi[:, None]).all()
     stable = rc == ru
     assert (got[stable] == rc[stable][:, None]).all()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("algo", [oracle.SSSP, oracle.VITERBI])
+def test_churn_all_snapshots(evq, algo):
+    # the heavy-churn workload (mid graph, 100k + 100k updates per snapshot, about half the
+    # vertices unstable) as bench.py times it: the seeded source, window [0,64), after the
+    # warm-up queries, every snapshot and both bounds against the oracle
+    inst = synth.config_instance("churn", seed=1)
+    rep = oracle.replay(inst)
+    src = synth.pick_sources(inst, 1, seed=1)[0]
+    V, K = inst.num_vertices, inst.K
+    print(f"churn: algo {algo} source {src}", flush=True)
+    want = oracle.window_values(inst, algo, src, 0, K, replayed=rep)
+    rc_o, ru_o = oracle.bounds(V, rep[0], rep[1], algo, src, 0, K)
+    with evq.Graph.from_instance(inst) as g:
+        for _ in range(2):
+            g.query(algo, src, 0, K)
+        got, st = gpu_values(g, algo, src, 0, K, stats=True)
+        rc, ru = gpu_bounds(g, algo, src, 0, K)
+    assert np.array_equal(rc, rc_o) and np.array_equal(ru, ru_o)
+    assert_equal_values(got, want, f"churn algo {algo} source {src}")
+    assert st["n_unstable"] == int((rc_o != ru_o).sum())
+    assert st["n_unstable"] > V // 4
